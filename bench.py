@@ -1,0 +1,214 @@
+"""Benchmark: single-pass maximal matching (Skipper) on one MI355X.
+
+One step = one full matching pass (state initialisation + sweep) over a graph
+resident in HBM. The default workload is R-MAT scale 27, edge factor 16,
+(a, b, c) = (0.57, 0.19, 0.19), symmetrised, deduplicated, ids permuted.
+
+value  = m / (ms_per_step) in GEdges/s, m = directed CSR entries.
+roofline: the sweep kernel's algorithmic bytes per launch
+          (offsets w(n+1) + neighbour ids 4*T_seq + source states n + mates 4n,
+          T_seq = ids SGMM reads) over its mean duration from HIP events
+          recorded on the launch stream, against 8 TB/s.
+cpu_baseline: the oracle's single-thread SGMM on the host, on the same graph.
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = "GEdges/s single-pass MM + % HBM roofline; batched vs per-graph graphs/s"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def make_workload(name: str, seed: int):
+    import graphgen
+    if name == "er65536":
+        return graphgen.er(65536, 16, seed=seed).with_int32_offsets(), {
+            "workload": "er", "n": 65536, "avg_degree": 16, "offsets": "int32", "seed": seed}
+    if name.startswith("rmat"):
+        scale = int(name[4:])
+        return graphgen.rmat(scale, 16, seed=seed), {
+            "workload": "rmat", "scale": scale, "edge_factor": 16, "abc": [0.57, 0.19, 0.19],
+            "permuted": True, "offsets": "int64", "seed": seed}
+    if name.startswith("grid"):
+        side = int(name[4:])
+        return graphgen.grid(side, side), {"workload": "grid", "rows": side, "cols": side,
+                                           "offsets": "int64"}
+    raise SystemExit("unknown workload %r" % name)
+
+
+def cpu_baseline(csr, budget_s: float = 30.0):
+    """Times the oracle's single-thread SGMM (untuned) on the host."""
+    import oracle
+    times = []
+    res = None
+    while True:
+        t0 = time.perf_counter()
+        res = oracle.sgmm(csr)
+        times.append(time.perf_counter() - t0)
+        if len(times) >= 3 or sum(times) * (len(times) + 1) / len(times) > budget_s:
+            break
+    t = float(np.median(times))
+    return res, t, len(times)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="rmat27")
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--layout", default="u8", choices=["u8", "u32"])
+    ap.add_argument("--lazy", type=int, default=1)
+    ap.add_argument("--wave-vertices", type=int, default=None)
+    ap.add_argument("--wg-size", type=int, default=None)
+    ap.add_argument("--disperse", type=int, default=None)
+    ap.add_argument("--assist-after", type=int, default=None)
+    ap.add_argument("--no-stats", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the matching pass of one graph runs on a single "
+              "MI355X (no multi-GPU path is built); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2507_04420_amd as mm
+    from paper_2507_04420_amd import _lib
+
+    t0 = time.perf_counter()
+    csr, config = make_workload(args.workload, args.seed)
+    log("generated %s: n=%d m=%d in %.1fs" % (args.workload, csr.n, csr.m, time.perf_counter() - t0))
+
+    # CPU baseline: the oracle's SGMM, single thread; also yields T_seq.
+    ref, t_sgmm, reps = cpu_baseline(csr)
+    t_seq = ref.touched
+    log("SGMM (oracle, 1 thread): %.3fs x%d, pairs=%d, T_seq=%d (%.4f m)" % (
+        t_sgmm, reps, ref.pairs, t_seq, t_seq / max(csr.m, 1)))
+
+    dev = torch.device("cuda:0")
+    off = torch.from_numpy(csr.off).to(dev)
+    nbr = torch.from_numpy(csr.nbr).to(dev)
+    torch.cuda.synchronize()
+
+    tun = mm.Tuning.default()
+    tun.layout = _lib.MM_LAYOUT_U8 if args.layout == "u8" else _lib.MM_LAYOUT_U32
+    tun.lazy_init = args.lazy if args.layout == "u8" else 0
+    if args.wave_vertices:
+        tun.wave_vertices = args.wave_vertices
+    if args.wg_size:
+        tun.wg_size = args.wg_size
+    if args.disperse is not None:
+        tun.disperse = args.disperse
+    if args.assist_after is not None:
+        tun.assist_after = args.assist_after
+
+    g = mm.Graph(off, nbr, symmetric=True, validate=True, timing=True, tuning=tun)
+    out = torch.empty(csr.n, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        g.run(out)
+    g.sync()
+    g.timing()  # drop warm-up launches
+
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        g.run(out)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    g.sync()
+    total_ms = ev0.elapsed_time(ev1)
+    ms_per_step = total_ms / args.steps
+    sweep = g.timing()
+    log("timed %d steps: %.4f ms/step; sweep kernel mean %.4f ms (min %.4f, max %.4f, n=%d)" % (
+        args.steps, ms_per_step, sweep["mean_ms"], sweep["min_ms"], sweep["max_ms"], sweep["count"]))
+
+    # Untimed: exact check of the last output.
+    import oracle
+    mate = out.cpu().numpy()
+    chk = oracle.check(csr, mate)
+    log("checker: violations=%d size=%d (SGMM %d)" % (chk.violations, chk.size, ref.pairs))
+
+    counters = None
+    if not args.no_stats:
+        gs = mm.Graph(off, nbr, symmetric=True, stats=True, tuning=tun)
+        o2 = gs.run()
+        gs.sync()
+        counters = gs.stats()
+        c2 = oracle.check(csr, o2.cpu().numpy())
+        counters["checker_violations"] = c2.violations
+        gs.close()
+        log("counters: %s" % counters)
+
+    n, m = csr.n, csr.m
+    w = csr.off.dtype.itemsize
+    # Algorithmic bytes of one sweep launch (lazy U8 path): offsets, the ids a
+    # sequential pass must read, one state byte per source, one mate per vertex.
+    b_sweep = w * (n + 1) + 4 * t_seq + n + 4 * n
+    b_pass = b_sweep + n  # plus the state initialisation
+    sweep_s = sweep["mean_ms"] / 1e3
+    achieved = b_sweep / sweep_s / 1e9 if sweep_s > 0 else 0.0
+    value = m / (ms_per_step / 1e3) / 1e9
+    result = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "GEdges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": dict(config, n=n, m=m, layout=args.layout, lazy_init=int(tun.lazy_init),
+                       wave_vertices=tun.wave_vertices, wg_size=tun.wg_size,
+                       disperse=tun.disperse, assist_after=tun.assist_after),
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "sweep_kernel",
+            "achieved": round(achieved, 2),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 5),
+            "traffic": None,
+            "alg_bytes_per_launch": int(b_sweep),
+            "sweep_ms": round(sweep["mean_ms"], 5),
+            "pass_alg_bytes": int(b_pass),
+            "pass_frac": round(b_pass / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 5),
+        },
+        "cpu_baseline": {
+            "value": round(m / t_sgmm / 1e9, 4),
+            "unit": "GEdges/s",
+            "cores": 1,
+            "kind": "oracle",
+            "sample": "full graph, SGMM single thread, median of %d run(s), %.3f s each" % (reps, t_sgmm),
+        },
+        "checker": {"violations": chk.violations, "size": chk.size, "size_sgmm": ref.pairs,
+                    "t_seq": t_seq},
+        "counters": counters,
+    }
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,182 @@
+/*
+ * mm.h: C ABI of the MI355X (gfx950) maximal-matching library.
+ *
+ * The library computes a maximal matching of an undirected graph with the
+ * single-pass, just-in-time conflict-resolution method of Skipper
+ * (Koohi Esfahani, arXiv 2507.04420, Section IV and Algorithm 1): every vertex
+ * carries a state (accessible, reserved, matched); each edge (x, y), x != y,
+ * is examined by the lane that owns its source, which reserves the lower-id
+ * endpoint u, then tries to move the higher-id endpoint v from accessible to
+ * matched, and on success marks u matched (otherwise releases u). Once a
+ * source is matched the rest of its neighbour list is skipped (Section II-B,
+ * CSR form of greedy matching; Fig. 6g).
+ *
+ * Conventions for every entry point:
+ *  - Pointers marked "device" are device (HBM) addresses on the current HIP
+ *    device; pointers marked "host" are host addresses.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream). Work
+ *    is enqueued on it and the call returns without waiting.
+ *  - Return codes only; nothing crosses the ABI as an exception. After a
+ *    non-OK status, mm_last_error() returns a thread-local message.
+ *  - The graph arrays are borrowed: the library neither copies nor frees
+ *    them, and they must outlive the handle. Workspaces and outputs are
+ *    caller-owned device memory.
+ *
+ * Graph format (Section II-A): CSR with `offsets` of n+1 entries (int32 or
+ * int64, non-decreasing, offsets[0] = 0, offsets[n] = m) and `neighbors` of m
+ * int32 ids in [0, n). Self-loops and duplicate entries are allowed and never
+ * matched. A non-symmetric CSR is accepted; the result is then maximal for the
+ * undirected union of its entries (Section V-C, input format).
+ *
+ * Output: a mate array of n int32 entries: match[v] = w if {v, w} is in the
+ * matching, -1 if v is unmatched. It is symmetric, and the matching is
+ * maximal. Several maximal matchings can be correct: the method is
+ * non-deterministic (Section V-C).
+ */
+#ifndef MM_H
+#define MM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mm_graph* mm_handle;
+
+typedef enum {
+  MM_OK = 0,
+  MM_ERR_INVALID_ARG = 1,    /* null pointer, bad size or bad tuning value */
+  MM_ERR_INVALID_GRAPH = 2,  /* MM_VALIDATE found a malformed CSR */
+  MM_ERR_OUT_OF_MEMORY = 3,  /* workspace smaller than mm_workspace_bytes() */
+  MM_ERR_HIP = 4,            /* a HIP runtime call failed (message has details) */
+  MM_ERR_NO_PROGRESS = 5,    /* a wavefront exceeded its loop-trip budget */
+  MM_ERR_UNSUPPORTED = 6     /* option combination not supported */
+} mm_status;
+
+typedef enum { MM_OFF_I32 = 0, MM_OFF_I64 = 1 } mm_offset_type;
+
+/* Vertex state layouts (Section IV-C keeps one byte of state per vertex). */
+typedef enum {
+  /* One state byte per vertex, four per 32-bit word; byte transitions use
+     32-bit atomics on the containing word. The mate array is separate. */
+  MM_LAYOUT_U8 = 0,
+  /* One 32-bit word per vertex that is also the output: -1 accessible,
+     -2 reserved, >= 0 matched (the word holds the mate). */
+  MM_LAYOUT_U32 = 1
+} mm_layout;
+
+/* Creation flags. */
+enum {
+  MM_VALIDATE = 1u,   /* check the CSR on the device at create (synchronous) */
+  MM_SYMMETRIC = 2u,  /* caller asserts every entry (x,y) has its reverse (y,x);
+                         enables lazy mate initialisation */
+  MM_STATS = 4u,      /* run the instrumented kernels: counters for mm_get_stats */
+  MM_TIMING = 8u      /* record HIP events around each sweep launch (mm_get_timing) */
+};
+
+/* Launch and layout parameters. None of them changes what a correct result
+   is; they change only speed. Fill with mm_default_tuning() first. */
+typedef struct {
+  int32_t layout;        /* mm_layout */
+  int32_t wg_size;       /* threads per workgroup: 64, 128, 192 or 256 */
+  int32_t wave_vertices; /* source vertices handed to one wavefront, >= 64, multiple of 64 */
+  int32_t disperse;      /* 0: a wavefront's lanes take consecutive sources;
+                            1: concurrently active lanes of a wavefront take sources
+                            wave_vertices/64 apart (for high-locality graphs) */
+  int32_t assist_after;  /* scan steps after which the wavefront helps a lane's
+                            long scan 64 entries at a time; <= 0 disables */
+  int32_t lazy_init;     /* 1: mate entries written by the sweep itself instead of
+                            a separate -1 fill (needs MM_SYMMETRIC and MM_LAYOUT_U8) */
+  int64_t iter_cap;      /* loop-trip budget per wavefront; 0 = default of
+                            65536 + 8 x (neighbour entries of its block);
+                            exceeding it raises MM_ERR_NO_PROGRESS */
+} mm_tuning;
+
+/* Counters of the instrumented kernels (MM_STATS). Conflicts follow Table II
+   of the paper: a failed CAS while reserving u or matching v. */
+typedef struct {
+  uint64_t sources;           /* source vertices visited */
+  uint64_t sources_skipped;   /* sources already matched when visited */
+  uint64_t touched;           /* neighbour ids read by scanning lanes (T_gpu) */
+  uint64_t assist_reads;      /* neighbour ids read by wavefront assists */
+  uint64_t reserve_attempts;  /* CAS/fetch-or on u */
+  uint64_t reserve_conflicts; /* u found reserved by another lane */
+  uint64_t reserve_matched;   /* u found matched by the atomic (stale filter) */
+  uint64_t match_attempts;    /* CAS on v */
+  uint64_t match_conflicts;   /* v found reserved by another lane */
+  uint64_t match_matched;     /* v found matched by the atomic */
+  uint64_t word_retries;      /* U8 layout: CAS retried because another byte of
+                                 the same 32-bit word changed (not a conflict) */
+  uint64_t pairs;             /* matched pairs committed */
+  uint64_t loop_trips;        /* sum over wavefronts of loop trips */
+  uint64_t reserved_[3];
+} mm_stats;
+
+/* Fills *t with the defaults. */
+void mm_default_tuning(mm_tuning* t);
+
+/* Bytes of device workspace a graph of n vertices needs under tuning t
+   (NULL = defaults). Returns 0 if n or t is invalid. */
+size_t mm_workspace_bytes(int64_t n, const mm_tuning* t);
+
+/*
+ * Creates a handle for one graph.
+ *  offsets    device, n+1 entries of `off_type`
+ *  neighbors  device, m int32 entries
+ *  n, m       vertex and entry counts; 0 <= n <= 2^31-1; m <= 2^31-1 for int32 offsets
+ *  workspace  device, >= mm_workspace_bytes(n, tuning) bytes, 256-byte aligned,
+ *             caller-owned, must outlive the handle; holds vertex states,
+ *             counters and the error flag
+ *  flags      MM_VALIDATE | MM_SYMMETRIC | MM_STATS | MM_TIMING
+ *  tuning     host, NULL = defaults; copied
+ * With MM_VALIDATE the call runs a device check on `stream` and waits for it;
+ * a malformed CSR returns MM_ERR_INVALID_GRAPH and no handle.
+ */
+mm_status mm_create(const void* offsets, mm_offset_type off_type, const int32_t* neighbors,
+                    int64_t n, int64_t m, void* workspace, size_t workspace_bytes,
+                    uint32_t flags, const mm_tuning* tuning, void* stream, mm_handle* out);
+
+/*
+ * Enqueues one maximal-matching pass on `stream`: state initialisation, then
+ * the sweep (Algorithm 1). match_out: device, n int32, caller-owned; valid
+ * after the stream reaches this point. One pass at a time per handle (the
+ * vertex states live in its workspace); different handles may run
+ * concurrently on different streams.
+ */
+mm_status mm_run(mm_handle h, void* stream, int32_t* match_out);
+
+/* Waits for `stream`, then reports a device-side failure of any earlier pass
+   of this handle (MM_ERR_NO_PROGRESS) and clears it. */
+mm_status mm_sync(mm_handle h, void* stream);
+
+/* Waits for `stream` and copies the counters accumulated since the last
+   mm_reset_stats (MM_STATS handles only; others return MM_ERR_UNSUPPORTED). */
+mm_status mm_get_stats(mm_handle h, void* stream, mm_stats* out);
+mm_status mm_reset_stats(mm_handle h, void* stream);
+
+/* MM_TIMING handles: waits for the events of the passes enqueued since the
+   last call, and returns how many sweep launches they hold and the sum, min
+   and max of their device durations in milliseconds (hipEventElapsedTime of
+   events recorded on the launch stream right before and after the sweep
+   kernel). Up to 512 launches are kept between calls; older ones are dropped
+   (count tells how many were measured). */
+mm_status mm_get_timing(mm_handle h, int64_t* count, double* total_ms, double* min_ms,
+                        double* max_ms);
+
+/* Frees the host-side handle (and its timing events). Does not touch
+   caller-owned memory. */
+void mm_destroy(mm_handle h);
+
+/* Thread-local description of the last non-OK status returned on this thread. */
+const char* mm_last_error(void);
+
+/* Library version string. */
+const char* mm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MM_H */

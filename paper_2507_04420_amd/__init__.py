@@ -1,0 +1,168 @@
+"""Skipper maximal matching on MI355X (gfx950).
+
+Python surface over the C ABI of include/mm.h. PyTorch supplies device
+memory and streams; every step of a matching pass runs in the library's HIP
+kernels.
+
+    g = Graph(offsets, neighbors, symmetric=True)   # CSR on the GPU
+    mate = g.run()                                  # int32[n], -1 = unmatched
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import asdict, dataclass
+
+from . import _lib
+from ._lib import MMError  # noqa: F401
+
+__all__ = ["Graph", "Tuning", "MMError", "maximal_matching", "library_path", "version"]
+
+
+def library_path() -> str:
+    return _lib.LIB_PATH
+
+
+def version() -> str:
+    return _lib.load().mm_version().decode()
+
+
+@dataclass
+class Tuning:
+    """Launch and layout parameters (see mm_tuning in include/mm.h)."""
+    layout: int = _lib.MM_LAYOUT_U8
+    wg_size: int = 256
+    wave_vertices: int = 1024
+    disperse: int = 0
+    assist_after: int = 16
+    lazy_init: int = 1
+    iter_cap: int = 0
+
+    @classmethod
+    def default(cls) -> "Tuning":
+        t = _lib.mm_tuning()
+        _lib.load().mm_default_tuning(ctypes.byref(t))
+        return cls(**{f: getattr(t, f) for f, _ in _lib.mm_tuning._fields_})
+
+    def to_c(self) -> _lib.mm_tuning:
+        return _lib.mm_tuning(**asdict(self))
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _check_graph_tensors(offsets, neighbors):
+    import torch
+    if not (offsets.is_cuda and neighbors.is_cuda):
+        raise ValueError("offsets and neighbors must be CUDA (HIP) tensors")
+    if offsets.dim() != 1 or neighbors.dim() != 1:
+        raise ValueError("offsets and neighbors must be 1-D")
+    if not offsets.is_contiguous() or not neighbors.is_contiguous():
+        raise ValueError("offsets and neighbors must be contiguous")
+    if offsets.dtype == torch.int64:
+        off_type = _lib.MM_OFF_I64
+    elif offsets.dtype == torch.int32:
+        off_type = _lib.MM_OFF_I32
+    else:
+        raise ValueError("offsets must be int32 or int64")
+    if neighbors.dtype != torch.int32:
+        raise ValueError("neighbors must be int32")
+    if offsets.numel() < 1:
+        raise ValueError("offsets needs n+1 >= 1 entries")
+    return off_type
+
+
+class Graph:
+    """One graph resident on the GPU, with its workspace.
+
+    The CSR tensors are borrowed (kept referenced here). ``symmetric=True``
+    asserts every entry has its reverse, which allows lazy mate output.
+    """
+
+    def __init__(self, offsets, neighbors, *, symmetric: bool = False, validate: bool = False,
+                 stats: bool = False, timing: bool = False, tuning: Tuning | None = None,
+                 stream=None):
+        import torch
+        lib = _lib.load()
+        off_type = _check_graph_tensors(offsets, neighbors)
+        self.offsets, self.neighbors = offsets, neighbors
+        self.n = offsets.numel() - 1
+        self.m = neighbors.numel()
+        self.tuning = tuning if tuning is not None else Tuning.default()
+        ct = self.tuning.to_c()
+        nbytes = lib.mm_workspace_bytes(self.n, ctypes.byref(ct))
+        if nbytes == 0:
+            raise MMError(_lib.MM_ERR_INVALID_ARG, "invalid n or tuning")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=offsets.device)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        flags = ((_lib.MM_VALIDATE if validate else 0) | (_lib.MM_SYMMETRIC if symmetric else 0)
+                 | (_lib.MM_STATS if stats else 0) | (_lib.MM_TIMING if timing else 0))
+        h = ctypes.c_void_p()
+        _lib.check(lib.mm_create(ctypes.c_void_p(offsets.data_ptr()), off_type,
+                                 ctypes.c_void_p(neighbors.data_ptr()), self.n, self.m,
+                                 ctypes.c_void_p(aligned), nbytes, flags, ctypes.byref(ct),
+                                 _stream_ptr(stream), ctypes.byref(h)))
+        self._h = h
+        self.device = offsets.device
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        if self._h is None:
+            raise ValueError("graph handle was closed")
+        return self._h
+
+    def run(self, out=None, stream=None):
+        """Enqueues one matching pass; returns the int32 mate tensor."""
+        import torch
+        if out is None:
+            out = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        elif out.dtype != torch.int32 or out.numel() != self.n or not out.is_contiguous():
+            raise ValueError("out must be a contiguous int32 tensor of n entries")
+        _lib.check(_lib.load().mm_run(self.handle, _stream_ptr(stream), ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def sync(self, stream=None) -> None:
+        """Waits for the stream and raises if a pass ran out of its loop budget."""
+        _lib.check(_lib.load().mm_sync(self.handle, _stream_ptr(stream)))
+
+    def stats(self, stream=None) -> dict:
+        s = _lib.mm_stats()
+        _lib.check(_lib.load().mm_get_stats(self.handle, _stream_ptr(stream), ctypes.byref(s)))
+        return {f: int(getattr(s, f)) for f, _ in _lib.mm_stats._fields_ if not f.startswith("reserved")}
+
+    def timing(self) -> dict:
+        """Sweep-kernel durations of the passes since the last call (ms)."""
+        cnt, tot, lo, hi = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _lib.check(_lib.load().mm_get_timing(self.handle, ctypes.byref(cnt), ctypes.byref(tot),
+                                             ctypes.byref(lo), ctypes.byref(hi)))
+        n = cnt.value
+        return {"count": n, "total_ms": tot.value, "mean_ms": tot.value / n if n else 0.0,
+                "min_ms": lo.value, "max_ms": hi.value}
+
+    def reset_stats(self, stream=None) -> None:
+        _lib.check(_lib.load().mm_reset_stats(self.handle, _stream_ptr(stream)))
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None:
+            _lib.load().mm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def maximal_matching(offsets, neighbors, *, symmetric: bool = False, tuning: Tuning | None = None,
+                     stream=None):
+    """One-shot helper: create, run, wait; returns the int32 mate tensor."""
+    g = Graph(offsets, neighbors, symmetric=symmetric, tuning=tuning, stream=stream)
+    out = g.run(stream=stream)
+    g.sync(stream=stream)
+    g.close()
+    return out

@@ -1,0 +1,103 @@
+"""ctypes declarations of the C ABI in include/mm.h.
+
+Loads the in-tree libmm_hip.so. If it has not been built yet, it is built
+once with hipcc; if that fails, the import fails loudly. There is no other
+implementation to fall back to.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libmm_hip.so")
+_lib = None
+_lock = threading.Lock()
+
+MM_OK = 0
+MM_ERR_INVALID_ARG = 1
+MM_ERR_INVALID_GRAPH = 2
+MM_ERR_OUT_OF_MEMORY = 3
+MM_ERR_HIP = 4
+MM_ERR_NO_PROGRESS = 5
+MM_ERR_UNSUPPORTED = 6
+STATUS_NAMES = {
+    0: "MM_OK", 1: "MM_ERR_INVALID_ARG", 2: "MM_ERR_INVALID_GRAPH", 3: "MM_ERR_OUT_OF_MEMORY",
+    4: "MM_ERR_HIP", 5: "MM_ERR_NO_PROGRESS", 6: "MM_ERR_UNSUPPORTED",
+}
+
+MM_OFF_I32, MM_OFF_I64 = 0, 1
+MM_LAYOUT_U8, MM_LAYOUT_U32 = 0, 1
+MM_VALIDATE, MM_SYMMETRIC, MM_STATS, MM_TIMING = 1, 2, 4, 8
+
+
+class mm_tuning(ctypes.Structure):
+    _fields_ = [
+        ("layout", ctypes.c_int32),
+        ("wg_size", ctypes.c_int32),
+        ("wave_vertices", ctypes.c_int32),
+        ("disperse", ctypes.c_int32),
+        ("assist_after", ctypes.c_int32),
+        ("lazy_init", ctypes.c_int32),
+        ("iter_cap", ctypes.c_int64),
+    ]
+
+
+class mm_stats(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_uint64) for name in (
+        "sources", "sources_skipped", "touched", "assist_reads", "reserve_attempts",
+        "reserve_conflicts", "reserve_matched", "match_attempts", "match_conflicts",
+        "match_matched", "word_retries", "pairs", "loop_trips", "reserved0", "reserved1",
+        "reserved2")]
+
+
+# Every entry point declared in include/mm.h, with its ctypes signature.
+_P, _I32, _I64, _U32, _SZ = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
+                             ctypes.c_size_t)
+SIGNATURES = {
+    "mm_default_tuning": (None, [ctypes.POINTER(mm_tuning)]),
+    "mm_workspace_bytes": (_SZ, [_I64, ctypes.POINTER(mm_tuning)]),
+    "mm_create": (_I32, [_P, _I32, _P, _I64, _I64, _P, _SZ, _U32, ctypes.POINTER(mm_tuning), _P,
+                         ctypes.POINTER(_P)]),
+    "mm_run": (_I32, [_P, _P, _P]),
+    "mm_sync": (_I32, [_P, _P]),
+    "mm_get_stats": (_I32, [_P, _P, ctypes.POINTER(mm_stats)]),
+    "mm_reset_stats": (_I32, [_P, _P]),
+    "mm_get_timing": (_I32, [_P, ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_double),
+                             ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+    "mm_destroy": (None, [_P]),
+    "mm_last_error": (ctypes.c_char_p, []),
+    "mm_version": (ctypes.c_char_p, []),
+}
+
+
+def load():
+    """Returns the loaded library, building it first if it is absent."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            from . import build as _build
+            _build.build(force=True)
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+        return lib
+
+
+class MMError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, str(status)), message))
+        self.status = status
+        self.message = message
+
+
+def check(status: int) -> None:
+    if status != MM_OK:
+        msg = load().mm_last_error()
+        raise MMError(status, msg.decode() if msg else "")

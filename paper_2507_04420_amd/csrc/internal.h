@@ -1,0 +1,33 @@
+// Host-side helpers shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "mm.h"
+
+namespace mmi {
+
+// Records a thread-local message for mm_last_error() and returns s.
+mm_status fail(mm_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+
+inline size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Validates a tuning struct (wg_size, wave_vertices, layout, flags ranges).
+mm_status check_tuning(const mm_tuning& t);
+
+// Control block at the start of every workspace: error word at 0, counters
+// at kStatsOffset, a work-queue counter at kQueueOffset.
+constexpr size_t kCtrlBytes = 4096;
+constexpr size_t kStatsOffset = 256;
+constexpr size_t kQueueOffset = 1024;
+
+}  // namespace mmi
+
+#define MMI_HIP_TRY(expr)                                                          \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      return ::mmi::fail(MM_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)

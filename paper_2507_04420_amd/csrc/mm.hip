@@ -1,0 +1,423 @@
+// C ABI of the gfx950 maximal-matching library (declared in include/mm.h):
+// handles, workspace layout, argument checks, and the kernel launches of one
+// pass (state initialisation, then the sweep of Algorithm 1).
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "internal.h"
+#include "mm.h"
+#include "sweep.h"
+
+using namespace mmk;
+using mmi::fail;
+using mmi::kCtrlBytes;
+using mmi::kStatsOffset;
+using mmi::round_up;
+#define HIP_TRY MMI_HIP_TRY
+
+namespace {
+thread_local std::string g_last_error;
+}  // namespace
+
+namespace mmi {
+
+mm_status fail(mm_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return s;
+}
+
+mm_status check_tuning(const mm_tuning& t) {
+  if (t.layout != MM_LAYOUT_U8 && t.layout != MM_LAYOUT_U32)
+    return fail(MM_ERR_INVALID_ARG, "tuning.layout must be MM_LAYOUT_U8 or MM_LAYOUT_U32");
+  if (t.wg_size < 64 || t.wg_size > 256 || t.wg_size % 64)
+    return fail(MM_ERR_INVALID_ARG, "tuning.wg_size must be 64, 128, 192 or 256 (got %d)",
+                t.wg_size);
+  if (t.wave_vertices < 64 || t.wave_vertices % 64)
+    return fail(MM_ERR_INVALID_ARG, "tuning.wave_vertices must be a positive multiple of 64");
+  if (t.disperse != 0 && t.disperse != 1)
+    return fail(MM_ERR_INVALID_ARG, "tuning.disperse must be 0 or 1");
+  if (t.lazy_init != 0 && t.lazy_init != 1)
+    return fail(MM_ERR_INVALID_ARG, "tuning.lazy_init must be 0 or 1");
+  if (t.iter_cap < 0) return fail(MM_ERR_INVALID_ARG, "tuning.iter_cap must be >= 0");
+  return MM_OK;
+}
+
+}  // namespace mmi
+
+using mmi::check_tuning;
+
+namespace {
+
+// ---------------------------------------------------------------- kernels
+
+// Fills `words` 32-bit words with `value` (state and mate initialisation,
+// Alg. 1 L3-4).
+__global__ void fill_u32_kernel(uint32_t* __restrict__ p, int64_t words, uint32_t value) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t quads = words >> 2;
+  uint4* q = reinterpret_cast<uint4*>(p);
+  const uint4 vv = make_uint4(value, value, value, value);
+  for (int64_t j = t; j < quads; j += stride) q[j] = vv;
+  for (int64_t j = (quads << 2) + t; j < words; j += stride) p[j] = value;
+}
+
+// CSR well-formedness (checked at create with MM_VALIDATE). Bits of *flags:
+// 1 offsets[0] != 0 or offsets[n] != m; 2 offsets decrease; 4 neighbour out
+// of range.
+template <typename OffT>
+__global__ void validate_kernel(const OffT* __restrict__ off, const int32_t* __restrict__ nbr,
+                                int64_t n, int64_t m, uint32_t* flags) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t f = 0;
+  if (t == 0 && ((int64_t)off[0] != 0 || (int64_t)off[n] != m)) f |= 1u;
+  for (int64_t v = t; v < n; v += stride)
+    if (off[v + 1] < off[v]) f |= 2u;
+  for (int64_t j = t; j < m; j += stride) {
+    const int32_t y = nbr[j];
+    if (y < 0 || (int64_t)y >= n) f |= 4u;
+  }
+  if (f) atomicOr(flags, f);
+}
+
+// One graph: wavefront w sweeps sources [w * wave_vertices, ...).
+template <typename OffT, class Layout, bool LAZY, bool STATS>
+__global__ __launch_bounds__(256) void sweep_kernel(SweepParams p, const OffT* __restrict__ off,
+                                                   const int32_t* __restrict__ nbr, int64_t n,
+                                                   Layout L, int32_t* __restrict__ mate,
+                                                   unsigned long long* stats) {
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t vb = wave * p.wave_vertices;
+  if (vb >= n) return;
+  const int64_t nv = (n - vb < p.wave_vertices) ? (n - vb) : p.wave_vertices;
+  Counters<STATS> cnt;
+  sweep_block<OffT, Layout, LAZY, STATS>(p, off, nbr, L, mate, vb, nv, cnt);
+  if (STATS) cnt.flush(stats);
+}
+
+// ---------------------------------------------------------------- helpers
+
+int fill_grid(int64_t words) {
+  int64_t blocks = (words / 4 + 255) / 256;
+  if (blocks < 1) blocks = 1;
+  if (blocks > 8192) blocks = 8192;
+  return (int)blocks;
+}
+
+size_t state_bytes(int64_t n, const mm_tuning& t) {
+  return t.layout == MM_LAYOUT_U8 ? round_up((size_t)((n + 3) / 4) * 4, 256) : 0;
+}
+
+}  // namespace
+
+// Ring of event pairs bracketing sweep launches (MM_TIMING handles).
+struct TimingRing {
+  static constexpr int kCap = 512;
+  hipEvent_t ev[2 * kCap] = {};
+  int64_t recorded = 0;  // launches recorded since the last read
+  bool ready = false;
+  hipError_t init() {
+    for (int i = 0; i < 2 * kCap; ++i) {
+      hipError_t e = hipEventCreate(&ev[i]);
+      if (e != hipSuccess) return e;
+    }
+    ready = true;
+    return hipSuccess;
+  }
+  void destroy() {
+    for (int i = 0; i < 2 * kCap; ++i)
+      if (ev[i]) hipEventDestroy(ev[i]);
+  }
+  hipEvent_t before() const { return ev[2 * (recorded % kCap)]; }
+  hipEvent_t after() const { return ev[2 * (recorded % kCap) + 1]; }
+};
+
+struct mm_graph {
+  const void* off;
+  int off64;
+  const int32_t* nbr;
+  int64_t n, m;
+  uint8_t* ws;
+  size_t ws_bytes;
+  uint32_t flags;
+  mm_tuning tun;
+  int device;
+  TimingRing* timing;
+};
+
+extern "C" {
+
+const char* mm_version(void) { return "skipper-gfx950 0.1"; }
+
+const char* mm_last_error(void) { return g_last_error.c_str(); }
+
+void mm_default_tuning(mm_tuning* t) {
+  if (!t) return;
+  std::memset(t, 0, sizeof(*t));
+  t->layout = MM_LAYOUT_U8;
+  t->wg_size = 256;
+  t->wave_vertices = 1024;
+  t->disperse = 0;
+  t->assist_after = 16;
+  t->lazy_init = 1;
+  t->iter_cap = 0;
+}
+
+size_t mm_workspace_bytes(int64_t n, const mm_tuning* tp) {
+  mm_tuning t;
+  if (tp) t = *tp; else mm_default_tuning(&t);
+  if (n < 0 || n > INT32_MAX || check_tuning(t) != MM_OK) return 0;
+  return kCtrlBytes + state_bytes(n, t);
+}
+
+mm_status mm_create(const void* offsets, mm_offset_type off_type, const int32_t* neighbors,
+                    int64_t n, int64_t m, void* workspace, size_t workspace_bytes, uint32_t flags,
+                    const mm_tuning* tuning, void* stream, mm_handle* out) {
+  if (!out) return fail(MM_ERR_INVALID_ARG, "out handle pointer is null");
+  *out = nullptr;
+  if (off_type != MM_OFF_I32 && off_type != MM_OFF_I64)
+    return fail(MM_ERR_INVALID_ARG, "off_type must be MM_OFF_I32 or MM_OFF_I64");
+  if (n < 0 || n > INT32_MAX) return fail(MM_ERR_INVALID_ARG, "n = %lld out of [0, 2^31-1]", (long long)n);
+  if (m < 0) return fail(MM_ERR_INVALID_ARG, "m = %lld is negative", (long long)m);
+  if (off_type == MM_OFF_I32 && m > INT32_MAX)
+    return fail(MM_ERR_INVALID_ARG, "m = %lld does not fit int32 offsets", (long long)m);
+  if (!offsets) return fail(MM_ERR_INVALID_ARG, "offsets is null");
+  if (!neighbors && m > 0) return fail(MM_ERR_INVALID_ARG, "neighbors is null");
+  if (!workspace) return fail(MM_ERR_INVALID_ARG, "workspace is null");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256)
+    return fail(MM_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  if (flags & ~(uint32_t)(MM_VALIDATE | MM_SYMMETRIC | MM_STATS | MM_TIMING))
+    return fail(MM_ERR_INVALID_ARG, "unknown flag bits 0x%x", flags);
+  mm_tuning t;
+  if (tuning) t = *tuning; else mm_default_tuning(&t);
+  mm_status st = check_tuning(t);
+  if (st != MM_OK) return st;
+  if (t.lazy_init && (t.layout != MM_LAYOUT_U8 || !(flags & MM_SYMMETRIC)))
+    t.lazy_init = 0;  // lazy mate output is only sound for symmetric input on the U8 layout
+  const size_t need = kCtrlBytes + state_bytes(n, t);
+  if (workspace_bytes < need)
+    return fail(MM_ERR_OUT_OF_MEMORY, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
+
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  uint8_t* ws = static_cast<uint8_t*>(workspace);
+  HIP_TRY(hipMemsetAsync(ws, 0, kCtrlBytes, s));
+  if (flags & MM_VALIDATE) {
+    uint32_t* f = reinterpret_cast<uint32_t*>(ws);
+    int64_t work = n > m ? n : m;
+    int blocks = (int)((work + 255) / 256);
+    if (blocks < 1) blocks = 1;
+    if (blocks > 4096) blocks = 4096;
+    if (off_type == MM_OFF_I64)
+      hipLaunchKernelGGL((validate_kernel<int64_t>), dim3(blocks), dim3(256), 0, s,
+                         static_cast<const int64_t*>(offsets), neighbors, n, m, f);
+    else
+      hipLaunchKernelGGL((validate_kernel<int32_t>), dim3(blocks), dim3(256), 0, s,
+                         static_cast<const int32_t*>(offsets), neighbors, n, m, f);
+    HIP_TRY(hipGetLastError());
+    uint32_t hf = 0;
+    HIP_TRY(hipMemcpyAsync(&hf, f, sizeof(hf), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipMemsetAsync(ws, 0, kCtrlBytes, s));
+    if (hf) {
+      return fail(MM_ERR_INVALID_GRAPH, "invalid CSR:%s%s%s",
+                  (hf & 1u) ? " offsets[0] != 0 or offsets[n] != m;" : "",
+                  (hf & 2u) ? " offsets decrease;" : "",
+                  (hf & 4u) ? " neighbour id out of [0, n);" : "");
+    }
+  }
+  mm_graph* g = new (std::nothrow) mm_graph();
+  if (!g) return fail(MM_ERR_OUT_OF_MEMORY, "host allocation of the handle failed");
+  g->off = offsets;
+  g->off64 = off_type == MM_OFF_I64;
+  g->nbr = neighbors;
+  g->n = n;
+  g->m = m;
+  g->ws = ws;
+  g->ws_bytes = workspace_bytes;
+  g->flags = flags;
+  g->tun = t;
+  g->device = dev;
+  g->timing = nullptr;
+  if (flags & MM_TIMING) {
+    g->timing = new (std::nothrow) TimingRing();
+    if (!g->timing) {
+      delete g;
+      return fail(MM_ERR_OUT_OF_MEMORY, "host allocation of the timing ring failed");
+    }
+    hipError_t e = g->timing->init();
+    if (e != hipSuccess) {
+      g->timing->destroy();
+      delete g->timing;
+      delete g;
+      return fail(MM_ERR_HIP, "hipEventCreate failed: %s", hipGetErrorString(e));
+    }
+  }
+  *out = g;
+  return MM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+template <typename OffT, class Layout, bool LAZY, bool STATS>
+hipError_t launch_sweep(const mm_graph* g, const Layout& L, int32_t* mate, hipStream_t s) {
+  SweepParams p;
+  p.wave_vertices = g->tun.wave_vertices;
+  p.disperse = g->tun.disperse;
+  p.assist_after = g->tun.assist_after;
+  p.iter_cap = g->tun.iter_cap;
+  p.err = reinterpret_cast<uint32_t*>(g->ws);
+  unsigned long long* stats = reinterpret_cast<unsigned long long*>(g->ws + kStatsOffset);
+  const int64_t waves = (g->n + p.wave_vertices - 1) / p.wave_vertices;
+  const int wpb = g->tun.wg_size / 64;
+  const int64_t blocks = (waves + wpb - 1) / wpb;
+  if (blocks == 0) return hipSuccess;
+  if (g->timing) {
+    hipError_t e = hipEventRecord(g->timing->before(), s);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((sweep_kernel<OffT, Layout, LAZY, STATS>), dim3((unsigned)blocks),
+                     dim3(g->tun.wg_size), 0, s, p, static_cast<const OffT*>(g->off), g->nbr, g->n,
+                     L, mate, stats);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (g->timing) {
+    e = hipEventRecord(g->timing->after(), s);
+    ++g->timing->recorded;
+  }
+  return e;
+}
+
+template <typename OffT, bool STATS>
+hipError_t run_typed(const mm_graph* g, int32_t* mate, hipStream_t s) {
+  const int64_t n = g->n;
+  if (g->tun.layout == MM_LAYOUT_U32) {
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(fill_grid(n)), dim3(256), 0, s,
+                       reinterpret_cast<uint32_t*>(mate), n, 0xffffffffu);
+    LayoutU32 L{mate};
+    return launch_sweep<OffT, LayoutU32, false, STATS>(g, L, mate, s);
+  }
+  uint32_t* st = reinterpret_cast<uint32_t*>(g->ws + kCtrlBytes);
+  const int64_t words = (n + 3) / 4;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(fill_grid(words)), dim3(256), 0, s, st, words, 0u);
+  LayoutU8 L{st, mate};
+  if (g->tun.lazy_init) return launch_sweep<OffT, LayoutU8, true, STATS>(g, L, mate, s);
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(fill_grid(n)), dim3(256), 0, s,
+                     reinterpret_cast<uint32_t*>(mate), n, 0xffffffffu);
+  return launch_sweep<OffT, LayoutU8, false, STATS>(g, L, mate, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+mm_status mm_run(mm_handle g, void* stream, int32_t* match_out) {
+  if (!g) return fail(MM_ERR_INVALID_ARG, "handle is null");
+  if (!match_out && g->n > 0) return fail(MM_ERR_INVALID_ARG, "match_out is null");
+  if (g->n == 0) return MM_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool stats = (g->flags & MM_STATS) != 0;
+  hipError_t e;
+  if (g->off64)
+    e = stats ? run_typed<int64_t, true>(g, match_out, s) : run_typed<int64_t, false>(g, match_out, s);
+  else
+    e = stats ? run_typed<int32_t, true>(g, match_out, s) : run_typed<int32_t, false>(g, match_out, s);
+  if (e != hipSuccess) return fail(MM_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e));
+  return MM_OK;
+}
+
+mm_status mm_sync(mm_handle g, void* stream) {
+  if (!g) return fail(MM_ERR_INVALID_ARG, "handle is null");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  uint32_t err = 0;
+  HIP_TRY(hipMemcpyAsync(&err, g->ws, sizeof(err), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (err) {
+    HIP_TRY(hipMemsetAsync(g->ws, 0, sizeof(uint32_t), s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return fail(MM_ERR_NO_PROGRESS, "a wavefront exceeded its loop-trip budget (%lld%s)",
+                (long long)g->tun.iter_cap, g->tun.iter_cap ? "" : ": per-block default");
+  }
+  return MM_OK;
+}
+
+mm_status mm_get_stats(mm_handle g, void* stream, mm_stats* out) {
+  if (!g || !out) return fail(MM_ERR_INVALID_ARG, "null argument");
+  if (!(g->flags & MM_STATS)) return fail(MM_ERR_UNSUPPORTED, "handle was created without MM_STATS");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  unsigned long long c[16] = {};
+  HIP_TRY(hipMemcpyAsync(c, g->ws + kStatsOffset, sizeof(c), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  std::memset(out, 0, sizeof(*out));
+  out->sources = c[S_SOURCES];
+  out->sources_skipped = c[S_SKIPPED];
+  out->touched = c[S_TOUCHED];
+  out->assist_reads = c[S_ASSIST];
+  out->reserve_attempts = c[S_RES_ATT];
+  out->reserve_conflicts = c[S_RES_CONF];
+  out->reserve_matched = c[S_RES_MCHD];
+  out->match_attempts = c[S_MAT_ATT];
+  out->match_conflicts = c[S_MAT_CONF];
+  out->match_matched = c[S_MAT_MCHD];
+  out->word_retries = c[S_WORD_RETRY];
+  out->pairs = c[S_PAIRS];
+  out->loop_trips = c[S_TRIPS];
+  return MM_OK;
+}
+
+mm_status mm_reset_stats(mm_handle g, void* stream) {
+  if (!g) return fail(MM_ERR_INVALID_ARG, "handle is null");
+  HIP_TRY(hipMemsetAsync(g->ws + kStatsOffset, 0, 16 * sizeof(unsigned long long),
+                         static_cast<hipStream_t>(stream)));
+  return MM_OK;
+}
+
+mm_status mm_get_timing(mm_handle g, int64_t* count, double* total_ms, double* min_ms,
+                        double* max_ms) {
+  if (!g || !count || !total_ms) return fail(MM_ERR_INVALID_ARG, "null argument");
+  if (!g->timing) return fail(MM_ERR_UNSUPPORTED, "handle was created without MM_TIMING");
+  TimingRing& r = *g->timing;
+  const int64_t have = r.recorded < TimingRing::kCap ? r.recorded : TimingRing::kCap;
+  double tot = 0.0, lo = 0.0, hi = 0.0;
+  for (int64_t k = r.recorded - have; k < r.recorded; ++k) {
+    const int slot = (int)(k % TimingRing::kCap);
+    HIP_TRY(hipEventSynchronize(r.ev[2 * slot + 1]));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, r.ev[2 * slot], r.ev[2 * slot + 1]));
+    tot += ms;
+    if (k == r.recorded - have || ms < lo) lo = ms;
+    if (k == r.recorded - have || ms > hi) hi = ms;
+  }
+  r.recorded = 0;
+  *count = have;
+  *total_ms = tot;
+  if (min_ms) *min_ms = lo;
+  if (max_ms) *max_ms = hi;
+  return MM_OK;
+}
+
+void mm_destroy(mm_handle g) {
+  if (!g) return;
+  if (g->timing) {
+    g->timing->destroy();
+    delete g->timing;
+  }
+  delete g;
+}
+
+}  // extern "C"

@@ -1,0 +1,112 @@
+"""The C-ABI library loads and exports every entry point of include/mm.h;
+host-side argument checks return their documented status codes (no GPU call
+is made before these checks)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2507_04420_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "mm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^[A-Za-z_][\w\s\*]*?\b(mm_\w+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_expected_entry_points():
+    names = declared_functions()
+    for must in ("mm_create", "mm_run", "mm_destroy", "mm_workspace_bytes", "mm_last_error"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.load()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert set(declared_functions()) == set(_lib.SIGNATURES)
+
+
+def test_version_and_defaults():
+    lib = _lib.load()
+    assert lib.mm_version().startswith(b"skipper-gfx950")
+    t = _lib.mm_tuning()
+    lib.mm_default_tuning(ctypes.byref(t))
+    assert t.layout == _lib.MM_LAYOUT_U8 and t.wg_size % 64 == 0 and t.wave_vertices % 64 == 0
+
+
+def test_workspace_bytes():
+    lib = _lib.load()
+    t = _lib.mm_tuning()
+    lib.mm_default_tuning(ctypes.byref(t))
+    small = lib.mm_workspace_bytes(0, ctypes.byref(t))
+    big = lib.mm_workspace_bytes(1 << 20, ctypes.byref(t))
+    assert small > 0 and big >= small + (1 << 20) // 4 * 4
+    assert lib.mm_workspace_bytes(-1, ctypes.byref(t)) == 0
+    assert lib.mm_workspace_bytes(1 << 31, ctypes.byref(t)) == 0
+    t.layout = _lib.MM_LAYOUT_U32
+    assert lib.mm_workspace_bytes(1 << 20, ctypes.byref(t)) == small
+    t.wg_size = 100
+    assert lib.mm_workspace_bytes(10, ctypes.byref(t)) == 0
+
+
+def _create(lib, **kw):
+    args = dict(off=ctypes.c_void_p(0x1000), off_type=_lib.MM_OFF_I64, nbr=ctypes.c_void_p(0x2000),
+                n=10, m=20, ws=ctypes.c_void_p(0x100000), ws_bytes=1 << 20, flags=0, tuning=None)
+    args.update(kw)
+    h = ctypes.c_void_p()
+    st = lib.mm_create(args["off"], args["off_type"], args["nbr"], args["n"], args["m"], args["ws"],
+                       args["ws_bytes"], args["flags"], args["tuning"], None, ctypes.byref(h))
+    return st, h
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(off=None), _lib.MM_ERR_INVALID_ARG),
+    (dict(nbr=None), _lib.MM_ERR_INVALID_ARG),
+    (dict(ws=None), _lib.MM_ERR_INVALID_ARG),
+    (dict(ws=ctypes.c_void_p(0x100004)), _lib.MM_ERR_INVALID_ARG),
+    (dict(n=-1), _lib.MM_ERR_INVALID_ARG),
+    (dict(n=1 << 31), _lib.MM_ERR_INVALID_ARG),
+    (dict(m=-5), _lib.MM_ERR_INVALID_ARG),
+    (dict(off_type=_lib.MM_OFF_I32, m=1 << 31), _lib.MM_ERR_INVALID_ARG),
+    (dict(off_type=7), _lib.MM_ERR_INVALID_ARG),
+    (dict(flags=0x80), _lib.MM_ERR_INVALID_ARG),
+    (dict(ws_bytes=16), _lib.MM_ERR_OUT_OF_MEMORY),
+])
+def test_create_argument_errors(kw, status):
+    lib = _lib.load()
+    st, h = _create(lib, **kw)
+    assert st == status
+    assert not h.value
+    assert lib.mm_last_error()
+
+
+def test_create_bad_tuning():
+    lib = _lib.load()
+    t = _lib.mm_tuning()
+    lib.mm_default_tuning(ctypes.byref(t))
+    t.wave_vertices = 100
+    st, _ = _create(lib, tuning=ctypes.pointer(t))
+    assert st == _lib.MM_ERR_INVALID_ARG
+    assert b"wave_vertices" in lib.mm_last_error()
+
+
+def test_null_handle_calls():
+    lib = _lib.load()
+    assert lib.mm_run(None, None, None) == _lib.MM_ERR_INVALID_ARG
+    assert lib.mm_sync(None, None) == _lib.MM_ERR_INVALID_ARG
+    assert lib.mm_reset_stats(None, None) == _lib.MM_ERR_INVALID_ARG
+    s = _lib.mm_stats()
+    assert lib.mm_get_stats(None, None, ctypes.byref(s)) == _lib.MM_ERR_INVALID_ARG
+    lib.mm_destroy(None)
+
+
+def test_error_raises_python_exception():
+    with pytest.raises(_lib.MMError) as ei:
+        _lib.check(_lib.MM_ERR_INVALID_ARG)
+    assert ei.value.status == _lib.MM_ERR_INVALID_ARG

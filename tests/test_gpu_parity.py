@@ -1,0 +1,280 @@
+"""GPU parity: the HIP library against the oracle, through the C ABI.
+
+Several maximal matchings are correct and the method is non-deterministic
+(Section V-C), so parity means:
+  * the exact checker finds zero violations of every class;
+  * where the maximal matching is unique (disjoint edges, empty, isolated,
+    loop-only graphs) the mate arrays are equal element by element;
+  * where every maximal matching has the same size (cliques, K_{a,b}, stars)
+    the sizes are equal;
+  * on graphs with at most 12 vertices the output is one of the maximal
+    matchings found by brute-force enumeration;
+  * the size is reported beside SGMM's and is at least half of it (a maximal
+    matching has at least half the pairs of any matching).
+"""
+import itertools
+import random
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2507_04420_amd as mm  # noqa: E402
+from paper_2507_04420_amd import _lib  # noqa: E402
+
+TUNINGS = {
+    "u8_lazy": mm.Tuning(),
+    "u8_eager": mm.Tuning(lazy_init=0),
+    "u32": mm.Tuning(layout=_lib.MM_LAYOUT_U32, lazy_init=0),
+    "u8_disperse": mm.Tuning(disperse=1),
+    "u8_small_blocks": mm.Tuning(wg_size=64, wave_vertices=64, assist_after=2),
+    "u32_no_assist": mm.Tuning(layout=_lib.MM_LAYOUT_U32, lazy_init=0, assist_after=0),
+}
+
+
+def to_dev(csr):
+    return torch.from_numpy(np.ascontiguousarray(csr.off)).cuda(), torch.from_numpy(
+        np.ascontiguousarray(csr.nbr)).cuda()
+
+
+def gpu_match(csr, tuning=None, symmetric=True, stats=False, validate=True):
+    off, nbr = to_dev(csr)
+    g = mm.Graph(off, nbr, symmetric=symmetric, validate=validate, tuning=tuning, stats=stats)
+    out = g.run()
+    g.sync()
+    mate = out.cpu().numpy()
+    st = g.stats() if stats else None
+    g.close()
+    return mate, st
+
+
+def assert_parity(csr, mate, exact=None, same_size_as=None):
+    c = oracle.check(csr, mate)
+    assert c.violations == 0, c
+    assert c.bad_input == 0
+    r = oracle.sgmm(csr)
+    assert 2 * c.size >= r.pairs, (c.size, r.pairs)
+    if exact is not None:
+        np.testing.assert_array_equal(mate, exact)
+    if same_size_as is not None:
+        assert c.size == same_size_as
+    return c
+
+
+def pairs_of(mate):
+    return sorted((int(a), int(b)) for a, b in enumerate(mate) if b > a)
+
+
+@pytest.fixture(params=sorted(TUNINGS))
+def tuning(request):
+    return TUNINGS[request.param]
+
+
+# ---------------------------------------------------------------- small graphs
+
+def test_fig6_worked_example(tuning):
+    g = graphgen.from_edges(4, [(0, 1), (0, 2), (0, 3), (1, 2), (2, 3)])
+    mate, _ = gpu_match(g, tuning)
+    assert_parity(g, mate)
+    assert pairs_of(mate) in ([(0, 2)], [(0, 1), (2, 3)], [(0, 3), (1, 2)])
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 64, 65, 1000])
+def test_path(tuning, k):
+    g = graphgen.from_edges(k, [(i, i + 1) for i in range(k - 1)] or np.zeros((0, 2)))
+    mate, _ = gpu_match(g, tuning)
+    c = assert_parity(g, mate)
+    assert (k - 1 + 2) // 3 <= c.size <= k // 2
+
+
+@pytest.mark.parametrize("k", [1, 5, 63, 64, 65, 5000])
+def test_star(tuning, k):
+    g = graphgen.from_edges(k + 1, [(0, j) for j in range(1, k + 1)])
+    mate, _ = gpu_match(g, tuning)
+    assert_parity(g, mate, same_size_as=1)
+
+
+@pytest.mark.parametrize("n", [2, 3, 17, 64, 130])
+def test_clique(tuning, n):
+    g = graphgen.from_edges(n, list(itertools.combinations(range(n), 2)))
+    mate, _ = gpu_match(g, tuning)
+    assert_parity(g, mate, same_size_as=n // 2)
+
+
+@pytest.mark.parametrize("a,b", [(1, 1), (3, 70), (70, 3), (64, 64), (100, 37)])
+def test_complete_bipartite(tuning, a, b):
+    g = graphgen.from_edges(a + b, [(i, a + j) for i in range(a) for j in range(b)])
+    mate, _ = gpu_match(g, tuning)
+    assert_parity(g, mate, same_size_as=min(a, b))
+
+
+@pytest.mark.parametrize("k", [1, 64, 1000, 4099])
+def test_disjoint_edges_bitwise(tuning, k):
+    g = graphgen.from_edges(2 * k, [(2 * i, 2 * i + 1) for i in range(k)])
+    exact = np.arange(2 * k, dtype=np.int32) ^ 1
+    mate, _ = gpu_match(g, tuning)
+    assert_parity(g, mate, exact=exact)
+
+
+def test_empty_isolated_loops(tuning):
+    for n in (1, 63, 64, 65, 3000):
+        g = graphgen.from_edges(n, np.zeros((0, 2)))
+        mate, _ = gpu_match(g, tuning)
+        assert_parity(g, mate, exact=np.full(n, -1, dtype=np.int32))
+    g = graphgen.from_edges(130, [(v, v) for v in range(0, 130, 3)], symmetric=False)
+    mate, _ = gpu_match(g, tuning)
+    assert_parity(g, mate, exact=np.full(130, -1, dtype=np.int32))
+
+
+def test_zero_vertices():
+    off = torch.zeros(1, dtype=torch.int64, device="cuda")
+    nbr = torch.zeros(0, dtype=torch.int32, device="cuda")
+    g = mm.Graph(off, nbr, symmetric=True, validate=True)
+    out = g.run()
+    g.sync()
+    assert out.numel() == 0
+
+
+@pytest.mark.parametrize("seed", range(30))
+def test_random_small_in_bruteforce_set(seed):
+    rng = random.Random(1000 + seed)
+    n = rng.randint(2, 12)
+    p = rng.choice([0.2, 0.4, 0.7])
+    edges = [e for e in itertools.combinations(range(n), 2) if rng.random() < p]
+    g = graphgen.from_edges(n, edges if edges else np.zeros((0, 2)))
+    mset = {tuple(m) for m in oracle.enumerate_matchings(g)}
+    for name in sorted(TUNINGS):
+        mate, _ = gpu_match(g, TUNINGS[name])
+        assert tuple(mate) in mset, (name, pairs_of(mate))
+
+
+# ---------------------------------------------------------------- mid-size, ragged, skewed
+
+@pytest.mark.parametrize("seed", [1, 2, 3, 4, 5])
+def test_er_65536_deg16(tuning, seed):
+    g = graphgen.er(65536, 16, seed=seed)
+    mate, _ = gpu_match(g, tuning)
+    assert_parity(g, mate)
+
+
+def test_er_int32_offsets(tuning):
+    g = graphgen.er(65536, 16, seed=11).with_int32_offsets()
+    mate, _ = gpu_match(g, tuning)
+    assert_parity(g, mate)
+
+
+@pytest.mark.parametrize("n", [100_003, 4097, 1025])
+def test_er_ragged(tuning, n):
+    g = graphgen.er(n, 9, seed=n)
+    mate, _ = gpu_match(g, tuning)
+    assert_parity(g, mate)
+
+
+@pytest.mark.parametrize("scale", [12, 16, 18])
+def test_rmat(tuning, scale):
+    g = graphgen.rmat(scale, seed=scale)
+    mate, _ = gpu_match(g, tuning)
+    assert_parity(g, mate)
+
+
+@pytest.mark.parametrize("H,W", [(1, 1), (7, 9), (301, 517), (1024, 1024)])
+def test_grid(tuning, H, W):
+    g = graphgen.grid(H, W)
+    mate, _ = gpu_match(g, tuning)
+    assert_parity(g, mate)
+
+
+def test_non_symmetric_input(tuning):
+    # Section V-C: each edge stored in one endpoint's list only; the result must
+    # be maximal for the union (no lazy output is used for such input)
+    rng = np.random.default_rng(5)
+    n = 20000
+    e = rng.integers(0, n, size=(120000, 2))
+    g = graphgen.from_edges(n, e, symmetric=False)
+    mate, _ = gpu_match(g, tuning, symmetric=False)
+    assert_parity(g, mate)
+
+
+def test_duplicates_and_loops(tuning):
+    rng = np.random.default_rng(9)
+    n = 5000
+    e = rng.integers(0, n, size=(40000, 2))
+    e = np.concatenate([e, e[:5000], np.stack([np.arange(n)] * 2, 1)])
+    g = graphgen.from_edges(n, e, symmetric=True, dedup=False, sort=False)
+    mate, _ = gpu_match(g, tuning)
+    assert_parity(g, mate)
+
+
+# ---------------------------------------------------------------- contention
+
+@pytest.mark.parametrize("rep", range(3))
+def test_contention_star_and_clique(rep):
+    for name in sorted(TUNINGS):
+        t = TUNINGS[name]
+        g = graphgen.from_edges(200_001, [(0, j) for j in range(1, 200_001)])
+        mate, _ = gpu_match(g, t)
+        assert_parity(g, mate, same_size_as=1)
+        g = graphgen.from_edges(600, list(itertools.combinations(range(600), 2)))
+        mate, _ = gpu_match(g, t)
+        assert_parity(g, mate, same_size_as=300)
+
+
+def test_contention_unpermuted_rmat(tuning):
+    g = graphgen.rmat(16, seed=3, permute=False)
+    mate, _ = gpu_match(g, tuning)
+    assert_parity(g, mate)
+
+
+# ---------------------------------------------------------------- handle behaviour
+
+def test_repeated_runs_same_handle(tuning):
+    g = graphgen.rmat(15, seed=7)
+    off, nbr = to_dev(g)
+    h = mm.Graph(off, nbr, symmetric=True, tuning=tuning)
+    for _ in range(4):
+        out = h.run()
+        h.sync()
+        assert_parity(g, out.cpu().numpy())
+
+
+def test_stats_consistent():
+    g = graphgen.rmat(16, seed=1)
+    mate, st = gpu_match(g, mm.Tuning(), stats=True)
+    c = assert_parity(g, mate)
+    assert st["pairs"] == c.size
+    assert st["sources"] == g.n
+    assert st["touched"] <= g.m
+    assert st["match_attempts"] >= st["pairs"]
+
+
+def test_validate_rejects_bad_graph():
+    off = torch.tensor([0, 2, 3], dtype=torch.int64, device="cuda")
+    nbr = torch.tensor([1, 7, 0], dtype=torch.int32, device="cuda")
+    with pytest.raises(mm.MMError) as ei:
+        mm.Graph(off, nbr, validate=True)
+    assert ei.value.status == _lib.MM_ERR_INVALID_GRAPH
+    off = torch.tensor([0, 2, 1, 3], dtype=torch.int64, device="cuda")
+    nbr = torch.tensor([1, 2, 0], dtype=torch.int32, device="cuda")
+    with pytest.raises(mm.MMError):
+        mm.Graph(off, nbr, validate=True)
+
+
+def test_loop_budget_reports_no_progress():
+    # A one-trip budget cannot finish a clique; every wavefront still exits
+    # normally and the failure surfaces at sync.
+    g = graphgen.from_edges(300, list(itertools.combinations(range(300), 2)))
+    off, nbr = to_dev(g)
+    h = mm.Graph(off, nbr, symmetric=True, tuning=mm.Tuning(iter_cap=1))
+    h.run()
+    with pytest.raises(mm.MMError) as ei:
+        h.sync()
+    assert ei.value.status == _lib.MM_ERR_NO_PROGRESS
+    h2 = mm.Graph(off, nbr, symmetric=True)
+    out = h2.run()
+    h2.sync()
+    assert_parity(g, out.cpu().numpy(), same_size_as=150)
