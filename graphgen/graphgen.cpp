@@ -19,9 +19,10 @@
 //     networks", Phys. Rev. E 71, 2005).
 //   * R-MAT (Chakrabarti, Zhan and Faloutsos, SDM 2004): each sample descends
 //     `scale` levels of the adjacency matrix, picking a quadrant with
-//     probabilities (a, b, c, 1-a-b-c); no per-level noise. Vertex ids are then
-//     relabelled by a keyed bijection (a Feistel network on the id bits with
-//     cycle walking), which is a seeded pseudo-random permutation.
+//     probabilities (a, b, c, 1-a-b-c), resolved to 1/65536; no per-level
+//     noise. Vertex ids are then relabelled by a keyed bijection (a Feistel
+//     network on the id bits with cycle walking), a seeded pseudo-random
+//     permutation.
 //   * The 4-neighbour 2D grid, row-major ids, neighbour lists in ascending id
 //     order (up, left, right, down).
 //   * Mixtures of the three, concatenated into one CSR with global int64
@@ -60,6 +61,7 @@ inline double unit_open0(uint64_t r) {
 
 // Keyed bijection on [0, 2^bits): a 4-round balanced Feistel network on
 // 2*ceil(bits/2) bits, cycle-walked back into the domain when bits is odd.
+// Round function: a keyed multiply-xorshift of the right half.
 struct Relabel {
   int half;
   uint64_t hmask, dom;
@@ -68,13 +70,14 @@ struct Relabel {
     half = (bits + 1) / 2;
     hmask = (half >= 64) ? ~0ULL : ((1ULL << half) - 1);
     dom = 1ULL << bits;
-    for (int r = 0; r < 4; ++r) key[r] = stream_key(seed, 0x7e1abe1ULL + r);
+    for (int r = 0; r < 4; ++r) key[r] = stream_key(seed, 0x7e1abe1ULL + r) | 1ULL;
   }
   uint64_t once(uint64_t x) const {
     uint64_t l = x >> half, r = x & hmask;
     for (int k = 0; k < 4; ++k) {
-      uint64_t f = sm64_mix(r ^ key[k]) & hmask;
-      uint64_t nl = r, nr = l ^ f;
+      uint64_t f = (r ^ key[k]) * 0x9e3779b97f4a7c15ULL;
+      f = ((f ^ (f >> 29)) * key[k]) >> 23;
+      const uint64_t nl = r, nr = (l ^ f) & hmask;
       l = nl;
       r = nr;
     }
@@ -165,11 +168,14 @@ gg_csr* build_symmetric(int64_t n, const Sampler& s, int64_t nchunks, int nt) {
   return g;
 }
 
+// R-MAT sample k draws 16 bits per level from the counter-based generator
+// (four levels per 64-bit draw), so quadrant probabilities are resolved to
+// 1/65536.
 struct RmatSampler {
   int scale;
   int64_t samples;
   int64_t chunk;
-  uint32_t ta, tab, tabc;  // cumulative quadrant thresholds on 32-bit draws
+  uint32_t ta, tab, tabc;  // cumulative quadrant thresholds on 16-bit draws
   uint64_t key;
   bool permute;
   Relabel rel;
@@ -177,8 +183,9 @@ struct RmatSampler {
       : scale(scale_), samples(samples_), chunk(1 << 16), key(stream_key(seed, 0x12a7ULL)),
         permute(perm), rel(scale_, seed) {
     auto th = [](double p) {
-      double x = p * 4294967296.0;
-      if (x >= 4294967295.0) return 0xffffffffu;
+      double x = std::floor(p * 65536.0 + 0.5);
+      if (x < 0) x = 0;
+      if (x > 65536.0) x = 65536.0;
       return static_cast<uint32_t>(x);
     };
     ta = th(a);
@@ -191,21 +198,15 @@ struct RmatSampler {
     int64_t lo = ci * chunk, hi = std::min(samples, lo + chunk);
     for (int64_t k = lo; k < hi; ++k) {
       uint64_t u = 0, v = 0;
-      uint64_t ctr = static_cast<uint64_t>(k) * 16;
+      uint64_t ctr = static_cast<uint64_t>(k) * 8;
       uint64_t r = 0;
       for (int lvl = 0; lvl < scale; ++lvl) {
-        uint32_t q;
-        if ((lvl & 1) == 0) {
-          r = draw(key, ctr++);
-          q = static_cast<uint32_t>(r);
-        } else {
-          q = static_cast<uint32_t>(r >> 32);
-        }
-        uint64_t bu, bv;
-        if (q < ta) { bu = 0; bv = 0; }
-        else if (q < tab) { bu = 0; bv = 1; }
-        else if (q < tabc) { bu = 1; bv = 0; }
-        else { bu = 1; bv = 1; }
+        if ((lvl & 3) == 0) r = draw(key, ctr++);
+        const uint32_t q = static_cast<uint32_t>(r & 0xffffu);
+        r >>= 16;
+        // quadrant (0,0) below a, (0,1) below a+b, (1,0) below a+b+c, else (1,1)
+        const uint64_t bu = q >= tab;
+        const uint64_t bv = (q >= ta) & ((q < tab) | (q >= tabc));
         u = (u << 1) | bu;
         v = (v << 1) | bv;
       }

@@ -62,9 +62,15 @@ typedef enum {
   /* One state byte per vertex, four per 32-bit word; byte transitions use
      32-bit atomics on the containing word. The mate array is separate. */
   MM_LAYOUT_U8 = 0,
-  /* One 32-bit word per vertex that is also the output: -1 accessible,
-     -2 reserved, >= 0 matched (the word holds the mate). */
-  MM_LAYOUT_U32 = 1
+  /* One 32-bit word per vertex that is also the output: matched = the mate
+     (>= 0); accessible and reserved are two reserved values (-1 and -2 with
+     MM_PROTOCOL_CAS; INT32_MAX and INT32_MAX-1 with MM_PROTOCOL_TWO_PHASE, so
+     that reserving is an atomic min). */
+  MM_LAYOUT_U32 = 1,
+  /* Two state bits per vertex, sixteen per 32-bit word, same field encoding
+     and atomics as MM_LAYOUT_U8 (a denser copy of it, so that neighbour-state
+     reads hit the 4 MB per-XCD L2 more often). The mate array is separate. */
+  MM_LAYOUT_U2 = 2
 } mm_layout;
 
 /* Creation flags. */
@@ -76,10 +82,23 @@ enum {
   MM_TIMING = 8u      /* record HIP events around each sweep launch (mm_get_timing) */
 };
 
+/* How the higher endpoint v of an edge is taken (Algorithm 1, L13-14). */
+typedef enum {
+  /* As printed: one CAS moves v from accessible to matched. */
+  MM_PROTOCOL_CAS = 0,
+  /* v is reserved like u (fetch-or / atomic-min, no CAS), then both are marked
+     matched by the holder. Same state transitions (Fig. 4), same id order. */
+  MM_PROTOCOL_TWO_PHASE = 1
+} mm_protocol;
+
 /* Launch and layout parameters. None of them changes what a correct result
    is; they change only speed. Fill with mm_default_tuning() first. */
 typedef struct {
   int32_t layout;        /* mm_layout */
+  int32_t protocol;      /* mm_protocol */
+  int32_t hint;          /* 1: skip matched neighbours by a one-bit-per-vertex
+                            "matched" hint (set after a vertex is matched)
+                            instead of reading its state */
   int32_t wg_size;       /* threads per workgroup: 64, 128, 192 or 256 */
   int32_t wave_vertices; /* source vertices handed to one wavefront, >= 64, multiple of 64 */
   int32_t disperse;      /* 0: a wavefront's lanes take consecutive sources;
@@ -87,8 +106,11 @@ typedef struct {
                             wave_vertices/64 apart (for high-locality graphs) */
   int32_t assist_after;  /* scan steps after which the wavefront helps a lane's
                             long scan 64 entries at a time; <= 0 disables */
-  int32_t lazy_init;     /* 1: mate entries written by the sweep itself instead of
-                            a separate -1 fill (needs MM_SYMMETRIC and MM_LAYOUT_U8) */
+  int32_t lazy_init;     /* 1: unmatched outputs written by the sweep itself instead
+                            of a separate fill (needs MM_SYMMETRIC; not with
+                            MM_LAYOUT_U32 + MM_PROTOCOL_CAS, where it is implicit) */
+  int32_t scan_width;    /* neighbour ids a lane reads per scan step: 1..8 */
+  int32_t reserved_;     /* must be 0 */
   int64_t iter_cap;      /* loop-trip budget per wavefront; 0 = default of
                             65536 + 8 x (neighbour entries of its block);
                             exceeding it raises MM_ERR_NO_PROGRESS */

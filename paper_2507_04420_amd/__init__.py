@@ -30,11 +30,15 @@ def version() -> str:
 class Tuning:
     """Launch and layout parameters (see mm_tuning in include/mm.h)."""
     layout: int = _lib.MM_LAYOUT_U8
+    protocol: int = _lib.MM_PROTOCOL_CAS
+    hint: int = 0
     wg_size: int = 256
     wave_vertices: int = 1024
     disperse: int = 0
     assist_after: int = 16
     lazy_init: int = 1
+    scan_width: int = 4
+    reserved_: int = 0
     iter_cap: int = 0
 
     @classmethod

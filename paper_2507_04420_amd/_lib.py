@@ -28,18 +28,23 @@ STATUS_NAMES = {
 }
 
 MM_OFF_I32, MM_OFF_I64 = 0, 1
-MM_LAYOUT_U8, MM_LAYOUT_U32 = 0, 1
+MM_LAYOUT_U8, MM_LAYOUT_U32, MM_LAYOUT_U2 = 0, 1, 2
+MM_PROTOCOL_CAS, MM_PROTOCOL_TWO_PHASE = 0, 1
 MM_VALIDATE, MM_SYMMETRIC, MM_STATS, MM_TIMING = 1, 2, 4, 8
 
 
 class mm_tuning(ctypes.Structure):
     _fields_ = [
         ("layout", ctypes.c_int32),
+        ("protocol", ctypes.c_int32),
+        ("hint", ctypes.c_int32),
         ("wg_size", ctypes.c_int32),
         ("wave_vertices", ctypes.c_int32),
         ("disperse", ctypes.c_int32),
         ("assist_after", ctypes.c_int32),
         ("lazy_init", ctypes.c_int32),
+        ("scan_width", ctypes.c_int32),
+        ("reserved_", ctypes.c_int32),
         ("iter_cap", ctypes.c_int64),
     ]
 

@@ -17,6 +17,11 @@ inline size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 // Validates a tuning struct (wg_size, wave_vertices, layout, flags ranges).
 mm_status check_tuning(const mm_tuning& t);
 
+// Workspace pieces after the control block: packed states (U8 layout only),
+// then the matched hint (if enabled), each rounded to 256 bytes.
+size_t state_bytes(int64_t n, const mm_tuning& t);
+size_t hint_bytes(int64_t n, const mm_tuning& t);
+
 // Control block at the start of every workspace: error word at 0, counters
 // at kStatsOffset, a work-queue counter at kQueueOffset.
 constexpr size_t kCtrlBytes = 4096;

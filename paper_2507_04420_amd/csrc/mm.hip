@@ -38,8 +38,11 @@ mm_status fail(mm_status s, const char* fmt, ...) {
 }
 
 mm_status check_tuning(const mm_tuning& t) {
-  if (t.layout != MM_LAYOUT_U8 && t.layout != MM_LAYOUT_U32)
-    return fail(MM_ERR_INVALID_ARG, "tuning.layout must be MM_LAYOUT_U8 or MM_LAYOUT_U32");
+  if (t.layout != MM_LAYOUT_U8 && t.layout != MM_LAYOUT_U32 && t.layout != MM_LAYOUT_U2)
+    return fail(MM_ERR_INVALID_ARG, "tuning.layout must be MM_LAYOUT_U8, MM_LAYOUT_U32 or MM_LAYOUT_U2");
+  if (t.protocol != MM_PROTOCOL_CAS && t.protocol != MM_PROTOCOL_TWO_PHASE)
+    return fail(MM_ERR_INVALID_ARG, "tuning.protocol must be MM_PROTOCOL_CAS or MM_PROTOCOL_TWO_PHASE");
+  if (t.hint != 0 && t.hint != 1) return fail(MM_ERR_INVALID_ARG, "tuning.hint must be 0 or 1");
   if (t.wg_size < 64 || t.wg_size > 256 || t.wg_size % 64)
     return fail(MM_ERR_INVALID_ARG, "tuning.wg_size must be 64, 128, 192 or 256 (got %d)",
                 t.wg_size);
@@ -49,8 +52,21 @@ mm_status check_tuning(const mm_tuning& t) {
     return fail(MM_ERR_INVALID_ARG, "tuning.disperse must be 0 or 1");
   if (t.lazy_init != 0 && t.lazy_init != 1)
     return fail(MM_ERR_INVALID_ARG, "tuning.lazy_init must be 0 or 1");
+  if (t.scan_width < 1 || t.scan_width > kMaxW)
+    return fail(MM_ERR_INVALID_ARG, "tuning.scan_width must be in [1, %d]", kMaxW);
+  if (t.reserved_ != 0) return fail(MM_ERR_INVALID_ARG, "tuning.reserved_ must be 0");
   if (t.iter_cap < 0) return fail(MM_ERR_INVALID_ARG, "tuning.iter_cap must be >= 0");
   return MM_OK;
+}
+
+size_t state_bytes(int64_t n, const mm_tuning& t) {
+  if (t.layout == MM_LAYOUT_U8) return round_up((size_t)((n + 3) / 4) * 4, 256);
+  if (t.layout == MM_LAYOUT_U2) return round_up((size_t)((n + 15) / 16) * 4, 256);
+  return 0;
+}
+
+size_t hint_bytes(int64_t n, const mm_tuning& t) {
+  return t.hint ? round_up((size_t)((n + 31) / 32) * 4, 256) : 0;
 }
 
 }  // namespace mmi
@@ -73,6 +89,15 @@ __global__ void fill_u32_kernel(uint32_t* __restrict__ p, int64_t words, uint32_
   for (int64_t j = (quads << 2) + t; j < words; j += stride) p[j] = value;
 }
 
+// Rewrites every word equal to `from` as `to` (word layout, two-phase
+// encoding, without lazy output: vertices left accessible become -1).
+__global__ void replace_u32_kernel(uint32_t* __restrict__ p, int64_t words, uint32_t from,
+                                   uint32_t to) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < words; j += stride)
+    if (p[j] == from) p[j] = to;
+}
+
 // CSR well-formedness (checked at create with MM_VALIDATE). Bits of *flags:
 // 1 offsets[0] != 0 or offsets[n] != m; 2 offsets decrease; 4 neighbour out
 // of range.
@@ -93,31 +118,26 @@ __global__ void validate_kernel(const OffT* __restrict__ off, const int32_t* __r
 }
 
 // One graph: wavefront w sweeps sources [w * wave_vertices, ...).
-template <typename OffT, class Layout, bool LAZY, bool STATS>
+template <typename OffT, class Layout, bool HINT, bool LAZY, bool STATS>
 __global__ __launch_bounds__(256) void sweep_kernel(SweepParams p, const OffT* __restrict__ off,
                                                    const int32_t* __restrict__ nbr, int64_t n,
-                                                   Layout L, int32_t* __restrict__ mate,
-                                                   unsigned long long* stats) {
+                                                   Layout L, unsigned long long* stats) {
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t vb = wave * p.wave_vertices;
   if (vb >= n) return;
   const int64_t nv = (n - vb < p.wave_vertices) ? (n - vb) : p.wave_vertices;
   Counters<STATS> cnt;
-  sweep_block<OffT, Layout, LAZY, STATS>(p, off, nbr, L, mate, vb, nv, cnt);
+  sweep_block<OffT, Layout, HINT, LAZY, STATS>(p, off, nbr, L, vb, nv, cnt);
   if (STATS) cnt.flush(stats);
 }
 
 // ---------------------------------------------------------------- helpers
 
-int fill_grid(int64_t words) {
+int grid_for(int64_t words) {
   int64_t blocks = (words / 4 + 255) / 256;
   if (blocks < 1) blocks = 1;
   if (blocks > 8192) blocks = 8192;
   return (int)blocks;
-}
-
-size_t state_bytes(int64_t n, const mm_tuning& t) {
-  return t.layout == MM_LAYOUT_U8 ? round_up((size_t)((n + 3) / 4) * 4, 256) : 0;
 }
 
 }  // namespace
@@ -127,13 +147,11 @@ struct TimingRing {
   static constexpr int kCap = 512;
   hipEvent_t ev[2 * kCap] = {};
   int64_t recorded = 0;  // launches recorded since the last read
-  bool ready = false;
   hipError_t init() {
     for (int i = 0; i < 2 * kCap; ++i) {
       hipError_t e = hipEventCreate(&ev[i]);
       if (e != hipSuccess) return e;
     }
-    ready = true;
     return hipSuccess;
   }
   void destroy() {
@@ -153,13 +171,116 @@ struct mm_graph {
   size_t ws_bytes;
   uint32_t flags;
   mm_tuning tun;
+  bool lazy;  // effective lazy output
   int device;
   TimingRing* timing;
+  uint32_t* st() const { return reinterpret_cast<uint32_t*>(ws + kCtrlBytes); }
+  uint32_t* hint() const {
+    return tun.hint ? reinterpret_cast<uint32_t*>(ws + kCtrlBytes + mmi::state_bytes(n, tun))
+                    : nullptr;
+  }
 };
+
+namespace {
+
+SweepParams make_params(const mm_graph* g) {
+  SweepParams p;
+  p.wave_vertices = g->tun.wave_vertices;
+  p.disperse = g->tun.disperse;
+  p.assist_after = g->tun.assist_after;
+  p.scan_width = g->tun.scan_width;
+  p.iter_cap = g->tun.iter_cap;
+  p.err = reinterpret_cast<uint32_t*>(g->ws);
+  return p;
+}
+
+template <typename OffT, class Layout, bool HINT, bool LAZY, bool STATS>
+hipError_t launch_sweep(const mm_graph* g, const Layout& L, hipStream_t s) {
+  const SweepParams p = make_params(g);
+  unsigned long long* stats = reinterpret_cast<unsigned long long*>(g->ws + kStatsOffset);
+  const int64_t waves = (g->n + p.wave_vertices - 1) / p.wave_vertices;
+  const int wpb = g->tun.wg_size / 64;
+  const int64_t blocks = (waves + wpb - 1) / wpb;
+  if (blocks == 0) return hipSuccess;
+  if (g->timing) {
+    hipError_t e = hipEventRecord(g->timing->before(), s);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((sweep_kernel<OffT, Layout, HINT, LAZY, STATS>), dim3((unsigned)blocks),
+                     dim3(g->tun.wg_size), 0, s, p, static_cast<const OffT*>(g->off), g->nbr, g->n,
+                     L, stats);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (g->timing) {
+    e = hipEventRecord(g->timing->after(), s);
+    ++g->timing->recorded;
+  }
+  return e;
+}
+
+template <typename OffT, class Layout, bool STATS>
+hipError_t dispatch_flags(const mm_graph* g, const Layout& L, hipStream_t s) {
+  const bool hint = g->tun.hint != 0;
+  if constexpr (Layout::kStateIsMate && !Layout::kTwoPhase) {
+    // ACC is already the output value -1: no lazy output is needed.
+    return hint ? launch_sweep<OffT, Layout, true, false, STATS>(g, L, s)
+                : launch_sweep<OffT, Layout, false, false, STATS>(g, L, s);
+  } else {
+    if (hint)
+      return g->lazy ? launch_sweep<OffT, Layout, true, true, STATS>(g, L, s)
+                     : launch_sweep<OffT, Layout, true, false, STATS>(g, L, s);
+    return g->lazy ? launch_sweep<OffT, Layout, false, true, STATS>(g, L, s)
+                   : launch_sweep<OffT, Layout, false, false, STATS>(g, L, s);
+  }
+}
+
+void fill(uint32_t* p, int64_t words, uint32_t value, hipStream_t s) {
+  if (words > 0)
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(words)), dim3(256), 0, s, p, words, value);
+}
+
+template <typename OffT, bool STATS>
+hipError_t run_typed(const mm_graph* g, int32_t* mate, hipStream_t s) {
+  const int64_t n = g->n;
+  uint32_t* mate_w = reinterpret_cast<uint32_t*>(mate);
+  Hint hint{g->hint()};
+  if (hint.bits) fill(hint.bits, (n + 31) / 32, 0u, s);
+  const bool two = g->tun.protocol == MM_PROTOCOL_TWO_PHASE;
+  hipError_t e;
+  if (g->tun.layout == MM_LAYOUT_U32) {
+    if (two) {
+      fill(mate_w, n, LayoutU32<true>::kAcc, s);
+      e = dispatch_flags<OffT, LayoutU32<true>, STATS>(g, LayoutU32<true>{mate, hint}, s);
+      if (e == hipSuccess && !g->lazy) {
+        hipLaunchKernelGGL(replace_u32_kernel, dim3(grid_for(n)), dim3(256), 0, s, mate_w, n,
+                           LayoutU32<true>::kAcc, 0xffffffffu);
+        e = hipGetLastError();
+      }
+      return e;
+    }
+    fill(mate_w, n, LayoutU32<false>::kAcc, s);
+    return dispatch_flags<OffT, LayoutU32<false>, STATS>(g, LayoutU32<false>{mate, hint}, s);
+  }
+  if (!g->lazy) fill(mate_w, n, 0xffffffffu, s);
+  if (g->tun.layout == MM_LAYOUT_U2) {
+    fill(g->st(), (n + 15) / 16, 0u, s);
+    using L2T = LayoutPacked<2, true>;
+    using L2C = LayoutPacked<2, false>;
+    if (two) return dispatch_flags<OffT, L2T, STATS>(g, L2T{g->st(), mate, hint}, s);
+    return dispatch_flags<OffT, L2C, STATS>(g, L2C{g->st(), mate, hint}, s);
+  }
+  fill(g->st(), (n + 3) / 4, 0u, s);
+  using L8T = LayoutPacked<8, true>;
+  using L8C = LayoutPacked<8, false>;
+  if (two) return dispatch_flags<OffT, L8T, STATS>(g, L8T{g->st(), mate, hint}, s);
+  return dispatch_flags<OffT, L8C, STATS>(g, L8C{g->st(), mate, hint}, s);
+}
+
+}  // namespace
 
 extern "C" {
 
-const char* mm_version(void) { return "skipper-gfx950 0.1"; }
+const char* mm_version(void) { return "skipper-gfx950 0.2"; }
 
 const char* mm_last_error(void) { return g_last_error.c_str(); }
 
@@ -167,11 +288,14 @@ void mm_default_tuning(mm_tuning* t) {
   if (!t) return;
   std::memset(t, 0, sizeof(*t));
   t->layout = MM_LAYOUT_U8;
+  t->protocol = MM_PROTOCOL_CAS;
+  t->hint = 0;
   t->wg_size = 256;
   t->wave_vertices = 1024;
   t->disperse = 0;
   t->assist_after = 16;
   t->lazy_init = 1;
+  t->scan_width = 4;
   t->iter_cap = 0;
 }
 
@@ -179,7 +303,7 @@ size_t mm_workspace_bytes(int64_t n, const mm_tuning* tp) {
   mm_tuning t;
   if (tp) t = *tp; else mm_default_tuning(&t);
   if (n < 0 || n > INT32_MAX || check_tuning(t) != MM_OK) return 0;
-  return kCtrlBytes + state_bytes(n, t);
+  return kCtrlBytes + mmi::state_bytes(n, t) + mmi::hint_bytes(n, t);
 }
 
 mm_status mm_create(const void* offsets, mm_offset_type off_type, const int32_t* neighbors,
@@ -189,7 +313,8 @@ mm_status mm_create(const void* offsets, mm_offset_type off_type, const int32_t*
   *out = nullptr;
   if (off_type != MM_OFF_I32 && off_type != MM_OFF_I64)
     return fail(MM_ERR_INVALID_ARG, "off_type must be MM_OFF_I32 or MM_OFF_I64");
-  if (n < 0 || n > INT32_MAX) return fail(MM_ERR_INVALID_ARG, "n = %lld out of [0, 2^31-1]", (long long)n);
+  if (n < 0 || n > INT32_MAX)
+    return fail(MM_ERR_INVALID_ARG, "n = %lld out of [0, 2^31-1]", (long long)n);
   if (m < 0) return fail(MM_ERR_INVALID_ARG, "m = %lld is negative", (long long)m);
   if (off_type == MM_OFF_I32 && m > INT32_MAX)
     return fail(MM_ERR_INVALID_ARG, "m = %lld does not fit int32 offsets", (long long)m);
@@ -204,9 +329,7 @@ mm_status mm_create(const void* offsets, mm_offset_type off_type, const int32_t*
   if (tuning) t = *tuning; else mm_default_tuning(&t);
   mm_status st = check_tuning(t);
   if (st != MM_OK) return st;
-  if (t.lazy_init && (t.layout != MM_LAYOUT_U8 || !(flags & MM_SYMMETRIC)))
-    t.lazy_init = 0;  // lazy mate output is only sound for symmetric input on the U8 layout
-  const size_t need = kCtrlBytes + state_bytes(n, t);
+  const size_t need = kCtrlBytes + mmi::state_bytes(n, t) + mmi::hint_bytes(n, t);
   if (workspace_bytes < need)
     return fail(MM_ERR_OUT_OF_MEMORY, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
 
@@ -250,6 +373,9 @@ mm_status mm_create(const void* offsets, mm_offset_type off_type, const int32_t*
   g->ws_bytes = workspace_bytes;
   g->flags = flags;
   g->tun = t;
+  // Lazy output is only sound when every edge is in both endpoints' lists.
+  g->lazy = t.lazy_init && (flags & MM_SYMMETRIC) &&
+            !(t.layout == MM_LAYOUT_U32 && t.protocol == MM_PROTOCOL_CAS);
   g->device = dev;
   g->timing = nullptr;
   if (flags & MM_TIMING) {
@@ -269,62 +395,6 @@ mm_status mm_create(const void* offsets, mm_offset_type off_type, const int32_t*
   *out = g;
   return MM_OK;
 }
-
-}  // extern "C"
-
-namespace {
-
-template <typename OffT, class Layout, bool LAZY, bool STATS>
-hipError_t launch_sweep(const mm_graph* g, const Layout& L, int32_t* mate, hipStream_t s) {
-  SweepParams p;
-  p.wave_vertices = g->tun.wave_vertices;
-  p.disperse = g->tun.disperse;
-  p.assist_after = g->tun.assist_after;
-  p.iter_cap = g->tun.iter_cap;
-  p.err = reinterpret_cast<uint32_t*>(g->ws);
-  unsigned long long* stats = reinterpret_cast<unsigned long long*>(g->ws + kStatsOffset);
-  const int64_t waves = (g->n + p.wave_vertices - 1) / p.wave_vertices;
-  const int wpb = g->tun.wg_size / 64;
-  const int64_t blocks = (waves + wpb - 1) / wpb;
-  if (blocks == 0) return hipSuccess;
-  if (g->timing) {
-    hipError_t e = hipEventRecord(g->timing->before(), s);
-    if (e != hipSuccess) return e;
-  }
-  hipLaunchKernelGGL((sweep_kernel<OffT, Layout, LAZY, STATS>), dim3((unsigned)blocks),
-                     dim3(g->tun.wg_size), 0, s, p, static_cast<const OffT*>(g->off), g->nbr, g->n,
-                     L, mate, stats);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  if (g->timing) {
-    e = hipEventRecord(g->timing->after(), s);
-    ++g->timing->recorded;
-  }
-  return e;
-}
-
-template <typename OffT, bool STATS>
-hipError_t run_typed(const mm_graph* g, int32_t* mate, hipStream_t s) {
-  const int64_t n = g->n;
-  if (g->tun.layout == MM_LAYOUT_U32) {
-    hipLaunchKernelGGL(fill_u32_kernel, dim3(fill_grid(n)), dim3(256), 0, s,
-                       reinterpret_cast<uint32_t*>(mate), n, 0xffffffffu);
-    LayoutU32 L{mate};
-    return launch_sweep<OffT, LayoutU32, false, STATS>(g, L, mate, s);
-  }
-  uint32_t* st = reinterpret_cast<uint32_t*>(g->ws + kCtrlBytes);
-  const int64_t words = (n + 3) / 4;
-  hipLaunchKernelGGL(fill_u32_kernel, dim3(fill_grid(words)), dim3(256), 0, s, st, words, 0u);
-  LayoutU8 L{st, mate};
-  if (g->tun.lazy_init) return launch_sweep<OffT, LayoutU8, true, STATS>(g, L, mate, s);
-  hipLaunchKernelGGL(fill_u32_kernel, dim3(fill_grid(n)), dim3(256), 0, s,
-                     reinterpret_cast<uint32_t*>(mate), n, 0xffffffffu);
-  return launch_sweep<OffT, LayoutU8, false, STATS>(g, L, mate, s);
-}
-
-}  // namespace
-
-extern "C" {
 
 mm_status mm_run(mm_handle g, void* stream, int32_t* match_out) {
   if (!g) return fail(MM_ERR_INVALID_ARG, "handle is null");

@@ -1,36 +1,39 @@
 // The single-pass sweep of Skipper (Algorithm 1) as a gfx950 kernel.
 //
 // Work decomposition. Each wavefront owns a block of consecutive source
-// vertices (the GPU form of the paper's blocks of consecutive vertices with
-// about equal work, Section IV-C). Every lane works on one source at a time;
-// a lane that finishes takes the next source of the block (ballot + mbcnt
-// hand-out), so lanes stay busy whatever the spread of scan lengths. The
-// hardware dispatcher hands blocks to the 256 CUs as earlier ones retire.
+// vertices (the GPU form of the paper's blocks of consecutive vertices,
+// Section IV-C). Every lane works on one source at a time; a lane that
+// finishes takes the block's next source (ballot + mbcnt hand-out), so lanes
+// stay busy whatever the spread of scan lengths. The hardware dispatcher hands
+// blocks to the CUs as earlier ones retire.
 //
 // Per lane, one source x at a time (Section II-B, CSR form):
 //   * skip x if it is already matched (Fig. 6g);
-//   * walk N_x in stored order; skip self-loops (Alg. 1 L6-7) and neighbours
-//     seen matched; for a candidate y take u = min(x,y), v = max(x,y)
-//     (Alg. 1 L8-9, which rules out reservation cycles) and run the
-//     reservation: reserve u (L11), move v from ACC to MCHD (L13-14), then
-//     mark u matched (L15) or release it (L17-18);
-//   * stop at the first matched pair: x is matched and the rest of N_x is
-//     never read.
+//   * walk N_x in stored order, W ids at a time; skip self-loops (Alg. 1 L6-7)
+//     and neighbours seen matched; for a candidate y take u = min(x,y),
+//     v = max(x,y) (L8-9, which rules out reservation cycles) and run the
+//     reservation: reserve u (L11), take v (L13-14), then mark u matched (L15)
+//     or release it (L17-18);
+//   * stop at the first matched pair: the rest of N_x is never read.
+//
+// Pipelining. A lane's work is a chain of dependent memory operations
+// (offsets -> ids -> states -> reserve -> take v). Each trip of the loop
+// first consumes the results of the operations issued on the previous trip
+// (ALU only), then issues one operation per lane, so the operations of all
+// lanes, whatever their phase, are in flight together.
 //
 // Waiting without intra-wavefront spin. Lanes of a wavefront share one
-// instruction stream, so a lane may not loop waiting for a reservation that
-// another lane of the same wavefront holds. Every wait of Algorithm 1 (L11's
-// "continue" on a reserved u, L13's loop on a reserved v) therefore becomes
-// "stay in this phase and retry on the next trip of the wavefront's loop":
-// each trip, every lane advances by at most one protocol step. Reservation
-// chains only wait on higher ids (u < v), so the lane at the top of any chain
-// meets ACC or MCHD and finishes; no trip can block all lanes.
+// instruction stream, so no lane may loop waiting for a reservation that
+// another lane of its wavefront holds. Every wait of Algorithm 1 (L11's
+// "continue" on a reserved u, L13's loop on a reserved v) is "stay in this
+// phase and poll again next trip". Reservation chains only wait on higher ids
+// (u < v), so the lane at the top of any chain meets ACC or MCHD and finishes.
 //
-// Long scans. When a lane has scanned `assist_after` neighbours and still has
-// more than a few left, the whole wavefront reads the next 64 ids of that list
-// at once, finds the first one not seen matched with a ballot, and moves the
-// lane's cursor there (or 64 ahead). It also re-reads the source's state so a
-// source matched by another lane stops early.
+// Long scans (the wavefront tier). When a lane has read `assist_after` ids of
+// its list and more than 2W remain, the whole wavefront reads the next 64 ids
+// of that list and their states in two trips, finds the first candidate with
+// a ballot and moves the lane's cursor there (or 64 ahead); the other lanes
+// keep working meanwhile.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -39,7 +42,21 @@
 
 namespace mmk {
 
-enum : int { P_IDLE = 0, P_SCAN = 1, P_TRYU = 2, P_TRYV = 3, P_FINAL = 4, P_DONE = 5 };
+constexpr int kMaxW = 4;
+
+enum : int {
+  P_IDLE = 0,  // needs a source
+  P_SRC,       // offsets and source state requested
+  P_IDS,       // next W neighbour ids requested
+  P_STS,       // states of the buffered ids requested
+  P_RES,       // reserve(u) issued (Alg. 1 L11)
+  P_CHK,       // u was reserved by another lane: coherent re-read of u and v (L10)
+  P_MAT,       // v requested: CAS ACC -> MCHD (L14), or reserve(v) (two-phase)
+  P_MATW,      // v was reserved by another lane: coherent re-read of v (L13)
+  P_FIN,       // list exhausted: final check of the source's own state
+  P_ASST,      // paused while the wavefront scans ahead for this lane
+  P_DONE
+};
 
 // Launch parameters shared by every block of a sweep. Vertex ids inside a
 // block are local to its graph; the layout object and the offsets pointer
@@ -48,6 +65,7 @@ struct SweepParams {
   int64_t wave_vertices;   // multiple of 64
   int32_t disperse;
   int32_t assist_after;
+  int32_t scan_width;      // 1..kMaxW
   int64_t iter_cap;        // 0: per-block default budget
   uint32_t* err;           // bit 0: loop-trip budget exceeded
 };
@@ -61,15 +79,12 @@ template <bool ON>
 struct Counters {
   __device__ __forceinline__ void add(int, uint32_t) {}
   __device__ __forceinline__ void flush(unsigned long long*) {}
-  uint32_t word_retries = 0;
 };
 template <>
 struct Counters<true> {
   uint32_t c[S_NUM] = {};
-  uint32_t word_retries = 0;
   __device__ __forceinline__ void add(int k, uint32_t v) { c[k] += v; }
   __device__ __forceinline__ void flush(unsigned long long* out) {
-    c[S_WORD_RETRY] += word_retries;
 #pragma unroll
     for (int k = 0; k < S_NUM; ++k) {
       unsigned long long s = c[k];
@@ -93,148 +108,303 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
 }
 
 // Sweeps the sources vb .. vb+nv-1 of one graph with one wavefront.
-// off: the graph's offsets (entries index `nbr`); L: its state layout;
-// mate: its mate array (local ids).
-template <typename OffT, class Layout, bool LAZY, bool STATS>
+// off: the graph's offsets (entries index `nbr`); L: its state layout (with
+// its mate array and hint, all based at the graph's first vertex).
+// HINT: skip matched neighbours by the one-bit-per-vertex hint instead of the
+// state word.
+template <typename OffT, class Layout, bool HINT, bool LAZY, bool STATS>
 __device__ __forceinline__ void sweep_block(const SweepParams& a, const OffT* __restrict__ off,
                                             const int32_t* __restrict__ nbr, const Layout& L,
-                                            int32_t* __restrict__ mate, int64_t vb, int64_t nv,
-                                            Counters<STATS>& cnt) {
+                                            int64_t vb, int64_t nv, Counters<STATS>& cnt) {
   const int lane = (int)(threadIdx.x & 63);
+  const int W = a.scan_width;
   const bool disperse = a.disperse && nv == a.wave_vertices;
   const int64_t stride = a.wave_vertices >> 6;
-
   // Loop-trip budget: explicit, or by default 65536 plus 8 per neighbour entry
   // of the block (a pass needs at most about one trip per entry plus short
   // waits), so even an unforeseen livelock ends with an error flag.
   const int64_t cap = a.iter_cap > 0 ? a.iter_cap
                                      : 65536 + 8 * ((int64_t)off[vb + nv] - (int64_t)off[vb]);
+
+  // Filter reads: the hint bit, or the vertex's own state word.
+  auto filter_word = [&](int64_t y) -> uint32_t {
+    if (HINT) return ld_cached(L.hint.bits + (y >> 5));
+    return L.word_cached(y);
+  };
+  auto filter_matched = [&](uint32_t word, int64_t y) -> bool {
+    if (HINT) return ((word >> (uint32_t)(y & 31)) & 1u) != 0;
+    return Layout::matched(word, y);
+  };
+
   int64_t handed = 0;  // wavefront-uniform hand-out cursor
+  int64_t trips = 0;
   int phase = P_IDLE;
   int64_t x = 0, i = 0, e = 0, u = 0, v = 0;
+  int32_t ids[kMaxW];
+  uint32_t rw[kMaxW];
+#pragma unroll
+  for (int j = 0; j < kMaxW; ++j) {
+    ids[j] = 0;
+    rw[j] = 0;
+  }
+  int k = 0, nids = 0, steps = 0;
   uint32_t xword = 0, vguess = 0;
-  int32_t steps = 0;
-  int64_t trips = 0;
+  // Results of the operations issued on a trip, one register per phase:
+  // different lanes issue different phases on the same trip, and a shared
+  // destination register would force a wait between them.
+  int64_t src_b = 0, src_e = 0;
+  uint32_t src_w = 0, res_w = 0, chk_u = 0, chk_v = 0, mat_w = 0, matw_w = 0, fin_w = 0;
+  // wavefront assist (uniform state)
+  int asst = 0, al = 0;
+  int64_t ai = 0, ae = 0, ax = 0;
+  int32_t aid = -1;
+  uint32_t aw = 0, axw = 0;
 
+  // Next candidate among the buffered ids [k, nids), else read on.
+  auto advance = [&]() {
+    int found = -1;
+    int32_t fy = 0;
+    uint32_t fw = 0;
+#pragma unroll
+    for (int j = kMaxW - 1; j >= 0; --j) {
+      if (j >= k && j < nids && (int64_t)ids[j] != x && !filter_matched(rw[j], ids[j])) {
+        found = j;
+        fy = ids[j];
+        fw = rw[j];
+      }
+    }
+    if (found >= 0) {
+      const int64_t y = fy;
+      k = found + 1;
+      u = x < y ? x : y;
+      v = x < y ? y : x;
+      vguess = HINT ? 0u : ((x < y) ? fw : xword);
+      phase = P_RES;
+    } else {
+      k = nids;
+      phase = (i < e) ? P_IDS : (LAZY ? P_FIN : P_IDLE);
+    }
+  };
+  // The current edge cannot be matched because w (u or v) is matched.
+  auto edge_dead = [&](int64_t w) {
+    if (w == x) phase = P_IDLE; else advance();
+  };
+
+#pragma unroll 1
   while (true) {
-    // ---- hand the block's next sources to idle lanes
-    const uint64_t idle = __ballot(phase == P_IDLE);
-    if (idle) {
-      if (phase == P_IDLE) {
-        const int64_t k = handed + lanes_below(idle);
-        if (k < nv) {
-          x = vb + (disperse ? (k & 63) * stride + (k >> 6) : k);
-          const int64_t b = (int64_t)off[x], en = (int64_t)off[x + 1];
+    // ---------------- consume the results of last trip's operations
+    // One wait for everything issued on the previous trip (s_waitcnt vmcnt(0);
+    // expcnt and lgkmcnt left at their maxima), so that no issue branch below
+    // waits for a register written on an earlier trip.
+    __builtin_amdgcn_s_waitcnt(0x0f70);
+    switch (phase) {
+      case P_SRC: {
+        const int64_t b = src_b, en = src_e;
+        xword = src_w;
+        if (b == en) {
+          if (LAZY) L.write_unmatched(x);  // no incident entry: never matched (symmetric input)
+          phase = P_IDLE;
+        } else if (filter_matched(xword, x)) {
+          if (STATS) cnt.add(S_SKIPPED, 1);
+          phase = P_IDLE;
+        } else {
           i = b;
           e = en;
           steps = 0;
+          phase = P_IDS;
+        }
+        break;
+      }
+      case P_IDS: {
+        const int64_t rem = e - i;
+        nids = rem < W ? (int)rem : W;
+        i += nids;
+        steps += nids;
+        k = 0;
+        if (STATS) cnt.add(S_TOUCHED, (uint32_t)nids);
+        phase = P_STS;
+        break;
+      }
+      case P_STS:
+        advance();
+        break;
+      case P_RES: {
+        const int s = Layout::decode(res_w, u);
+        if (s == R_ACC) {
+          phase = P_MAT;
+        } else if (s == R_MCHD) {
+          if (STATS) cnt.add(S_RES_MCHD, 1);
+          edge_dead(u);
+        } else {
+          if (STATS) cnt.add(S_RES_CONF, 1);
+          phase = P_CHK;
+        }
+        break;
+      }
+      case P_CHK: {
+        const int su = Layout::decode(chk_u, u), sv = Layout::decode(chk_v, v);
+        if (sv == R_MCHD) {
+          edge_dead(v);
+        } else if (su == R_MCHD) {
+          edge_dead(u);
+        } else if (su == R_ACC) {
+          phase = P_RES;
+        }
+        break;
+      }
+      case P_MAT: {
+        bool won;
+        int s;
+        if (Layout::kTwoPhase) {
+          s = Layout::decode(mat_w, v);
+          won = s == R_ACC;
+        } else {
+          won = Layout::match_ok(mat_w, vguess, v);
+          s = won ? R_ACC : Layout::decode(mat_w, v);
+        }
+        if (won) {
+          L.commit(u, v);
+          if (STATS) cnt.add(S_PAIRS, 1);
+          phase = P_IDLE;
+        } else if (s == R_ACC) {  // CAS lost to a change in another byte of the word
+          if (STATS) cnt.add(S_WORD_RETRY, 1);
+          vguess = mat_w;
+        } else if (s == R_RSVD) {
+          if (STATS) cnt.add(S_MAT_CONF, 1);
+          phase = P_MATW;
+        } else {
+          if (STATS) cnt.add(S_MAT_MCHD, 1);
+          L.release(u);
+          edge_dead(v);
+        }
+        break;
+      }
+      case P_MATW: {
+        const int s = Layout::decode(matw_w, v);
+        if (s == R_ACC) {
+          vguess = matw_w;
+          phase = P_MAT;
+        } else if (s == R_MCHD) {
+          L.release(u);
+          edge_dead(v);
+        }
+        break;
+      }
+      case P_FIN: {
+        // x's list is exhausted and every neighbour was seen matched, so only
+        // a reservation already in flight on x can still match it. fin_w is
+        // the state read (or, for the word layout with the two-phase protocol,
+        // the state a CAS ACC -> -1 met).
+        const int s = Layout::decode(fin_w, x);
+        if (s == R_ACC) {
+          L.finalize_after_read(x);
+          phase = P_IDLE;
+        } else if (s == R_MCHD) {
+          phase = P_IDLE;
+        }
+        break;
+      }
+      default:
+        break;
+    }
+
+    // ---------------- wavefront assist: consume
+    if (asst == 2) {
+      const bool cand = aid >= 0 && (int64_t)aid != ax && !filter_matched(aw, aid);
+      const uint64_t cm = __ballot(cand);
+      if (lane == al) {
+        if (filter_matched(axw, x)) {
+          phase = P_IDLE;  // the source was matched by another lane meanwhile
+        } else {
+          i = cm ? ai + __builtin_ctzll(cm) : (ae - ai > 64 ? ai + 64 : ae);
+          steps = 0;
+          nids = 0;
+          k = 0;
+          phase = (i < e) ? P_IDS : (LAZY ? P_FIN : P_IDLE);
+        }
+      }
+      asst = 0;
+    }
+
+    // ---------------- hand the block's next sources to idle lanes
+    const uint64_t idle = __ballot(phase == P_IDLE);
+    if (idle) {
+      if (phase == P_IDLE) {
+        const int64_t kk = handed + lanes_below(idle);
+        if (kk < nv) {
+          x = vb + (disperse ? (kk & 63) * stride + (kk >> 6) : kk);
+          phase = P_SRC;
           if (STATS) cnt.add(S_SOURCES, 1);
-          if (b == en) {
-            if (LAZY) mate[x] = -1;  // no incident entry: never matched (symmetric input)
-          } else if (L.seen_matched(x, xword)) {
-            if (STATS) cnt.add(S_SKIPPED, 1);
-          } else {
-            phase = P_SCAN;
-          }
         } else {
           phase = P_DONE;
         }
       }
       handed += __popcll(idle);
     }
-    const uint64_t busy = __ballot(phase != P_IDLE && phase != P_DONE);
-    if (!busy) {
-      if (handed >= nv) break;
-      continue;
-    }
+    if (!__ballot(phase != P_DONE) && asst == 0) break;
     if (++trips > cap) {
-      if (phase == P_TRYV) L.release(u);
+      if (phase == P_MAT || phase == P_MATW) L.release(u);  // holding u
       if (lane == 0) atomicOr(a.err, 1u);
       break;
     }
 
-    // ---- wavefront assist for one long scan
-    if (a.assist_after > 0) {
-      const uint64_t lm = __ballot(phase == P_SCAN && steps >= a.assist_after && (e - i) > 4);
+    // ---------------- wavefront assist: issue
+    if (asst == 1) {
+      aw = (aid >= 0 && (int64_t)aid != ax) ? filter_word(aid) : 0u;
+      if (lane == al) axw = filter_word(x);
+      if (STATS && aid >= 0) cnt.add(S_ASSIST, 1);
+      asst = 2;
+    } else if (asst == 0 && a.assist_after > 0) {
+      const uint64_t lm =
+          __ballot(phase == P_IDS && steps >= a.assist_after && (e - i) > 2 * W);
       if (lm) {
-        const int ld = __builtin_ctzll(lm);
-        const int64_t xl = readlane64(x, ld), il = readlane64(i, ld), el = readlane64(e, ld);
-        const int64_t p = il + lane;
-        bool cand = false;
-        if (p < el) {
-          const int32_t yy = nbr[p];
-          uint32_t wd;
-          cand = (yy != xl) && !L.seen_matched(yy, wd);
-          if (STATS) cnt.add(S_ASSIST, 1);
-        }
-        const uint64_t cm = __ballot(cand);
-        if (lane == ld) {
-          i = cm ? il + __builtin_ctzll(cm) : (el - il > 64 ? il + 64 : el);
-          uint32_t wd;
-          if (L.seen_matched(x, wd)) phase = P_IDLE;  // source matched elsewhere
-        }
+        al = __builtin_ctzll(lm);
+        ai = readlane64(i, al);
+        ae = readlane64(e, al);
+        ax = readlane64(x, al);
+        if (lane == al) phase = P_ASST;
+        aid = (ai + lane < ae) ? nbr[ai + lane] : -1;
+        asst = 1;
       }
     }
 
-    // ---- one scan step: find the next candidate edge (x, y)
-    if (phase == P_SCAN) {
-      if (i >= e) {
-        phase = LAZY ? P_FINAL : P_IDLE;
-      } else {
-        const int64_t y = (int64_t)nbr[i];
-        ++i;
-        ++steps;
-        if (STATS) cnt.add(S_TOUCHED, 1);
-        uint32_t yword;
-        if (y != x && !L.seen_matched(y, yword)) {
-          u = (x < y ? x : y);
-          v = (x < y ? y : x);
-          vguess = (x < y) ? yword : xword;
-          phase = P_TRYU;
-        }
-      }
-    }
-    // ---- reserve u (Alg. 1 L11-12)
-    if (phase == P_TRYU) {
-      if (STATS) cnt.add(S_RES_ATT, 1);
-      const int r = L.reserve(u);
-      if (r == R_ACC) {
-        phase = P_TRYV;
-      } else if (r == R_MCHD) {
-        if (STATS) cnt.add(S_RES_MCHD, 1);
-        phase = (u == x) ? P_IDLE : P_SCAN;
-      } else {
-        if (STATS) cnt.add(S_RES_CONF, 1);
-        // L10 re-check of v while u is held by another lane; retry next trip
-        if (L.state_coherent(v) == R_MCHD) phase = (v == x) ? P_IDLE : P_SCAN;
-      }
-    }
-    // ---- match v (Alg. 1 L13-16), then mark u or release it (L17-18)
-    if (phase == P_TRYV) {
-      if (STATS) cnt.add(S_MAT_ATT, 1);
-      const int r = L.match(v, u, vguess, cnt.word_retries);
-      if (r == R_ACC) {
-        L.commit(u, v);
-        if (STATS) cnt.add(S_PAIRS, 1);
-        phase = P_IDLE;
-      } else if (r == R_MCHD) {
-        if (STATS) cnt.add(S_MAT_MCHD, 1);
-        L.release(u);
-        phase = (v == x) ? P_IDLE : P_SCAN;
-      } else if (r == R_RSVD) {
-        if (STATS) cnt.add(S_MAT_CONF, 1);
-      }
-    }
-    // ---- lazy output: x's list is exhausted, every neighbour is matched, so
-    // x can only be matched by a reservation already in flight on x
-    if (LAZY && phase == P_FINAL) {
-      const int s = L.state_coherent(x);
-      if (s == R_ACC) {
-        mate[x] = -1;
-        phase = P_IDLE;
-      } else if (s == R_MCHD) {
-        phase = P_IDLE;
-      }
+    // ---------------- issue one operation per lane
+    switch (phase) {
+      case P_SRC:
+        src_b = (int64_t)off[x];
+        src_e = (int64_t)off[x + 1];
+        src_w = filter_word(x);
+        break;
+      case P_IDS:
+#pragma unroll
+        for (int j = 0; j < kMaxW; ++j)
+          if (j < W) ids[j] = (i + j < e) ? nbr[i + j] : (int32_t)x;
+        break;
+      case P_STS:
+#pragma unroll
+        for (int j = 0; j < kMaxW; ++j)
+          if (j < nids && (int64_t)ids[j] != x) rw[j] = filter_word(ids[j]);
+        break;
+      case P_RES:
+        if (STATS) cnt.add(S_RES_ATT, 1);
+        res_w = L.reserve(u);
+        break;
+      case P_CHK:
+        chk_u = L.word_coherent(u);
+        chk_v = L.word_coherent(v);
+        break;
+      case P_MAT:
+        if (STATS) cnt.add(S_MAT_ATT, 1);
+        mat_w = Layout::kTwoPhase ? L.reserve(v) : L.match(v, u, vguess);
+        break;
+      case P_MATW:
+        matw_w = L.word_coherent(v);
+        break;
+      case P_FIN:
+        fin_w = L.fin_probe(x);
+        break;
+      default:
+        break;
     }
   }
   if (STATS) cnt.add(S_TRIPS, lane == 0 ? (uint32_t)trips : 0u);

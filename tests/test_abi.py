@@ -51,6 +51,8 @@ def test_workspace_bytes():
     assert lib.mm_workspace_bytes(1 << 31, ctypes.byref(t)) == 0
     t.layout = _lib.MM_LAYOUT_U32
     assert lib.mm_workspace_bytes(1 << 20, ctypes.byref(t)) == small
+    t.hint = 1
+    assert lib.mm_workspace_bytes(1 << 20, ctypes.byref(t)) == small + (1 << 20) // 8
     t.wg_size = 100
     assert lib.mm_workspace_bytes(10, ctypes.byref(t)) == 0
 
@@ -94,6 +96,13 @@ def test_create_bad_tuning():
     st, _ = _create(lib, tuning=ctypes.pointer(t))
     assert st == _lib.MM_ERR_INVALID_ARG
     assert b"wave_vertices" in lib.mm_last_error()
+    for field, bad in (("protocol", 2), ("hint", 3), ("scan_width", 0), ("scan_width", 9),
+                       ("layout", 5), ("reserved_", 1), ("iter_cap", -1)):
+        lib.mm_default_tuning(ctypes.byref(t))
+        setattr(t, field, bad)
+        st, _ = _create(lib, tuning=ctypes.pointer(t))
+        assert st == _lib.MM_ERR_INVALID_ARG, field
+        assert field.encode() in lib.mm_last_error(), field
 
 
 def test_null_handle_calls():
