@@ -9,9 +9,7 @@
 // Random numbers come from one counter-based generator: the SplitMix64 output
 // function (Steele, Lea and Flood, "Fast splittable pseudorandom number
 // generators", OOPSLA 2014) applied to a keyed counter, so every draw is a pure
-// function of (seed, stream, counter) and a pass over the samples can be
-// replayed. That replay lets the builder count degrees in one pass and scatter
-// in a second without ever holding an edge list.
+// function of (seed, stream, counter), whatever the thread count.
 //
 // Models:
 //   * Erdos-Renyi G(n, p) over unordered pairs, by geometric skipping over
@@ -109,60 +107,135 @@ struct gg_csr {
 
 namespace {
 
-// Builds a symmetric CSR from a replayable sampler of undirected pairs.
+// Builds a symmetric CSR from a sampler of undirected pairs.
 // `Sampler::for_each(i, emit)` calls emit(u, v) for every pair of chunk i.
 // Self-loops are dropped, both orientations inserted, lists sorted and
+// deduplicated. The result depends only on the multiset of pairs.
+//
+// One pass, no atomics: each thread takes a contiguous range of chunks and
+// appends its (source, target) pairs to per-bucket chains of fixed-size
+// blocks (a bucket is a range of consecutive sources; at most 1024 buckets, so
+// every thread writes to few streams). Each bucket is then turned into CSR
+// lists by a local counting sort over its chains, and every list is sorted and
 // deduplicated.
+namespace {
+constexpr int64_t kBlockPairs = 4096;
+struct PairBlock {
+  uint64_t p[kBlockPairs];
+  PairBlock* next;
+  int64_t used;
+};
+}  // namespace
+
 template <class Sampler>
 gg_csr* build_symmetric(int64_t n, const Sampler& s, int64_t nchunks, int nt) {
-  std::vector<uint32_t> cnt(n + 1, 0);
-  uint32_t* c = cnt.data();
-#pragma omp parallel for schedule(dynamic, 1) num_threads(nt)
-  for (int64_t i = 0; i < nchunks; ++i) {
-    s.for_each(i, [&](int64_t u, int64_t v) {
-      if (u == v) return;
-      __atomic_fetch_add(&c[u], 1u, __ATOMIC_RELAXED);
-      __atomic_fetch_add(&c[v], 1u, __ATOMIC_RELAXED);
-    });
+  int shift = 0;
+  while (((n - 1) >> shift) >= 1024) ++shift;  // at most 1024 buckets
+  const int64_t nb = n > 0 ? ((n - 1) >> shift) + 1 : 1;
+  // chains[t][b]: head of thread t's block chain for bucket b
+  std::vector<PairBlock*> heads((size_t)nt * nb, nullptr);
+  std::vector<int64_t> counts((size_t)nt * nb, 0);
+  bool oom = false;
+  auto chunk_lo = [&](int t) { return nchunks * t / nt; };
+#pragma omp parallel num_threads(nt)
+  {
+    const int t = omp_get_thread_num();
+    PairBlock** h = heads.data() + (size_t)t * nb;
+    int64_t* c = counts.data() + (size_t)t * nb;
+    auto push = [&](int64_t a, int64_t b) {
+      const int64_t k = a >> shift;
+      PairBlock* blk = h[k];
+      if (!blk || blk->used == kBlockPairs) {
+        PairBlock* nbk = static_cast<PairBlock*>(std::malloc(sizeof(PairBlock)));
+        if (!nbk) {
+          oom = true;
+          return;
+        }
+        nbk->next = blk;
+        nbk->used = 0;
+        h[k] = blk = nbk;
+      }
+      blk->p[blk->used++] = ((uint64_t)a << 32) | (uint64_t)b;
+      ++c[k];
+    };
+    for (int64_t i = chunk_lo(t); i < chunk_lo(t + 1); ++i)
+      s.for_each(i, [&](int64_t u, int64_t v) {
+        if (u == v) return;
+        push(u, v);
+        push(v, u);
+      });
   }
+  auto free_chains = [&]() {
+    for (PairBlock* b : heads)
+      while (b) {
+        PairBlock* nx = b->next;
+        std::free(b);
+        b = nx;
+      }
+  };
+  if (oom) {
+    free_chains();
+    throw std::bad_alloc();
+  }
+  std::vector<int64_t> bstart(nb + 1, 0);
+  for (int64_t b = 0; b < nb; ++b) {
+    int64_t tot = 0;
+    for (int t = 0; t < nt; ++t) tot += counts[(size_t)t * nb + b];
+    bstart[b + 1] = bstart[b] + tot;
+  }
+  const int64_t total = bstart[nb];
   int64_t* raw_off = static_cast<int64_t*>(std::malloc(sizeof(int64_t) * (n + 1)));
-  if (!raw_off) throw std::bad_alloc();
-  raw_off[0] = 0;
-  for (int64_t v = 0; v < n; ++v) raw_off[v + 1] = raw_off[v] + c[v];
-  const int64_t raw_m = raw_off[n];
-  int32_t* raw = static_cast<int32_t*>(std::malloc(sizeof(int32_t) * (raw_m > 0 ? raw_m : 1)));
-  if (!raw) throw std::bad_alloc();
-#pragma omp parallel for schedule(dynamic, 1) num_threads(nt)
-  for (int64_t i = 0; i < nchunks; ++i) {
-    s.for_each(i, [&](int64_t u, int64_t v) {
-      if (u == v) return;
-      uint32_t pu = __atomic_sub_fetch(&c[u], 1u, __ATOMIC_RELAXED);
-      raw[raw_off[u] + pu] = static_cast<int32_t>(v);
-      uint32_t pv = __atomic_sub_fetch(&c[v], 1u, __ATOMIC_RELAXED);
-      raw[raw_off[v] + pv] = static_cast<int32_t>(u);
-    });
+  int32_t* raw = static_cast<int32_t*>(std::malloc(sizeof(int32_t) * (total > 0 ? total : 1)));
+  std::vector<uint32_t> deg(n > 0 ? n : 1, 0);
+  if (!raw_off || !raw) {
+    free_chains();
+    throw std::bad_alloc();
   }
-  // Sort and deduplicate each list in place; cnt[v] becomes the new degree.
-#pragma omp parallel for schedule(dynamic, 4096) num_threads(nt)
-  for (int64_t v = 0; v < n; ++v) {
-    int32_t* b = raw + raw_off[v];
-    int32_t* e = raw + raw_off[v + 1];
-    std::sort(b, e);
-    c[v] = static_cast<uint32_t>(std::unique(b, e) - b);
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nt)
+  for (int64_t b = 0; b < nb; ++b) {
+    const int64_t v0 = b << shift, v1 = std::min(n, (b + 1) << shift);
+    for (int t = 0; t < nt; ++t)
+      for (const PairBlock* blk = heads[(size_t)t * nb + b]; blk; blk = blk->next)
+        for (int64_t q = 0; q < blk->used; ++q) ++deg[blk->p[q] >> 32];
+    std::vector<int64_t> fill(v1 - v0);
+    int64_t pos = bstart[b];
+    for (int64_t v = v0; v < v1; ++v) {
+      raw_off[v] = pos;
+      fill[v - v0] = pos;
+      pos += deg[v];
+    }
+    for (int t = 0; t < nt; ++t) {
+      PairBlock* blk = heads[(size_t)t * nb + b];
+      while (blk) {
+        for (int64_t q = 0; q < blk->used; ++q) {
+          const uint64_t pr = blk->p[q];
+          raw[fill[(int64_t)(pr >> 32) - v0]++] = (int32_t)(uint32_t)pr;
+        }
+        PairBlock* nx = blk->next;
+        std::free(blk);
+        blk = nx;
+      }
+      heads[(size_t)t * nb + b] = nullptr;
+    }
+    for (int64_t v = v0; v < v1; ++v) {
+      int32_t* lb = raw + raw_off[v];
+      int32_t* le = lb + deg[v];
+      std::sort(lb, le);
+      deg[v] = (uint32_t)(std::unique(lb, le) - lb);
+    }
   }
   gg_csr* g = new gg_csr();
   g->n = n;
   g->off = static_cast<int64_t*>(std::malloc(sizeof(int64_t) * (n + 1)));
   if (!g->off) throw std::bad_alloc();
   g->off[0] = 0;
-  for (int64_t v = 0; v < n; ++v) g->off[v + 1] = g->off[v] + c[v];
+  for (int64_t v = 0; v < n; ++v) g->off[v + 1] = g->off[v] + deg[v];
   g->m = g->off[n];
   g->nbr = static_cast<int32_t*>(std::malloc(sizeof(int32_t) * (g->m > 0 ? g->m : 1)));
   if (!g->nbr) throw std::bad_alloc();
 #pragma omp parallel for schedule(dynamic, 4096) num_threads(nt)
-  for (int64_t v = 0; v < n; ++v) {
-    std::memcpy(g->nbr + g->off[v], raw + raw_off[v], sizeof(int32_t) * c[v]);
-  }
+  for (int64_t v = 0; v < n; ++v)
+    std::memcpy(g->nbr + g->off[v], raw + raw_off[v], sizeof(int32_t) * deg[v]);
   std::free(raw);
   std::free(raw_off);
   return g;

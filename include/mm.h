@@ -79,7 +79,9 @@ enum {
   MM_SYMMETRIC = 2u,  /* caller asserts every entry (x,y) has its reverse (y,x);
                          enables lazy mate initialisation */
   MM_STATS = 4u,      /* run the instrumented kernels: counters for mm_get_stats */
-  MM_TIMING = 8u      /* record HIP events around each sweep launch (mm_get_timing) */
+  MM_TIMING = 8u,     /* record HIP events around each sweep launch (mm_get_timing) */
+  MM_CAPTURE = 16u    /* batches: capture one pass into a hipGraph at the first run
+                         for a given output and replay it afterwards */
 };
 
 /* How the higher endpoint v of an edge is taken (Algorithm 1, L13-14). */
@@ -190,6 +192,48 @@ mm_status mm_get_timing(mm_handle h, int64_t* count, double* total_ms, double* m
 /* Frees the host-side handle (and its timing events). Does not touch
    caller-owned memory. */
 void mm_destroy(mm_handle h);
+
+/* ------------------------------------------------------------------ batches
+ * Many independent graphs matched in one persistent launch. The graphs are
+ * concatenated: offsets_cat holds N+1 int64 positions into neighbors_cat
+ * (offsets_cat[0] = 0, offsets_cat[N] = M); the neighbour ids of graph g are
+ * local to it (0 .. n_g-1); vtx_off (host, num_graphs+1 entries, vtx_off[0] =
+ * 0) gives graph g the global vertices vtx_off[g] .. vtx_off[g+1]-1. The
+ * output match_out (device, N int32) receives, for every global vertex, the
+ * LOCAL id of its mate in its own graph, or -1. Each graph's result is a
+ * maximal matching of that graph, computed by the same sweep as mm_run.
+ */
+typedef struct mm_batch* mm_batch_handle;
+
+/* Workspace bytes for a batch (vtx_off: host). 0 if the arguments are invalid. */
+size_t mm_batch_workspace_bytes(int32_t num_graphs, const int64_t* vtx_off, const mm_tuning* t);
+
+/* Creates a batch handle: builds the work-item table (one item per wavefront
+   block of every graph) in the workspace and waits for it. Arrays are borrowed
+   like those of mm_create. flags: MM_VALIDATE | MM_SYMMETRIC | MM_STATS |
+   MM_CAPTURE. */
+mm_status mm_batch_create(const int64_t* offsets_cat, const int32_t* neighbors_cat,
+                          const int64_t* vtx_off, int32_t num_graphs, int64_t M, void* workspace,
+                          size_t workspace_bytes, uint32_t flags, const mm_tuning* tuning,
+                          void* stream, mm_batch_handle* out);
+
+/* Enqueues one pass over every graph of the batch on `stream`. With
+   MM_CAPTURE the pass is a hipGraph replay (captured at the first run with a
+   given match_out). The first run with a new match_out binds the graph
+   descriptors to it (a small synchronous upload). */
+mm_status mm_batch_run(mm_batch_handle h, void* stream, int32_t* match_out);
+
+/* As mm_sync, for a batch. */
+mm_status mm_batch_sync(mm_batch_handle h, void* stream);
+
+/* As mm_get_stats, for a batch created with MM_STATS. */
+mm_status mm_batch_get_stats(mm_batch_handle h, void* stream, mm_stats* out);
+
+/* Number of work items (wavefront blocks) of the batch; -1 for a null handle. */
+int64_t mm_batch_items(mm_batch_handle h);
+
+/* Frees the host-side handle and any captured graph. */
+void mm_batch_destroy(mm_batch_handle h);
 
 /* Thread-local description of the last non-OK status returned on this thread. */
 const char* mm_last_error(void);

@@ -15,7 +15,7 @@ from dataclasses import asdict, dataclass
 from . import _lib
 from ._lib import MMError  # noqa: F401
 
-__all__ = ["Graph", "Tuning", "MMError", "maximal_matching", "library_path", "version"]
+__all__ = ["Graph", "Batch", "Tuning", "MMError", "maximal_matching", "library_path", "version"]
 
 
 def library_path() -> str:
@@ -153,6 +153,83 @@ class Graph:
     def close(self) -> None:
         if getattr(self, "_h", None) is not None:
             _lib.load().mm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many graphs matched in one persistent launch (see mm_batch_* in mm.h).
+
+    offsets: int64 CUDA tensor of N+1 positions into `neighbors` (int32 CUDA
+    tensor of local ids); vtx_off: host sequence of num_graphs+1 vertex
+    offsets. run() returns the int32 tensor of LOCAL mates (-1 = unmatched).
+    ``capture=True`` replays a hipGraph of the pass after the first run.
+    """
+
+    def __init__(self, offsets, neighbors, vtx_off, *, symmetric: bool = False,
+                 validate: bool = False, stats: bool = False, capture: bool = False,
+                 tuning: Tuning | None = None, stream=None):
+        import numpy as np
+        import torch
+        lib = _lib.load()
+        import torch as _t
+        if offsets.dtype != _t.int64:
+            raise ValueError("batch offsets must be int64")
+        _check_graph_tensors(offsets, neighbors)
+        self._vtx = np.ascontiguousarray(np.asarray(vtx_off, dtype=np.int64))
+        self.num_graphs = int(self._vtx.shape[0]) - 1
+        self.N = int(self._vtx[-1])
+        if offsets.numel() != self.N + 1:
+            raise ValueError("offsets must have vtx_off[-1] + 1 entries")
+        self.offsets, self.neighbors = offsets, neighbors
+        self.tuning = tuning if tuning is not None else Tuning.default()
+        ct = self.tuning.to_c()
+        nbytes = lib.mm_batch_workspace_bytes(self.num_graphs, ctypes.c_void_p(self._vtx.ctypes.data),
+                                              ctypes.byref(ct))
+        if nbytes == 0:
+            raise MMError(_lib.MM_ERR_INVALID_ARG, "invalid vtx_off or tuning")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=offsets.device)
+        aligned = (self.workspace.data_ptr() + 255) // 256 * 256
+        flags = ((_lib.MM_VALIDATE if validate else 0) | (_lib.MM_SYMMETRIC if symmetric else 0)
+                 | (_lib.MM_STATS if stats else 0) | (_lib.MM_CAPTURE if capture else 0))
+        h = ctypes.c_void_p()
+        _lib.check(lib.mm_batch_create(ctypes.c_void_p(offsets.data_ptr()),
+                                       ctypes.c_void_p(neighbors.data_ptr()),
+                                       ctypes.c_void_p(self._vtx.ctypes.data), self.num_graphs,
+                                       neighbors.numel(), ctypes.c_void_p(aligned), nbytes, flags,
+                                       ctypes.byref(ct), _stream_ptr(stream), ctypes.byref(h)))
+        self._h = h
+        self.device = offsets.device
+
+    @property
+    def items(self) -> int:
+        return int(_lib.load().mm_batch_items(self._h))
+
+    def run(self, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty(self.N, dtype=torch.int32, device=self.device)
+        elif out.dtype != torch.int32 or out.numel() != self.N or not out.is_contiguous():
+            raise ValueError("out must be a contiguous int32 tensor of N entries")
+        _lib.check(_lib.load().mm_batch_run(self._h, _stream_ptr(stream), ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def sync(self, stream=None) -> None:
+        _lib.check(_lib.load().mm_batch_sync(self._h, _stream_ptr(stream)))
+
+    def stats(self, stream=None) -> dict:
+        s = _lib.mm_stats()
+        _lib.check(_lib.load().mm_batch_get_stats(self._h, _stream_ptr(stream), ctypes.byref(s)))
+        return {f: int(getattr(s, f)) for f, _ in _lib.mm_stats._fields_ if not f.startswith("reserved")}
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None:
+            _lib.load().mm_batch_destroy(self._h)
             self._h = None
 
     def __del__(self):

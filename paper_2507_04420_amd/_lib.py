@@ -30,7 +30,7 @@ STATUS_NAMES = {
 MM_OFF_I32, MM_OFF_I64 = 0, 1
 MM_LAYOUT_U8, MM_LAYOUT_U32, MM_LAYOUT_U2 = 0, 1, 2
 MM_PROTOCOL_CAS, MM_PROTOCOL_TWO_PHASE = 0, 1
-MM_VALIDATE, MM_SYMMETRIC, MM_STATS, MM_TIMING = 1, 2, 4, 8
+MM_VALIDATE, MM_SYMMETRIC, MM_STATS, MM_TIMING, MM_CAPTURE = 1, 2, 4, 8, 16
 
 
 class mm_tuning(ctypes.Structure):
@@ -72,6 +72,14 @@ SIGNATURES = {
     "mm_get_timing": (_I32, [_P, ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_double),
                              ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "mm_destroy": (None, [_P]),
+    "mm_batch_workspace_bytes": (_SZ, [_I32, _P, ctypes.POINTER(mm_tuning)]),
+    "mm_batch_create": (_I32, [_P, _P, _P, _I32, _I64, _P, _SZ, _U32, ctypes.POINTER(mm_tuning), _P,
+                               ctypes.POINTER(_P)]),
+    "mm_batch_run": (_I32, [_P, _P, _P]),
+    "mm_batch_sync": (_I32, [_P, _P]),
+    "mm_batch_get_stats": (_I32, [_P, _P, ctypes.POINTER(mm_stats)]),
+    "mm_batch_items": (_I64, [_P]),
+    "mm_batch_destroy": (None, [_P]),
     "mm_last_error": (ctypes.c_char_p, []),
     "mm_version": (ctypes.c_char_p, []),
 }

@@ -1,0 +1,59 @@
+// Descriptor-based batched sweep shared by the batch ABI and the serving loop.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "sweep.h"
+
+namespace mmb {
+
+// One graph of a batch. Pointers are based at the graph's first vertex: the
+// offsets index `nbr`, neighbour ids are local to the graph.
+struct GraphDesc {
+  const int64_t* off;
+  const int32_t* nbr;
+  int64_t n;
+  uint32_t* st;    // packed states, or null for the word layout
+  int32_t* mate;   // this graph's mate entries
+  uint32_t* hint;  // matched hint words, or null
+};
+
+// One wavefront block: sources vb .. vb+nv-1 of graph `desc`.
+struct WorkItem {
+  int32_t desc;
+  int32_t nv;
+  int64_t vb;
+};
+
+// Everything one pass of the batched sweep needs on the device.
+struct BatchPlan {
+  mmk::SweepParams params;
+  const GraphDesc* descs;
+  const WorkItem* items;
+  int64_t n_items;
+  uint32_t* queue;
+  unsigned long long* stats;
+  int32_t layout, protocol;
+  bool hint, lazy, stats_on;
+  int wg_size, num_cus;
+  int32_t* mate;  // base of all mate entries (N of them)
+  int64_t N;
+  uint32_t* st_base;
+  int64_t st_words;
+  uint32_t* hint_base;
+  int64_t hint_words;
+};
+
+// Enqueues one pass: fills, queue reset, persistent sweep, output fix-up.
+hipError_t enqueue_pass(const BatchPlan& bp, hipStream_t s);
+
+// Device check of a concatenated CSR (bits as for the single-graph check).
+hipError_t validate_batch(const int64_t* off, const int32_t* nbr, const int64_t* vtx_off_dev,
+                          int32_t num_graphs, int64_t N, int64_t M, uint32_t* flags,
+                          hipStream_t s);
+
+// 32-bit words of packed state for n vertices under `layout` (0 for words).
+int64_t state_words_for(int64_t n, int32_t layout);
+
+}  // namespace mmb

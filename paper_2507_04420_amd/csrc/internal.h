@@ -22,6 +22,9 @@ mm_status check_tuning(const mm_tuning& t);
 size_t state_bytes(int64_t n, const mm_tuning& t);
 size_t hint_bytes(int64_t n, const mm_tuning& t);
 
+// Copies the raw device counters (sweep.h order) into the ABI struct.
+void stats_from_counters(const unsigned long long* c, mm_stats* out);
+
 // Control block at the start of every workspace: error word at 0, counters
 // at kStatsOffset, a work-queue counter at kQueueOffset.
 constexpr size_t kCtrlBytes = 4096;

@@ -69,6 +69,23 @@ size_t hint_bytes(int64_t n, const mm_tuning& t) {
   return t.hint ? round_up((size_t)((n + 31) / 32) * 4, 256) : 0;
 }
 
+void stats_from_counters(const unsigned long long* c, mm_stats* out) {
+  std::memset(out, 0, sizeof(*out));
+  out->sources = c[S_SOURCES];
+  out->sources_skipped = c[S_SKIPPED];
+  out->touched = c[S_TOUCHED];
+  out->assist_reads = c[S_ASSIST];
+  out->reserve_attempts = c[S_RES_ATT];
+  out->reserve_conflicts = c[S_RES_CONF];
+  out->reserve_matched = c[S_RES_MCHD];
+  out->match_attempts = c[S_MAT_ATT];
+  out->match_conflicts = c[S_MAT_CONF];
+  out->match_matched = c[S_MAT_MCHD];
+  out->word_retries = c[S_WORD_RETRY];
+  out->pairs = c[S_PAIRS];
+  out->loop_trips = c[S_TRIPS];
+}
+
 }  // namespace mmi
 
 using mmi::check_tuning;
@@ -126,8 +143,10 @@ __global__ __launch_bounds__(256) void sweep_kernel(SweepParams p, const OffT* _
   const int64_t vb = wave * p.wave_vertices;
   if (vb >= n) return;
   const int64_t nv = (n - vb < p.wave_vertices) ? (n - vb) : p.wave_vertices;
+  __shared__ QSlot queues[4][kQueue];  // one ring per wavefront (wg_size <= 256)
   Counters<STATS> cnt;
-  sweep_block<OffT, Layout, HINT, LAZY, STATS>(p, off, nbr, L, vb, nv, cnt);
+  sweep_block<OffT, Layout, HINT, LAZY, STATS>(p, off, nbr, L, vb, nv, queues[threadIdx.x >> 6],
+                                               cnt);
   if (STATS) cnt.flush(stats);
 }
 
@@ -433,20 +452,7 @@ mm_status mm_get_stats(mm_handle g, void* stream, mm_stats* out) {
   unsigned long long c[16] = {};
   HIP_TRY(hipMemcpyAsync(c, g->ws + kStatsOffset, sizeof(c), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  std::memset(out, 0, sizeof(*out));
-  out->sources = c[S_SOURCES];
-  out->sources_skipped = c[S_SKIPPED];
-  out->touched = c[S_TOUCHED];
-  out->assist_reads = c[S_ASSIST];
-  out->reserve_attempts = c[S_RES_ATT];
-  out->reserve_conflicts = c[S_RES_CONF];
-  out->reserve_matched = c[S_RES_MCHD];
-  out->match_attempts = c[S_MAT_ATT];
-  out->match_conflicts = c[S_MAT_CONF];
-  out->match_matched = c[S_MAT_MCHD];
-  out->word_retries = c[S_WORD_RETRY];
-  out->pairs = c[S_PAIRS];
-  out->loop_trips = c[S_TRIPS];
+  mmi::stats_from_counters(c, out);
   return MM_OK;
 }
 

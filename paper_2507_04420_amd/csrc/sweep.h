@@ -2,10 +2,13 @@
 //
 // Work decomposition. Each wavefront owns a block of consecutive source
 // vertices (the GPU form of the paper's blocks of consecutive vertices,
-// Section IV-C). Every lane works on one source at a time; a lane that
-// finishes takes the block's next source (ballot + mbcnt hand-out), so lanes
-// stay busy whatever the spread of scan lengths. The hardware dispatcher hands
-// blocks to the CUs as earlier ones retire.
+// Section IV-C). A wavefront-level front end reads the block 64 sources at a
+// time (offsets and state, one coalesced load per lane), drops the sources
+// that need no scan (no entries, or already matched: Fig. 6g) and queues the
+// rest in LDS. Every lane works on one source at a time and takes the next
+// queued source when it finishes, so lanes stay busy whatever the spread of
+// scan lengths, and skipped sources cost no lane any loop trip. The hardware
+// dispatcher hands blocks to the CUs as earlier ones retire.
 //
 // Per lane, one source x at a time (Section II-B, CSR form):
 //   * skip x if it is already matched (Fig. 6g);
@@ -46,7 +49,6 @@ constexpr int kMaxW = 4;
 
 enum : int {
   P_IDLE = 0,  // needs a source
-  P_SRC,       // offsets and source state requested
   P_IDS,       // next W neighbour ids requested
   P_STS,       // states of the buffered ids requested
   P_RES,       // reserve(u) issued (Alg. 1 L11)
@@ -102,6 +104,14 @@ __device__ __forceinline__ int64_t readlane64(int64_t v, int l) {
   return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
+// One queued source of a wavefront's front end (kept in LDS).
+struct QSlot {
+  int64_t x, b, e;
+  uint32_t word;  // the filter word read for x (a first guess for a CAS on x)
+  uint32_t pad;
+};
+constexpr int kQueue = 128;  // ring entries per wavefront (power of two)
+
 __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                    __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
@@ -112,10 +122,12 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
 // its mate array and hint, all based at the graph's first vertex).
 // HINT: skip matched neighbours by the one-bit-per-vertex hint instead of the
 // state word.
+// q: this wavefront's LDS ring of kQueue slots.
 template <typename OffT, class Layout, bool HINT, bool LAZY, bool STATS>
 __device__ __forceinline__ void sweep_block(const SweepParams& a, const OffT* __restrict__ off,
                                             const int32_t* __restrict__ nbr, const Layout& L,
-                                            int64_t vb, int64_t nv, Counters<STATS>& cnt) {
+                                            int64_t vb, int64_t nv, QSlot* q,
+                                            Counters<STATS>& cnt) {
   const int lane = (int)(threadIdx.x & 63);
   const int W = a.scan_width;
   const bool disperse = a.disperse && nv == a.wave_vertices;
@@ -136,7 +148,16 @@ __device__ __forceinline__ void sweep_block(const SweepParams& a, const OffT* __
     return Layout::matched(word, y);
   };
 
-  int64_t handed = 0;  // wavefront-uniform hand-out cursor
+  auto source_of = [&](int64_t kk) -> int64_t {
+    return vb + (disperse ? (kk & 63) * stride + (kk >> 6) : kk);
+  };
+  // front end (wavefront-uniform): next hand-out index to read, the chunk
+  // whose offsets and states are in flight, and the LDS ring's cursors
+  int64_t chunk_next = 0, chunk_base = 0;
+  bool chunk_pending = false;
+  uint32_t q_head = 0, q_tail = 0;
+  int64_t cb_b = 0, cb_e = 0;  // this lane's source of the pending chunk
+  uint32_t cb_w = 0;
   int64_t trips = 0;
   int phase = P_IDLE;
   int64_t x = 0, i = 0, e = 0, u = 0, v = 0;
@@ -152,8 +173,7 @@ __device__ __forceinline__ void sweep_block(const SweepParams& a, const OffT* __
   // Results of the operations issued on a trip, one register per phase:
   // different lanes issue different phases on the same trip, and a shared
   // destination register would force a wait between them.
-  int64_t src_b = 0, src_e = 0;
-  uint32_t src_w = 0, res_w = 0, chk_u = 0, chk_v = 0, mat_w = 0, matw_w = 0, fin_w = 0;
+  uint32_t res_w = 0, chk_u = 0, chk_v = 0, mat_w = 0, matw_w = 0, fin_w = 0;
   // wavefront assist (uniform state)
   int asst = 0, al = 0;
   int64_t ai = 0, ae = 0, ax = 0;
@@ -198,23 +218,6 @@ __device__ __forceinline__ void sweep_block(const SweepParams& a, const OffT* __
     // waits for a register written on an earlier trip.
     __builtin_amdgcn_s_waitcnt(0x0f70);
     switch (phase) {
-      case P_SRC: {
-        const int64_t b = src_b, en = src_e;
-        xword = src_w;
-        if (b == en) {
-          if (LAZY) L.write_unmatched(x);  // no incident entry: never matched (symmetric input)
-          phase = P_IDLE;
-        } else if (filter_matched(xword, x)) {
-          if (STATS) cnt.add(S_SKIPPED, 1);
-          phase = P_IDLE;
-        } else {
-          i = b;
-          e = en;
-          steps = 0;
-          phase = P_IDS;
-        }
-        break;
-      }
       case P_IDS: {
         const int64_t rem = e - i;
         nids = rem < W ? (int)rem : W;
@@ -326,26 +329,74 @@ __device__ __forceinline__ void sweep_block(const SweepParams& a, const OffT* __
       asst = 0;
     }
 
-    // ---------------- hand the block's next sources to idle lanes
-    const uint64_t idle = __ballot(phase == P_IDLE);
-    if (idle) {
-      if (phase == P_IDLE) {
-        const int64_t kk = handed + lanes_below(idle);
-        if (kk < nv) {
-          x = vb + (disperse ? (kk & 63) * stride + (kk >> 6) : kk);
-          phase = P_SRC;
-          if (STATS) cnt.add(S_SOURCES, 1);
+    // ---------------- front end: consume the chunk read on the previous trip
+    if (chunk_pending) {
+      const int64_t kk = chunk_base + lane;
+      bool need = false;
+      int64_t xs = 0;
+      if (kk < nv) {
+        xs = source_of(kk);
+        if (STATS) cnt.add(S_SOURCES, 1);
+        if (cb_b == cb_e) {
+          if (LAZY) L.write_unmatched(xs);  // no incident entry: never matched (symmetric input)
+        } else if (filter_matched(cb_w, xs)) {
+          if (STATS) cnt.add(S_SKIPPED, 1);
         } else {
-          phase = P_DONE;
+          need = true;
         }
       }
-      handed += __popcll(idle);
+      const uint64_t nm = __ballot(need);
+      if (need) {
+        QSlot& slot = q[(q_tail + lanes_below(nm)) & (kQueue - 1)];
+        slot.x = xs;
+        slot.b = cb_b;
+        slot.e = cb_e;
+        slot.word = cb_w;
+      }
+      q_tail += (uint32_t)__popcll(nm);
+      chunk_pending = false;
     }
-    if (!__ballot(phase != P_DONE) && asst == 0) break;
+
+    // ---------------- hand queued sources to idle lanes
+    const uint64_t idle = __ballot(phase == P_IDLE);
+    const uint32_t avail = q_tail - q_head;
+    if (idle && avail) {
+      __builtin_amdgcn_wave_barrier();
+      if (phase == P_IDLE) {
+        const uint32_t r = lanes_below(idle);
+        if (r < avail) {
+          const QSlot slot = q[(q_head + r) & (kQueue - 1)];
+          x = slot.x;
+          i = slot.b;
+          e = slot.e;
+          xword = HINT ? 0u : slot.word;
+          steps = 0;
+          phase = P_IDS;
+        }
+      }
+      const uint32_t ni = (uint32_t)__popcll(idle);
+      q_head += ni < avail ? ni : avail;
+    }
+    const bool front_done = chunk_next >= nv && !chunk_pending && q_head == q_tail;
+    if (front_done && !__ballot(phase != P_IDLE) && asst == 0) break;
     if (++trips > cap) {
       if (phase == P_MAT || phase == P_MATW) L.release(u);  // holding u
       if (lane == 0) atomicOr(a.err, 1u);
       break;
+    }
+
+    // ---------------- front end: read the next 64 sources when the queue runs low
+    if (!chunk_pending && chunk_next < nv && q_tail - q_head < 64) {
+      chunk_base = chunk_next;
+      chunk_next += 64;
+      const int64_t kk = chunk_base + lane;
+      if (kk < nv) {
+        const int64_t xs = source_of(kk);
+        cb_b = (int64_t)off[xs];
+        cb_e = (int64_t)off[xs + 1];
+        cb_w = filter_word(xs);
+      }
+      chunk_pending = true;
     }
 
     // ---------------- wavefront assist: issue
@@ -370,11 +421,6 @@ __device__ __forceinline__ void sweep_block(const SweepParams& a, const OffT* __
 
     // ---------------- issue one operation per lane
     switch (phase) {
-      case P_SRC:
-        src_b = (int64_t)off[x];
-        src_e = (int64_t)off[x + 1];
-        src_w = filter_word(x);
-        break;
       case P_IDS:
 #pragma unroll
         for (int j = 0; j < kMaxW; ++j)

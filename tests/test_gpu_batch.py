@@ -1,0 +1,132 @@
+"""GPU parity of the batched path (one persistent launch over many graphs).
+
+Every member graph's slice of the output is checked against the oracle on
+that graph alone; graphs with a unique maximal matching must match exactly.
+The hipGraph-captured pass is replayed several times with host work and
+synchronisation in between, and every replay is checked.
+"""
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2507_04420_amd as mm  # noqa: E402
+from paper_2507_04420_amd import _lib  # noqa: E402
+
+TUNINGS = {
+    "u8_cas": mm.Tuning(lazy_init=0),
+    "u32_cas": mm.Tuning(layout=_lib.MM_LAYOUT_U32, lazy_init=0),
+    "u2_two_hint": mm.Tuning(layout=_lib.MM_LAYOUT_U2, protocol=_lib.MM_PROTOCOL_TWO_PHASE, hint=1),
+    "u32_two_lazy": mm.Tuning(layout=_lib.MM_LAYOUT_U32, protocol=_lib.MM_PROTOCOL_TWO_PHASE),
+    "u8_small": mm.Tuning(wave_vertices=64, wg_size=64, assist_after=2),
+}
+
+
+def check_members(mix, mate):
+    for g in range(mix.num_graphs):
+        v0, v1 = int(mix.vtx_off[g]), int(mix.vtx_off[g + 1])
+        sub = mix.member(g)
+        c = oracle.check(sub, mate[v0:v1])
+        assert c.violations == 0, (g, c)
+        assert 2 * c.size >= oracle.sgmm(sub).pairs
+
+
+def mixture_small(G=40, seed=3):
+    return graphgen.mixture(G, seed=seed, nmin=50, nmax=5000)
+
+
+@pytest.mark.parametrize("name", sorted(TUNINGS))
+def test_batch_mixture(name):
+    mix = mixture_small()
+    off = torch.from_numpy(mix.off).cuda()
+    nbr = torch.from_numpy(mix.nbr).cuda()
+    b = mm.Batch(off, nbr, mix.vtx_off, symmetric=True, validate=True, tuning=TUNINGS[name])
+    out = b.run()
+    b.sync()
+    check_members(mix, out.cpu().numpy())
+
+
+@pytest.mark.parametrize("name", ["u8_cas", "u2_two_hint"])
+def test_batch_capture_replays(name):
+    mix = mixture_small(G=30, seed=5)
+    off = torch.from_numpy(mix.off).cuda()
+    nbr = torch.from_numpy(mix.nbr).cuda()
+    b = mm.Batch(off, nbr, mix.vtx_off, symmetric=True, capture=True, tuning=TUNINGS[name])
+    out = torch.empty(mix.n, dtype=torch.int32, device="cuda")
+    for rep in range(4):
+        out.fill_(12345)  # eager work between replays
+        b.run(out)
+        b.sync()
+        torch.cuda.synchronize()
+        check_members(mix, out.cpu().numpy())
+    # a second output buffer re-binds and re-captures
+    out2 = b.run()
+    b.sync()
+    check_members(mix, out2.cpu().numpy())
+
+
+def test_batch_unique_results_and_edge_cases():
+    # members: disjoint edges (unique), isolated vertices, a single vertex,
+    # an empty graph (0 vertices), a triangle
+    parts = [graphgen.from_edges(8, [(0, 1), (2, 3), (4, 5), (6, 7)]),
+             graphgen.from_edges(5, np.zeros((0, 2))),
+             graphgen.from_edges(1, np.zeros((0, 2))),
+             graphgen.from_edges(0, np.zeros((0, 2))),
+             graphgen.from_edges(3, [(0, 1), (1, 2), (0, 2)])]
+    vtx = np.cumsum([0] + [p.n for p in parts])
+    eoff = np.cumsum([0] + [p.m for p in parts])
+    off = np.concatenate([p.off[:-1] + eoff[k] for k, p in enumerate(parts)] + [[eoff[-1]]]).astype(np.int64)
+    nbr = np.concatenate([p.nbr for p in parts]).astype(np.int32)
+    b = mm.Batch(torch.from_numpy(off).cuda(), torch.from_numpy(nbr).cuda(), vtx, symmetric=True,
+                 validate=True)
+    mate = b.run().cpu().numpy()
+    b.sync()
+    np.testing.assert_array_equal(mate[0:8], np.arange(8) ^ 1)
+    np.testing.assert_array_equal(mate[8:14], -1)
+    tri = mate[14:17]
+    assert sorted(tri.tolist()).count(-1) == 1 and oracle.check(parts[4], tri).ok
+
+
+def test_batch_matches_single_graph_path():
+    # the same graph alone through mm_run and inside a batch: both maximal,
+    # sizes within the alone-vs-mix tolerance
+    g = graphgen.rmat(14, seed=9)
+    mix = graphgen.concat([(graphgen.KIND_ER, 3000, 6.0)] * 3, seed=2)
+    parts = [g, mix.member(0), mix.member(1)]
+    vtx = np.cumsum([0] + [p.n for p in parts])
+    eoff = np.cumsum([0] + [p.m for p in parts])
+    off = np.concatenate([p.off[:-1] + eoff[k] for k, p in enumerate(parts)] + [[eoff[-1]]]).astype(np.int64)
+    nbr = np.concatenate([p.nbr for p in parts]).astype(np.int32)
+    b = mm.Batch(torch.from_numpy(off).cuda(), torch.from_numpy(nbr).cuda(), vtx, symmetric=True)
+    bm = b.run().cpu().numpy()
+    b.sync()
+    alone = mm.maximal_matching(torch.from_numpy(g.off).cuda(), torch.from_numpy(g.nbr).cuda(),
+                                symmetric=True).cpu().numpy()
+    c1, c2 = oracle.check(g, bm[:g.n]), oracle.check(g, alone)
+    assert c1.ok and c2.ok
+    assert abs(c1.size - c2.size) <= max(2, 0.01 * oracle.sgmm(g).pairs)
+
+
+def test_batch_validate_rejects_foreign_ids():
+    off = torch.tensor([0, 1, 2, 3], dtype=torch.int64, device="cuda")
+    nbr = torch.tensor([1, 0, 2], dtype=torch.int32, device="cuda")  # graph 1 has one vertex: id 2 is foreign
+    with pytest.raises(mm.MMError) as ei:
+        mm.Batch(off, nbr, [0, 2, 3], validate=True)
+    assert ei.value.status == _lib.MM_ERR_INVALID_GRAPH
+
+
+def test_batch_stats():
+    mix = mixture_small(G=12, seed=8)
+    b = mm.Batch(torch.from_numpy(mix.off).cuda(), torch.from_numpy(mix.nbr).cuda(), mix.vtx_off,
+                 symmetric=True, stats=True)
+    out = b.run()
+    b.sync()
+    st = b.stats()
+    mate = out.cpu().numpy()
+    check_members(mix, mate)
+    assert st["sources"] == mix.n
+    assert st["pairs"] == int((mate >= 0).sum()) // 2
