@@ -66,6 +66,94 @@ def cpu_baseline(csr, budget_s: float = 30.0):
     return res, t, len(times)
 
 
+def bench_batch(args, tun, dev):
+    """Batched matching of the 4096-graph mixture: one hipGraph-captured
+    persistent launch per pass, against one mm_run per graph on one stream
+    (same kernels, same tuning, caches warm)."""
+    import torch
+    import graphgen
+    import oracle
+    import paper_2507_04420_amd as mm
+
+    t0 = time.perf_counter()
+    mix = graphgen.mixture(args.batch_graphs, seed=args.seed)
+    G = mix.num_graphs
+    log("generated batch mixture: %d graphs, N=%d M=%d in %.1fs" % (G, mix.n, mix.m,
+                                                                    time.perf_counter() - t0))
+    off = torch.from_numpy(mix.off).to(dev)
+    nbr = torch.from_numpy(mix.nbr).to(dev)
+    b = mm.Batch(off, nbr, mix.vtx_off, symmetric=True, validate=True, capture=True, tuning=tun)
+    out = torch.empty(mix.n, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        b.run(out)
+    b.sync()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = max(3, args.steps // 2)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(reps):
+        b.run(out)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    b.sync()
+    ms_batched = ev0.elapsed_time(ev1) / reps
+    mate_b = out.cpu().numpy()
+
+    # per-graph launches: one handle per member graph, outputs are views of one tensor
+    vtx = mix.vtx_off
+    offs, handles = [], []
+    out2 = torch.empty(mix.n, dtype=torch.int32, device=dev)
+    views = []
+    for g in range(G):
+        v0, v1 = int(vtx[g]), int(vtx[g + 1])
+        e0, e1 = int(mix.off[v0]), int(mix.off[v1])
+        og = (off[v0:v1 + 1] - e0).contiguous()
+        offs.append(og)
+        handles.append(mm.Graph(og, nbr[e0:e1], symmetric=True, tuning=tun))
+        views.append(out2[v0:v1])
+    for h, o in zip(handles, views):
+        h.run(o)
+    torch.cuda.synchronize()
+    rounds = 3
+    ev0.record(stream)
+    for _ in range(rounds):
+        for h, o in zip(handles, views):
+            h.run(o)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_per_graph_total = ev0.elapsed_time(ev1) / rounds
+    mate_p = out2.cpu().numpy()
+
+    bad_b = bad_p = 0
+    for g in range(G):
+        sub = mix.member(g)
+        v0, v1 = int(vtx[g]), int(vtx[g + 1])
+        bad_b += oracle.check(sub, mate_b[v0:v1]).violations
+        bad_p += oracle.check(sub, mate_p[v0:v1]).violations
+    items = b.items
+    for h in handles:
+        h.close()
+    b.close()
+    res = {
+        "graphs": G,
+        "N": int(mix.n),
+        "M": int(mix.m),
+        "work_items": int(items),
+        "ms_batched": round(ms_batched, 4),
+        "graphs_per_s_batched": round(G / (ms_batched / 1e3), 1),
+        "ms_per_graph_launches": round(ms_per_graph_total, 4),
+        "graphs_per_s_per_graph": round(G / (ms_per_graph_total / 1e3), 1),
+        "ratio": round(ms_per_graph_total / ms_batched, 3),
+        "gedges_per_s_batched": round(mix.m / (ms_batched / 1e3) / 1e9, 2),
+        "checker_violations_batched": int(bad_b),
+        "checker_violations_per_graph": int(bad_p),
+    }
+    log("batch: %.3f ms batched vs %.3f ms per-graph launches (x%.2f), violations %d/%d" % (
+        ms_batched, ms_per_graph_total, res["ratio"], bad_b, bad_p))
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -73,13 +161,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="rmat27")
     ap.add_argument("--seed", type=int, default=1)
-    ap.add_argument("--layout", default="u8", choices=["u8", "u32"])
-    ap.add_argument("--lazy", type=int, default=1)
+    ap.add_argument("--layout", default=None, choices=["u8", "u32", "u2"])
+    ap.add_argument("--lazy", type=int, default=None)
     ap.add_argument("--wave-vertices", type=int, default=None)
     ap.add_argument("--wg-size", type=int, default=None)
     ap.add_argument("--disperse", type=int, default=None)
     ap.add_argument("--assist-after", type=int, default=None)
     ap.add_argument("--no-stats", action="store_true")
+    ap.add_argument("--batch-graphs", type=int, default=4096)
+    ap.add_argument("--no-batch", action="store_true")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -107,8 +197,10 @@ def main():
     torch.cuda.synchronize()
 
     tun = mm.Tuning.default()
-    tun.layout = _lib.MM_LAYOUT_U8 if args.layout == "u8" else _lib.MM_LAYOUT_U32
-    tun.lazy_init = args.lazy if args.layout == "u8" else 0
+    if args.layout is not None:
+        tun.layout = {"u8": _lib.MM_LAYOUT_U8, "u32": _lib.MM_LAYOUT_U32, "u2": _lib.MM_LAYOUT_U2}[args.layout]
+    if args.lazy is not None:
+        tun.lazy_init = args.lazy
     if args.wave_vertices:
         tun.wave_vertices = args.wave_vertices
     if args.wg_size:
@@ -158,12 +250,15 @@ def main():
         gs.close()
         log("counters: %s" % counters)
 
+    batch = None if args.no_batch else bench_batch(args, tun, dev)
+
     n, m = csr.n, csr.m
     w = csr.off.dtype.itemsize
-    # Algorithmic bytes of one sweep launch (lazy U8 path): offsets, the ids a
-    # sequential pass must read, one state byte per source, one mate per vertex.
+    # Algorithmic bytes of one sweep launch: offsets w(n+1), the ids a
+    # sequential pass must read 4*T_seq, one state byte read per source n, one
+    # mate written per vertex 4n; the pass adds the state initialisation n.
     b_sweep = w * (n + 1) + 4 * t_seq + n + 4 * n
-    b_pass = b_sweep + n  # plus the state initialisation
+    b_pass = b_sweep + n
     sweep_s = sweep["mean_ms"] / 1e3
     achieved = b_sweep / sweep_s / 1e9 if sweep_s > 0 else 0.0
     value = m / (ms_per_step / 1e3) / 1e9
@@ -180,9 +275,7 @@ def main():
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
-        "config": dict(config, n=n, m=m, layout=args.layout, lazy_init=int(tun.lazy_init),
-                       wave_vertices=tun.wave_vertices, wg_size=tun.wg_size,
-                       disperse=tun.disperse, assist_after=tun.assist_after),
+        "config": dict(config, n=n, m=m, tuning={k: int(v) for k, v in vars(tun).items()}),
         "roofline": {
             "bound": "hbm",
             "kernel": "sweep_kernel",
@@ -206,6 +299,7 @@ def main():
         "checker": {"violations": chk.violations, "size": chk.size, "size_sgmm": ref.pairs,
                     "t_seq": t_seq},
         "counters": counters,
+        "batch": batch,
     }
     print(json.dumps(result), flush=True)
 

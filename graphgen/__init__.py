@@ -119,7 +119,7 @@ class CSR:
         """Member graph g of a mixture, as a standalone CSR."""
         v0, v1 = int(self.vtx_off[g]), int(self.vtx_off[g + 1])
         e0, e1 = int(self.off[v0]), int(self.off[v1])
-        return CSR((self.off[v0:v1 + 1] - e0).astype(np.int64), self.nbr[e0:e1].copy(),
+        return CSR((self.off[v0:v1 + 1] - e0).astype(np.int64), self.nbr[e0:e1],
                    name="%s[%d]" % (self.name, g))
 
 

@@ -29,14 +29,14 @@ def version() -> str:
 @dataclass
 class Tuning:
     """Launch and layout parameters (see mm_tuning in include/mm.h)."""
-    layout: int = _lib.MM_LAYOUT_U8
+    layout: int = _lib.MM_LAYOUT_U32
     protocol: int = _lib.MM_PROTOCOL_CAS
     hint: int = 0
     wg_size: int = 256
     wave_vertices: int = 1024
     disperse: int = 0
-    assist_after: int = 16
-    lazy_init: int = 1
+    assist_after: int = 64
+    lazy_init: int = 0
     scan_width: int = 4
     reserved_: int = 0
     iter_cap: int = 0

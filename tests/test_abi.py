@@ -37,16 +37,20 @@ def test_version_and_defaults():
     assert lib.mm_version().startswith(b"skipper-gfx950")
     t = _lib.mm_tuning()
     lib.mm_default_tuning(ctypes.byref(t))
-    assert t.layout == _lib.MM_LAYOUT_U8 and t.wg_size % 64 == 0 and t.wave_vertices % 64 == 0
+    assert t.layout in (_lib.MM_LAYOUT_U8, _lib.MM_LAYOUT_U32, _lib.MM_LAYOUT_U2)
+    assert t.wg_size % 64 == 0 and t.wave_vertices % 64 == 0
 
 
 def test_workspace_bytes():
     lib = _lib.load()
     t = _lib.mm_tuning()
     lib.mm_default_tuning(ctypes.byref(t))
+    t.layout = _lib.MM_LAYOUT_U8
     small = lib.mm_workspace_bytes(0, ctypes.byref(t))
     big = lib.mm_workspace_bytes(1 << 20, ctypes.byref(t))
     assert small > 0 and big >= small + (1 << 20) // 4 * 4
+    t.layout = _lib.MM_LAYOUT_U2
+    assert lib.mm_workspace_bytes(1 << 20, ctypes.byref(t)) == small + (1 << 20) // 4
     assert lib.mm_workspace_bytes(-1, ctypes.byref(t)) == 0
     assert lib.mm_workspace_bytes(1 << 31, ctypes.byref(t)) == 0
     t.layout = _lib.MM_LAYOUT_U32

@@ -18,11 +18,14 @@ import paper_2507_04420_amd as mm  # noqa: E402
 from paper_2507_04420_amd import _lib  # noqa: E402
 
 TUNINGS = {
-    "u8_cas": mm.Tuning(lazy_init=0),
-    "u32_cas": mm.Tuning(layout=_lib.MM_LAYOUT_U32, lazy_init=0),
-    "u2_two_hint": mm.Tuning(layout=_lib.MM_LAYOUT_U2, protocol=_lib.MM_PROTOCOL_TWO_PHASE, hint=1),
-    "u32_two_lazy": mm.Tuning(layout=_lib.MM_LAYOUT_U32, protocol=_lib.MM_PROTOCOL_TWO_PHASE),
-    "u8_small": mm.Tuning(wave_vertices=64, wg_size=64, assist_after=2),
+    "u8_cas": mm.Tuning(layout=_lib.MM_LAYOUT_U8, lazy_init=0),
+    "u32_cas": mm.Tuning(),
+    "u2_two_hint": mm.Tuning(layout=_lib.MM_LAYOUT_U2, protocol=_lib.MM_PROTOCOL_TWO_PHASE, hint=1,
+                             lazy_init=1),
+    "u32_two_lazy": mm.Tuning(layout=_lib.MM_LAYOUT_U32, protocol=_lib.MM_PROTOCOL_TWO_PHASE,
+                              lazy_init=1),
+    "u8_small": mm.Tuning(layout=_lib.MM_LAYOUT_U8, wave_vertices=64, wg_size=64, assist_after=2,
+                          lazy_init=1),
 }
 
 

@@ -30,19 +30,21 @@ from paper_2507_04420_amd import _lib  # noqa: E402
 U8, U32, U2 = _lib.MM_LAYOUT_U8, _lib.MM_LAYOUT_U32, _lib.MM_LAYOUT_U2
 CAS, TWO = _lib.MM_PROTOCOL_CAS, _lib.MM_PROTOCOL_TWO_PHASE
 TUNINGS = {
-    "u8_cas_lazy": mm.Tuning(),
-    "u8_cas_eager": mm.Tuning(lazy_init=0),
-    "u8_two_hint": mm.Tuning(protocol=TWO, hint=1),
-    "u8_two_eager_w1": mm.Tuning(protocol=TWO, lazy_init=0, scan_width=1),
+    "default": mm.Tuning(),
+    "u8_cas_lazy": mm.Tuning(layout=U8, lazy_init=1, assist_after=16),
+    "u8_cas_eager": mm.Tuning(layout=U8, lazy_init=0),
+    "u8_two_hint": mm.Tuning(layout=U8, protocol=TWO, hint=1, lazy_init=1),
+    "u8_two_eager_w1": mm.Tuning(layout=U8, protocol=TWO, lazy_init=0, scan_width=1),
     "u32_cas": mm.Tuning(layout=U32, lazy_init=0),
     "u32_cas_hint_w1": mm.Tuning(layout=U32, hint=1, scan_width=1),
-    "u32_two_lazy_hint": mm.Tuning(layout=U32, protocol=TWO, hint=1),
+    "u32_two_lazy_hint": mm.Tuning(layout=U32, protocol=TWO, hint=1, lazy_init=1),
     "u32_two_eager": mm.Tuning(layout=U32, protocol=TWO, lazy_init=0, scan_width=3),
-    "u8_disperse": mm.Tuning(disperse=1, protocol=TWO),
-    "u8_small_blocks": mm.Tuning(wg_size=64, wave_vertices=64, assist_after=2),
+    "u8_disperse": mm.Tuning(layout=U8, disperse=1, protocol=TWO, lazy_init=1),
+    "u8_small_blocks": mm.Tuning(layout=U8, wg_size=64, wave_vertices=64, assist_after=2,
+                                 lazy_init=1),
     "u32_no_assist": mm.Tuning(layout=U32, protocol=TWO, assist_after=0, hint=1),
     "u2_two_eager": mm.Tuning(layout=U2, protocol=TWO, lazy_init=0),
-    "u2_two_lazy": mm.Tuning(layout=U2, protocol=TWO, scan_width=2),
+    "u2_two_lazy": mm.Tuning(layout=U2, protocol=TWO, scan_width=2, lazy_init=1),
     "u2_cas_hint": mm.Tuning(layout=U2, protocol=CAS, hint=1, lazy_init=0),
 }
 
