@@ -112,7 +112,9 @@ typedef struct {
                             of a separate fill (needs MM_SYMMETRIC; not with
                             MM_LAYOUT_U32 + MM_PROTOCOL_CAS, where it is implicit) */
   int32_t scan_width;    /* neighbour ids a lane reads per scan step: 1..8 */
-  int32_t reserved_;     /* must be 0 */
+  int32_t stream_loads;  /* 1: read offsets and neighbour ids with non-temporal loads,
+                            so that their lines are evicted first and the state (or
+                            hint) lines stay in L2 longer */
   int64_t iter_cap;      /* loop-trip budget per wavefront; 0 = default of
                             65536 + 8 x (neighbour entries of its block);
                             exceeding it raises MM_ERR_NO_PROGRESS */
@@ -234,6 +236,18 @@ int64_t mm_batch_items(mm_batch_handle h);
 
 /* Frees the host-side handle and any captured graph. */
 void mm_batch_destroy(mm_batch_handle h);
+
+/* ------------------------------------------------------------------ checks
+ * Device verification of a mate array against the graph of a handle
+ * (Section II-B's two conditions plus well-formedness). Waits for `stream`.
+ * counts (host, 6 entries): [0] mates out of [-1, n); [1] vertices matched to
+ * themselves; [2] asymmetric mates (mate[mate[x]] != x); [3] mates that are
+ * not an edge in either list; [4] entries (x, y), x != y, with both ends
+ * unmatched; [5] vertices whose mate is in [0, n). A maximal matching has counts[0..4] == 0.
+ * For a batch, ids are local to each graph.
+ */
+mm_status mm_check(mm_handle h, void* stream, const int32_t* match, int64_t* counts);
+mm_status mm_batch_check(mm_batch_handle h, void* stream, const int32_t* match, int64_t* counts);
 
 /* Thread-local description of the last non-OK status returned on this thread. */
 const char* mm_last_error(void);

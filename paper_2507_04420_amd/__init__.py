@@ -38,7 +38,7 @@ class Tuning:
     assist_after: int = 64
     lazy_init: int = 0
     scan_width: int = 4
-    reserved_: int = 0
+    stream_loads: int = 0
     iter_cap: int = 0
 
     @classmethod
@@ -77,6 +77,21 @@ def _check_graph_tensors(offsets, neighbors):
     if offsets.numel() < 1:
         raise ValueError("offsets needs n+1 >= 1 entries")
     return off_type
+
+
+CHECK_FIELDS = ("out_of_range", "self_mate", "asymmetric", "not_edge", "uncovered", "matched")
+
+
+def _check_mate(mate, n: int) -> None:
+    import torch
+    if mate.dtype != torch.int32 or mate.numel() != n or not mate.is_contiguous() or not mate.is_cuda:
+        raise ValueError("mate must be a contiguous int32 GPU tensor of %d entries" % n)
+
+
+def _check_result(c) -> dict:
+    r = {f: int(c[i]) for i, f in enumerate(CHECK_FIELDS)}
+    r["ok"] = all(r[f] == 0 for f in CHECK_FIELDS[:5])
+    return r
 
 
 class Graph:
@@ -146,6 +161,15 @@ class Graph:
         n = cnt.value
         return {"count": n, "total_ms": tot.value, "mean_ms": tot.value / n if n else 0.0,
                 "min_ms": lo.value, "max_ms": hi.value}
+
+    def check(self, mate, stream=None) -> dict:
+        """Device verification of a mate tensor (mm_check): violation counts
+        and ``ok`` (True iff the mates form a maximal matching)."""
+        _check_mate(mate, self.n)
+        c = (ctypes.c_int64 * 6)()
+        _lib.check(_lib.load().mm_check(self.handle, _stream_ptr(stream),
+                                         ctypes.c_void_p(mate.data_ptr()), c))
+        return _check_result(c)
 
     def reset_stats(self, stream=None) -> None:
         _lib.check(_lib.load().mm_reset_stats(self.handle, _stream_ptr(stream)))
@@ -221,6 +245,15 @@ class Batch:
 
     def sync(self, stream=None) -> None:
         _lib.check(_lib.load().mm_batch_sync(self._h, _stream_ptr(stream)))
+
+    def check(self, mate, stream=None) -> dict:
+        """Device verification of a mate tensor of local ids (mm_batch_check),
+        summed over the graphs of the batch."""
+        _check_mate(mate, self.N)
+        c = (ctypes.c_int64 * 6)()
+        _lib.check(_lib.load().mm_batch_check(self._h, _stream_ptr(stream),
+                                         ctypes.c_void_p(mate.data_ptr()), c))
+        return _check_result(c)
 
     def stats(self, stream=None) -> dict:
         s = _lib.mm_stats()

@@ -44,7 +44,7 @@ class mm_tuning(ctypes.Structure):
         ("assist_after", ctypes.c_int32),
         ("lazy_init", ctypes.c_int32),
         ("scan_width", ctypes.c_int32),
-        ("reserved_", ctypes.c_int32),
+        ("stream_loads", ctypes.c_int32),
         ("iter_cap", ctypes.c_int64),
     ]
 
@@ -80,6 +80,8 @@ SIGNATURES = {
     "mm_batch_get_stats": (_I32, [_P, _P, ctypes.POINTER(mm_stats)]),
     "mm_batch_items": (_I64, [_P]),
     "mm_batch_destroy": (None, [_P]),
+    "mm_check": (_I32, [_P, _P, _P, ctypes.POINTER(_I64)]),
+    "mm_batch_check": (_I32, [_P, _P, _P, ctypes.POINTER(_I64)]),
     "mm_last_error": (ctypes.c_char_p, []),
     "mm_version": (ctypes.c_char_p, []),
 }

@@ -6,6 +6,8 @@
 
 #include "sweep.h"
 
+struct mm_batch;
+
 namespace mmb {
 
 // One graph of a batch. Pointers are based at the graph's first vertex: the
@@ -55,5 +57,17 @@ hipError_t validate_batch(const int64_t* off, const int32_t* nbr, const int64_t*
 
 // 32-bit words of packed state for n vertices under `layout` (0 for words).
 int64_t state_words_for(int64_t n, int32_t layout);
+
+// What the device check needs from a batch handle.
+struct BatchInfo {
+  const int64_t* off;
+  const int32_t* nbr;
+  int32_t G;
+  int64_t N;
+  uint8_t* ws;
+  int64_t* vtx_dev;         // device scratch for the vertex-offset table
+  const int64_t* vtx_host;  // host copy of the table
+};
+BatchInfo batch_info(const mm_batch* b);
 
 }  // namespace mmb

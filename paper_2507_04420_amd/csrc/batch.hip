@@ -235,7 +235,7 @@ int64_t state_words_for(int64_t n, int32_t layout) {
 namespace {
 
 struct BatchLayout {  // byte offsets of the workspace pieces after the control block
-  size_t descs, items, st, hint, total;
+  size_t descs, items, vtx, st, hint, total;
   int64_t n_items, st_words, hint_words;
 };
 
@@ -257,6 +257,8 @@ bool plan_layout(int32_t G, const int64_t* vtx_off, const mm_tuning& t, BatchLay
   off += round_up(sizeof(mmb::GraphDesc) * (size_t)(G > 0 ? G : 1), 256);
   L.items = off;
   off += round_up(sizeof(mmb::WorkItem) * (size_t)(n_items > 0 ? n_items : 1), 256);
+  L.vtx = off;
+  off += round_up(sizeof(int64_t) * (size_t)(G + 1), 256);
   L.st = off;
   off += round_up((size_t)st_words * 4, 256);
   L.hint = off;
@@ -342,11 +344,7 @@ mm_status mm_batch_create(const int64_t* offsets_cat, const int32_t* neighbors_c
   uint8_t* ws = static_cast<uint8_t*>(workspace);
   HIP_TRY(hipMemsetAsync(ws, 0, kCtrlBytes, s));
   if (flags & MM_VALIDATE) {
-    // the vertex-offset table goes to the item area for the duration of the check
-    if (lay.st - lay.items < sizeof(int64_t) * (size_t)(num_graphs + 1) && lay.total - lay.items <
-        sizeof(int64_t) * (size_t)(num_graphs + 1))
-      return fail(MM_ERR_OUT_OF_MEMORY, "workspace too small to validate");
-    int64_t* vdev = reinterpret_cast<int64_t*>(ws + lay.items);
+    int64_t* vdev = reinterpret_cast<int64_t*>(ws + lay.vtx);
     HIP_TRY(hipMemcpyAsync(vdev, vtx_off, sizeof(int64_t) * (num_graphs + 1), hipMemcpyHostToDevice, s));
     uint32_t* f = reinterpret_cast<uint32_t*>(ws);
     HIP_TRY(mmb::validate_batch(offsets_cat, neighbors_cat, vdev, num_graphs, N, M, f, s));
@@ -420,6 +418,7 @@ mm_status mm_batch_create(const int64_t* offsets_cat, const int32_t* neighbors_c
   p.params.disperse = t.disperse;
   p.params.assist_after = t.assist_after;
   p.params.scan_width = t.scan_width;
+  p.params.stream_loads = t.stream_loads;
   p.params.iter_cap = t.iter_cap;
   p.params.err = reinterpret_cast<uint32_t*>(ws);
   p.descs = reinterpret_cast<const mmb::GraphDesc*>(ws + lay.descs);
@@ -508,6 +507,24 @@ mm_status mm_batch_get_stats(mm_batch_handle b, void* stream, mm_stats* out) {
 }
 
 int64_t mm_batch_items(mm_batch_handle b) { return b ? b->plan.n_items : -1; }
+
+}  // extern "C"
+
+namespace mmb {
+BatchInfo batch_info(const mm_batch* b) {
+  BatchInfo i;
+  i.off = b->off;
+  i.nbr = b->nbr;
+  i.G = b->G;
+  i.N = b->N;
+  i.ws = b->ws;
+  i.vtx_dev = reinterpret_cast<int64_t*>(b->ws + b->lay.vtx);
+  i.vtx_host = b->vtx_off.data();
+  return i;
+}
+}  // namespace mmb
+
+extern "C" {
 
 void mm_batch_destroy(mm_batch_handle b) {
   if (!b) return;

@@ -22,14 +22,23 @@ mm_status check_tuning(const mm_tuning& t);
 size_t state_bytes(int64_t n, const mm_tuning& t);
 size_t hint_bytes(int64_t n, const mm_tuning& t);
 
+// Accessors of a single-graph handle (defined with the handle).
+int64_t handle_n(const mm_graph* h);
+int handle_off64(const mm_graph* h);
+const void* handle_off(const mm_graph* h);
+const int32_t* handle_nbr(const mm_graph* h);
+uint8_t* handle_ws(const mm_graph* h);
+
 // Copies the raw device counters (sweep.h order) into the ABI struct.
 void stats_from_counters(const unsigned long long* c, mm_stats* out);
 
 // Control block at the start of every workspace: error word at 0, counters
-// at kStatsOffset, a work-queue counter at kQueueOffset.
+// at kStatsOffset, a work-queue counter at kQueueOffset, the six counters of
+// the device check at kCheckOffset.
 constexpr size_t kCtrlBytes = 4096;
 constexpr size_t kStatsOffset = 256;
 constexpr size_t kQueueOffset = 1024;
+constexpr size_t kCheckOffset = 2048;
 
 }  // namespace mmi
 

@@ -54,7 +54,8 @@ mm_status check_tuning(const mm_tuning& t) {
     return fail(MM_ERR_INVALID_ARG, "tuning.lazy_init must be 0 or 1");
   if (t.scan_width < 1 || t.scan_width > kMaxW)
     return fail(MM_ERR_INVALID_ARG, "tuning.scan_width must be in [1, %d]", kMaxW);
-  if (t.reserved_ != 0) return fail(MM_ERR_INVALID_ARG, "tuning.reserved_ must be 0");
+  if (t.stream_loads != 0 && t.stream_loads != 1)
+    return fail(MM_ERR_INVALID_ARG, "tuning.stream_loads must be 0 or 1");
   if (t.iter_cap < 0) return fail(MM_ERR_INVALID_ARG, "tuning.iter_cap must be >= 0");
   return MM_OK;
 }
@@ -200,6 +201,14 @@ struct mm_graph {
   }
 };
 
+namespace mmi {
+int64_t handle_n(const mm_graph* h) { return h->n; }
+int handle_off64(const mm_graph* h) { return h->off64; }
+const void* handle_off(const mm_graph* h) { return h->off; }
+const int32_t* handle_nbr(const mm_graph* h) { return h->nbr; }
+uint8_t* handle_ws(const mm_graph* h) { return h->ws; }
+}  // namespace mmi
+
 namespace {
 
 SweepParams make_params(const mm_graph* g) {
@@ -208,6 +217,7 @@ SweepParams make_params(const mm_graph* g) {
   p.disperse = g->tun.disperse;
   p.assist_after = g->tun.assist_after;
   p.scan_width = g->tun.scan_width;
+  p.stream_loads = g->tun.stream_loads;
   p.iter_cap = g->tun.iter_cap;
   p.err = reinterpret_cast<uint32_t*>(g->ws);
   return p;

@@ -68,6 +68,7 @@ struct SweepParams {
   int32_t disperse;
   int32_t assist_after;
   int32_t scan_width;      // 1..kMaxW
+  int32_t stream_loads;    // 1: offsets and ids through non-temporal loads
   int64_t iter_cap;        // 0: per-block default budget
   uint32_t* err;           // bit 0: loop-trip budget exceeded
 };
@@ -112,6 +113,13 @@ struct QSlot {
 };
 constexpr int kQueue = 128;  // ring entries per wavefront (power of two)
 
+// Loads of offsets and neighbour ids: non-temporal when streaming, so that
+// these once-read lines leave L2 before the state lines that are read again.
+template <typename T>
+__device__ __forceinline__ T ld_stream(const T* p, bool nt) {
+  return nt ? __builtin_nontemporal_load(p) : *p;
+}
+
 __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                    __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
@@ -130,6 +138,7 @@ __device__ __forceinline__ void sweep_block(const SweepParams& a, const OffT* __
                                             Counters<STATS>& cnt) {
   const int lane = (int)(threadIdx.x & 63);
   const int W = a.scan_width;
+  const bool nt = a.stream_loads != 0;
   const bool disperse = a.disperse && nv == a.wave_vertices;
   const int64_t stride = a.wave_vertices >> 6;
   // Loop-trip budget: explicit, or by default 65536 plus 8 per neighbour entry
@@ -392,8 +401,8 @@ __device__ __forceinline__ void sweep_block(const SweepParams& a, const OffT* __
       const int64_t kk = chunk_base + lane;
       if (kk < nv) {
         const int64_t xs = source_of(kk);
-        cb_b = (int64_t)off[xs];
-        cb_e = (int64_t)off[xs + 1];
+        cb_b = (int64_t)ld_stream(off + xs, nt);
+        cb_e = (int64_t)ld_stream(off + xs + 1, nt);
         cb_w = filter_word(xs);
       }
       chunk_pending = true;
@@ -414,7 +423,7 @@ __device__ __forceinline__ void sweep_block(const SweepParams& a, const OffT* __
         ae = readlane64(e, al);
         ax = readlane64(x, al);
         if (lane == al) phase = P_ASST;
-        aid = (ai + lane < ae) ? nbr[ai + lane] : -1;
+        aid = (ai + lane < ae) ? ld_stream(nbr + ai + lane, nt) : -1;
         asst = 1;
       }
     }
@@ -424,7 +433,7 @@ __device__ __forceinline__ void sweep_block(const SweepParams& a, const OffT* __
       case P_IDS:
 #pragma unroll
         for (int j = 0; j < kMaxW; ++j)
-          if (j < W) ids[j] = (i + j < e) ? nbr[i + j] : (int32_t)x;
+          if (j < W) ids[j] = (i + j < e) ? ld_stream(nbr + i + j, nt) : (int32_t)x;
         break;
       case P_STS:
 #pragma unroll

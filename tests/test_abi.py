@@ -101,7 +101,7 @@ def test_create_bad_tuning():
     assert st == _lib.MM_ERR_INVALID_ARG
     assert b"wave_vertices" in lib.mm_last_error()
     for field, bad in (("protocol", 2), ("hint", 3), ("scan_width", 0), ("scan_width", 9),
-                       ("layout", 5), ("reserved_", 1), ("iter_cap", -1)):
+                       ("layout", 5), ("stream_loads", 2), ("iter_cap", -1)):
         lib.mm_default_tuning(ctypes.byref(t))
         setattr(t, field, bad)
         st, _ = _create(lib, tuning=ctypes.pointer(t))
@@ -116,6 +116,9 @@ def test_null_handle_calls():
     assert lib.mm_reset_stats(None, None) == _lib.MM_ERR_INVALID_ARG
     s = _lib.mm_stats()
     assert lib.mm_get_stats(None, None, ctypes.byref(s)) == _lib.MM_ERR_INVALID_ARG
+    c = (ctypes.c_int64 * 6)()
+    assert lib.mm_check(None, None, None, c) == _lib.MM_ERR_INVALID_ARG
+    assert lib.mm_batch_check(None, None, None, c) == _lib.MM_ERR_INVALID_ARG
     lib.mm_destroy(None)
 
 

@@ -46,6 +46,7 @@ TUNINGS = {
     "u2_two_eager": mm.Tuning(layout=U2, protocol=TWO, lazy_init=0),
     "u2_two_lazy": mm.Tuning(layout=U2, protocol=TWO, scan_width=2, lazy_init=1),
     "u2_cas_hint": mm.Tuning(layout=U2, protocol=CAS, hint=1, lazy_init=0),
+    "u32_cas_hint_nt": mm.Tuning(layout=U32, hint=1, stream_loads=1),
 }
 
 
