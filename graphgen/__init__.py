@@ -14,6 +14,9 @@ Workload recipes (the paper's datasets are not available; these stand in):
 * ``grid(16384, 16384)``       4-neighbour mesh, row-major ids
 * ``mixture(G, seed)``         G graphs, type uniform over {ER, grid, R-MAT},
                                vertex counts log-uniform in [1e3, 2e5]
+* ``serve_pool(P, seed)``      P graphs of the same three types whose entry
+                               counts are log-uniform in [1e4, 5e7]: the
+                               resident graphs a stream of requests draws from
 """
 from __future__ import annotations
 
@@ -187,6 +190,30 @@ def member_spec(g: int, seed: int, nmin: float = 1e3, nmax: float = 2e5):
     else:
         param = 0.0
     return kind, n, param
+
+
+def serve_spec(i: int, seed: int, mmin: float = 1e4, mmax: float = 5e7):
+    """(kind, n, param) of serving-pool graph i: kind uniform over {ER, grid,
+    R-MAT}; a target entry count m log-uniform in [mmin, mmax]; ER average
+    degree uniform in [4, 32] with n = m / degree; a grid of about m / 4
+    vertices; R-MAT (edge factor 8) at scale clamp(round(log2(m / 16)), 6, 22)."""
+    kind = int(draw(seed, 5000 + i, 0) % 3)
+    lm = math.log(mmin) + _u01(seed, 5000 + i, 1) * (math.log(mmax) - math.log(mmin))
+    m = math.exp(lm)
+    if kind == KIND_ER:
+        deg = 4.0 + 28.0 * _u01(seed, 5000 + i, 2)
+        return kind, max(2, int(round(m / deg))), deg
+    if kind == KIND_RMAT:
+        sc = min(22, max(6, int(round(math.log2(m / 16.0)))))
+        return kind, 1 << sc, float(sc)
+    return kind, max(4, int(round(m / 4.0))), 0.0
+
+
+def serve_pool(num_graphs: int, seed: int = 1, mmin: float = 1e4, mmax: float = 5e7,
+               threads: int = 0) -> CSR:
+    """The serving workload's resident graphs, concatenated like a mixture."""
+    specs = [serve_spec(i, seed, mmin, mmax) for i in range(num_graphs)]
+    return concat(specs, seed, threads, "pool%d_s%d" % (num_graphs, seed))
 
 
 def concat(specs, seed: int, threads: int = 0, name: str = "mix") -> CSR:

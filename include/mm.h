@@ -115,6 +115,10 @@ typedef struct {
   int32_t stream_loads;  /* 1: read offsets and neighbour ids with non-temporal loads,
                             so that their lines are evicted first and the state (or
                             hint) lines stay in L2 longer */
+  int32_t whole_graph_vertices; /* a graph with at most this many vertices is swept
+                            by one wavefront (one work item of a batch), which makes
+                            its result independent of concurrent work: the same
+                            alone as inside any batch; 0 disables */
   int64_t iter_cap;      /* loop-trip budget per wavefront; 0 = default of
                             65536 + 8 x (neighbour entries of its block);
                             exceeding it raises MM_ERR_NO_PROGRESS */
@@ -210,8 +214,9 @@ typedef struct mm_batch* mm_batch_handle;
 /* Workspace bytes for a batch (vtx_off: host). 0 if the arguments are invalid. */
 size_t mm_batch_workspace_bytes(int32_t num_graphs, const int64_t* vtx_off, const mm_tuning* t);
 
-/* Creates a batch handle: builds the work-item table (one item per wavefront
-   block of every graph) in the workspace and waits for it. Arrays are borrowed
+/* Creates a batch handle: builds the graph descriptors and the work-item
+   table (one item per wavefront block of every graph) in the workspace and
+   waits for the upload. Arrays are borrowed
    like those of mm_create. flags: MM_VALIDATE | MM_SYMMETRIC | MM_STATS |
    MM_CAPTURE. */
 mm_status mm_batch_create(const int64_t* offsets_cat, const int32_t* neighbors_cat,
@@ -219,10 +224,24 @@ mm_status mm_batch_create(const int64_t* offsets_cat, const int32_t* neighbors_c
                           size_t workspace_bytes, uint32_t flags, const mm_tuning* tuning,
                           void* stream, mm_batch_handle* out);
 
-/* Enqueues one pass over every graph of the batch on `stream`. With
-   MM_CAPTURE the pass is a hipGraph replay (captured at the first run with a
-   given match_out). The first run with a new match_out binds the graph
-   descriptors to it (a small synchronous upload). */
+/* Creates a batch over graphs that live in separate allocations (a list
+   batch), as a server holding many resident graphs coalesces them into one
+   launch. offsets[g] and neighbors[g] (host arrays of num_graphs device
+   pointers) are graph g's own CSR: n[g]+1 int64 offsets from 0 to m[g], m[g]
+   int32 local ids (n, m: host arrays). The output layout is as for
+   mm_batch_create with vtx_off the prefix sums of n, which is also what
+   mm_batch_workspace_bytes takes. A graph with n[g] = 0 must have m[g] = 0
+   and its pointers are never read. MM_VALIDATE checks every graph's CSR on
+   the device. Arrays are borrowed; the host arrays may be freed on return. */
+mm_status mm_batch_create_list(const int64_t* const* offsets, const int32_t* const* neighbors,
+                               const int64_t* n, const int64_t* m, int32_t num_graphs,
+                               void* workspace, size_t workspace_bytes, uint32_t flags,
+                               const mm_tuning* tuning, void* stream, mm_batch_handle* out);
+
+/* Enqueues one pass over every graph of the batch on `stream`; nothing is
+   waited for. With MM_CAPTURE the pass is a hipGraph replay, captured at the
+   first run with a given match_out (a run with another output captures
+   again). */
 mm_status mm_batch_run(mm_batch_handle h, void* stream, int32_t* match_out);
 
 /* As mm_sync, for a batch. */

@@ -12,6 +12,8 @@ from __future__ import annotations
 import ctypes
 from dataclasses import asdict, dataclass
 
+import numpy as np
+
 from . import _lib
 from ._lib import MMError  # noqa: F401
 
@@ -39,6 +41,7 @@ class Tuning:
     lazy_init: int = 0
     scan_width: int = 4
     stream_loads: int = 0
+    whole_graph_vertices: int = 16384
     iter_cap: int = 0
 
     @classmethod
@@ -49,6 +52,9 @@ class Tuning:
 
     def to_c(self) -> _lib.mm_tuning:
         return _lib.mm_tuning(**asdict(self))
+
+    def as_dict(self) -> dict:
+        return asdict(self)
 
 
 def _stream_ptr(stream):
@@ -193,42 +199,88 @@ class Batch:
     tensor of local ids); vtx_off: host sequence of num_graphs+1 vertex
     offsets. run() returns the int32 tensor of LOCAL mates (-1 = unmatched).
     ``capture=True`` replays a hipGraph of the pass after the first run.
+    ``Batch.from_list`` builds a batch over graphs held in separate tensors.
     """
 
     def __init__(self, offsets, neighbors, vtx_off, *, symmetric: bool = False,
                  validate: bool = False, stats: bool = False, capture: bool = False,
                  tuning: Tuning | None = None, stream=None):
-        import numpy as np
         import torch
-        lib = _lib.load()
-        import torch as _t
-        if offsets.dtype != _t.int64:
+        if offsets.dtype != torch.int64:
             raise ValueError("batch offsets must be int64")
         _check_graph_tensors(offsets, neighbors)
-        self._vtx = np.ascontiguousarray(np.asarray(vtx_off, dtype=np.int64))
-        self.num_graphs = int(self._vtx.shape[0]) - 1
-        self.N = int(self._vtx[-1])
-        if offsets.numel() != self.N + 1:
+        vtx = np.ascontiguousarray(np.asarray(vtx_off, dtype=np.int64))
+        if offsets.numel() != int(vtx[-1]) + 1:
             raise ValueError("offsets must have vtx_off[-1] + 1 entries")
         self.offsets, self.neighbors = offsets, neighbors
+
+        def create(lib, ws, nbytes, flags, ct, h):
+            return lib.mm_batch_create(ctypes.c_void_p(offsets.data_ptr()),
+                                       ctypes.c_void_p(neighbors.data_ptr()),
+                                       ctypes.c_void_p(vtx.ctypes.data), len(vtx) - 1,
+                                       neighbors.numel(), ws, nbytes, flags, ct, _stream_ptr(stream), h)
+
+        self._setup(vtx, offsets.device, symmetric, validate, stats, capture, tuning, create)
+
+    @classmethod
+    def from_list(cls, graphs, *, symmetric: bool = False, validate: bool = False,
+                  stats: bool = False, capture: bool = False, tuning: Tuning | None = None,
+                  stream=None) -> "Batch":
+        """A batch over separately held graphs: ``graphs`` is a sequence of
+        (offsets int64, neighbors int32) CUDA tensor pairs, each a graph's own
+        CSR. The output holds graph g's mates at vtx_off[g] .. vtx_off[g+1]-1,
+        vtx_off being the prefix sums of the vertex counts."""
+        import torch
+        self = cls.__new__(cls)
+        G = len(graphs)
+        offs = (ctypes.c_void_p * max(G, 1))()
+        nbrs = (ctypes.c_void_p * max(G, 1))()
+        ns = np.zeros(max(G, 1), dtype=np.int64)
+        ms = np.zeros(max(G, 1), dtype=np.int64)
+        device = None
+        for g, (o, nb) in enumerate(graphs):
+            if o.dtype != torch.int64:
+                raise ValueError("graph %d: offsets must be int64" % g)
+            _check_graph_tensors(o, nb)
+            offs[g], nbrs[g] = o.data_ptr(), nb.data_ptr()
+            ns[g], ms[g] = o.numel() - 1, nb.numel()
+            device = o.device if device is None else device
+        self.graphs = list(graphs)  # borrowed: kept alive with the handle
+        vtx = np.zeros(G + 1, dtype=np.int64)
+        np.cumsum(ns[:G], out=vtx[1:])
+
+        def create(lib, ws, nbytes, flags, ct, h):
+            return lib.mm_batch_create_list(offs, nbrs, ctypes.c_void_p(ns.ctypes.data),
+                                            ctypes.c_void_p(ms.ctypes.data), G, ws, nbytes, flags,
+                                            ct, _stream_ptr(stream), h)
+
+        self._setup(vtx, device if device is not None else torch.device("cuda"), symmetric,
+                    validate, stats, capture, tuning, create)
+        return self
+
+    def _setup(self, vtx, device, symmetric, validate, stats, capture, tuning, create):
+        import torch
+        lib = _lib.load()
+        self._h = None
+        self._vtx = vtx
+        self.vtx_off = vtx
+        self.num_graphs = int(vtx.shape[0]) - 1
+        self.N = int(vtx[-1])
         self.tuning = tuning if tuning is not None else Tuning.default()
         ct = self.tuning.to_c()
-        nbytes = lib.mm_batch_workspace_bytes(self.num_graphs, ctypes.c_void_p(self._vtx.ctypes.data),
+        nbytes = lib.mm_batch_workspace_bytes(self.num_graphs, ctypes.c_void_p(vtx.ctypes.data),
                                               ctypes.byref(ct))
         if nbytes == 0:
             raise MMError(_lib.MM_ERR_INVALID_ARG, "invalid vtx_off or tuning")
-        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=offsets.device)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
         aligned = (self.workspace.data_ptr() + 255) // 256 * 256
         flags = ((_lib.MM_VALIDATE if validate else 0) | (_lib.MM_SYMMETRIC if symmetric else 0)
                  | (_lib.MM_STATS if stats else 0) | (_lib.MM_CAPTURE if capture else 0))
         h = ctypes.c_void_p()
-        _lib.check(lib.mm_batch_create(ctypes.c_void_p(offsets.data_ptr()),
-                                       ctypes.c_void_p(neighbors.data_ptr()),
-                                       ctypes.c_void_p(self._vtx.ctypes.data), self.num_graphs,
-                                       neighbors.numel(), ctypes.c_void_p(aligned), nbytes, flags,
-                                       ctypes.byref(ct), _stream_ptr(stream), ctypes.byref(h)))
+        _lib.check(create(lib, ctypes.c_void_p(aligned), nbytes, flags, ctypes.byref(ct),
+                          ctypes.byref(h)))
         self._h = h
-        self.device = offsets.device
+        self.device = device
 
     @property
     def items(self) -> int:

@@ -45,6 +45,7 @@ class mm_tuning(ctypes.Structure):
         ("lazy_init", ctypes.c_int32),
         ("scan_width", ctypes.c_int32),
         ("stream_loads", ctypes.c_int32),
+        ("whole_graph_vertices", ctypes.c_int32),
         ("iter_cap", ctypes.c_int64),
     ]
 
@@ -75,6 +76,8 @@ SIGNATURES = {
     "mm_batch_workspace_bytes": (_SZ, [_I32, _P, ctypes.POINTER(mm_tuning)]),
     "mm_batch_create": (_I32, [_P, _P, _P, _I32, _I64, _P, _SZ, _U32, ctypes.POINTER(mm_tuning), _P,
                                ctypes.POINTER(_P)]),
+    "mm_batch_create_list": (_I32, [_P, _P, _P, _P, _I32, _P, _SZ, _U32, ctypes.POINTER(mm_tuning),
+                                    _P, ctypes.POINTER(_P)]),
     "mm_batch_run": (_I32, [_P, _P, _P]),
     "mm_batch_sync": (_I32, [_P, _P]),
     "mm_batch_get_stats": (_I32, [_P, _P, ctypes.POINTER(mm_stats)]),

@@ -1,0 +1,250 @@
+"""Autotuner for the sweep's launch and layout parameters.
+
+The matching itself has no parameters; what is tuned is how the sweep maps to
+the device: the status layout and reservation protocol, the matched-hint
+bitmap, vertices per wavefront item, workgroup size, the list length after
+which a wavefront scans one source together, the per-lane scan width and lazy
+output. A coordinate search starts from the library defaults and, dimension
+by dimension, keeps the fastest value; every candidate's output must pass the
+device check (zero violations) or the candidate is discarded.
+
+Results are stored as JSON keyed by GPU architecture and compute-unit count,
+then by graph class ("rmat", "grid", "er" for single graphs; "batch" for
+many-graph batches), and read back with :func:`tuned`.
+
+    python -m paper_2507_04420_amd.autotune --classes batch,rmat --out tuned.json
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import time
+
+import numpy as np
+
+from . import Batch, Graph, Tuning, _lib
+
+TUNED_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned")
+
+# Values tried per dimension; the layout and protocol move together.
+SPACE = {
+    "layout_protocol": [(_lib.MM_LAYOUT_U32, _lib.MM_PROTOCOL_CAS),
+                        (_lib.MM_LAYOUT_U8, _lib.MM_PROTOCOL_CAS),
+                        (_lib.MM_LAYOUT_U2, _lib.MM_PROTOCOL_TWO_PHASE),
+                        (_lib.MM_LAYOUT_U32, _lib.MM_PROTOCOL_TWO_PHASE)],
+    "hint": [0, 1],
+    "disperse": [0, 1],
+    "wave_vertices": [256, 512, 1024, 2048, 4096],
+    "wg_size": [64, 128, 256],
+    "assist_after": [16, 32, 64, 128, 256],
+    "scan_width": [2, 3, 4],
+    "lazy_init": [0, 1],
+}
+
+
+def device_key() -> str:
+    import torch
+    p = torch.cuda.get_device_properties(0)
+    arch = getattr(p, "gcnArchName", "unknown").split(":")[0]
+    return "%s_%dcu" % (arch, p.multi_processor_count)
+
+
+def _with(t: Tuning, dim: str, value) -> Tuning:
+    d = t.as_dict()
+    if dim == "layout_protocol":
+        d["layout"], d["protocol"] = value
+    else:
+        d[dim] = value
+    return Tuning(**d)
+
+
+def _value(t: Tuning, dim: str):
+    return (t.layout, t.protocol) if dim == "layout_protocol" else getattr(t, dim)
+
+
+class SingleTarget:
+    """One resident graph; objective = GEdges/s of a whole pass."""
+
+    unit = "GEdges/s"
+
+    def __init__(self, csr, reps: int = 5):
+        import torch
+        self.off = torch.from_numpy(csr.off).cuda()
+        self.nbr = torch.from_numpy(csr.nbr).cuda()
+        self.m = csr.m
+        self.reps = reps
+        self.sample = "%s (n=%d, m=%d)" % (csr.name, csr.n, csr.m)
+
+    def measure(self, t: Tuning):
+        import torch
+        g = Graph(self.off, self.nbr, symmetric=True, tuning=t)
+        out = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        try:
+            g.run(out)
+            g.sync()
+            if not g.check(out)["ok"]:
+                return None
+            times = []
+            for _ in range(self.reps):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                g.run(out)
+                b.record()
+                g.sync()
+                times.append(a.elapsed_time(b) * 1e-3)
+            if not g.check(out)["ok"]:
+                return None
+            return self.m / float(np.median(times)) / 1e9
+        finally:
+            g.close()
+
+
+class BatchTarget:
+    """A many-graph batch; objective = graphs/s of a captured pass."""
+
+    unit = "graphs/s"
+
+    def __init__(self, mix, reps: int = 5):
+        import torch
+        self.off = torch.from_numpy(mix.off).cuda()
+        self.nbr = torch.from_numpy(mix.nbr).cuda()
+        self.vtx = mix.vtx_off
+        self.G = mix.num_graphs
+        self.reps = reps
+        self.sample = "%s (%d graphs, N=%d, M=%d)" % (mix.name, mix.num_graphs, mix.n, mix.m)
+
+    def measure(self, t: Tuning):
+        import torch
+        b = Batch(self.off, self.nbr, self.vtx, symmetric=True, capture=True, tuning=t)
+        out = torch.empty(b.N, dtype=torch.int32, device="cuda")
+        try:
+            b.run(out)
+            b.sync()
+            if not b.check(out)["ok"]:
+                return None
+            times = []
+            for _ in range(self.reps):
+                a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                b.run(out)
+                e.record()
+                b.sync()
+                times.append(a.elapsed_time(e) * 1e-3)
+            if not b.check(out)["ok"]:
+                return None
+            return self.G / float(np.median(times))
+        finally:
+            b.close()
+
+
+def search(target, start: Tuning | None = None, passes: int = 2, dims=None, log=print) -> dict:
+    """Coordinate search; returns the best tuning, its objective and the
+    number of candidates measured and rejected (failed check or error)."""
+    best = start if start is not None else Tuning.default()
+    cache = {}
+
+    def score(t):
+        key = tuple(sorted(t.as_dict().items()))
+        if key not in cache:
+            try:
+                cache[key] = target.measure(t)
+            except _lib.MMError as e:
+                log("  rejected %s: %s" % (t.as_dict(), e))
+                cache[key] = None
+        return cache[key]
+
+    default_obj = score(best)
+    if default_obj is None:
+        raise RuntimeError("the starting tuning fails the check")
+    best_obj = default_obj
+    dims = dims or list(SPACE)
+    for p in range(passes):
+        changed = False
+        for dim in dims:
+            for v in SPACE[dim]:
+                if v == _value(best, dim):
+                    continue
+                cand = _with(best, dim, v)
+                obj = score(cand)
+                if obj is not None and obj > best_obj * 1.01:  # 1% to beat noise
+                    best, best_obj, changed = cand, obj, True
+            log("  pass %d %-16s -> %s  %.4g %s" % (p, dim, _value(best, dim), best_obj, target.unit))
+        if not changed:
+            break
+    rejected = sum(1 for v in cache.values() if v is None)
+    return {"tuning": best.as_dict(), "objective": best_obj, "default_objective": default_obj,
+            "unit": target.unit, "sample": target.sample, "candidates": len(cache),
+            "rejected": rejected}
+
+
+def _targets(classes, seed):
+    import graphgen
+    out = {}
+    for c in classes:
+        if c == "rmat":
+            out[c] = lambda: SingleTarget(graphgen.rmat(24, seed=seed))
+        elif c == "grid":
+            out[c] = lambda: SingleTarget(graphgen.grid(8192, 8192))
+        elif c == "er":
+            out[c] = lambda: SingleTarget(graphgen.er(1 << 22, 16, seed=seed))
+        elif c == "batch":
+            out[c] = lambda: BatchTarget(graphgen.mixture(1024, seed=seed))
+        else:
+            raise ValueError("unknown graph class %r" % c)
+    return out
+
+
+def tuned_path(key: str | None = None) -> str:
+    return os.path.join(TUNED_DIR, "%s.json" % (key or device_key()))
+
+
+def tuned(graph_class: str, key: str | None = None) -> Tuning:
+    """The stored tuning for this device and graph class, else the defaults."""
+    path = tuned_path(key)
+    if os.path.exists(path):
+        with open(path) as f:
+            entry = json.load(f).get("classes", {}).get(graph_class)
+        if entry:
+            return Tuning(**entry["tuning"])
+    return Tuning.default()
+
+
+def classify(off: np.ndarray) -> str:
+    """Graph class of a CSR from its degree sequence: 'grid' when no vertex has
+    more than 4 entries, 'rmat' when the degrees are heavily skewed (largest
+    over 32 times the mean), else 'er'."""
+    deg = np.diff(off)
+    if deg.size == 0 or deg.max() <= 4:
+        return "grid"
+    return "rmat" if deg.max() > 32 * max(deg.mean(), 1e-9) else "er"
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--classes", default="batch,rmat,grid,er")
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--passes", type=int, default=2)
+    ap.add_argument("--out", default=None, help="JSON file (default: the package's tuned/ entry)")
+    a = ap.parse_args(argv)
+    key = device_key()
+    out = a.out or tuned_path(key)
+    doc = {"device": key, "classes": {}}
+    if os.path.exists(out):
+        with open(out) as f:
+            doc = json.load(f)
+    for c, make in _targets(a.classes.split(","), a.seed).items():
+        t0 = time.time()
+        print("== %s" % c, flush=True)
+        r = search(make(), passes=a.passes, log=lambda s: print(s, flush=True))
+        r["seconds"] = round(time.time() - t0, 1)
+        doc["classes"][c] = r
+        print(json.dumps({c: r}), flush=True)
+        os.makedirs(os.path.dirname(os.path.abspath(out)), exist_ok=True)
+        with open(out, "w") as f:
+            json.dump(doc, f, indent=1)
+    print("wrote", out)
+
+
+if __name__ == "__main__":
+    main()

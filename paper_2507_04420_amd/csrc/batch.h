@@ -10,14 +10,16 @@ struct mm_batch;
 
 namespace mmb {
 
-// One graph of a batch. Pointers are based at the graph's first vertex: the
-// offsets index `nbr`, neighbour ids are local to the graph.
+// One graph of a batch. `off` is based at the graph's first vertex and indexes
+// `nbr`; neighbour ids are local to the graph. Its mate entries are those at
+// v0 .. v0+n-1 of the batch's output.
 struct GraphDesc {
   const int64_t* off;
   const int32_t* nbr;
   int64_t n;
+  int64_t m;       // entries of the graph (list batches), -1 when not known
+  int64_t v0;      // first global vertex
   uint32_t* st;    // packed states, or null for the word layout
-  int32_t* mate;   // this graph's mate entries
   uint32_t* hint;  // matched hint words, or null
 };
 
@@ -55,18 +57,21 @@ hipError_t validate_batch(const int64_t* off, const int32_t* nbr, const int64_t*
                           int32_t num_graphs, int64_t N, int64_t M, uint32_t* flags,
                           hipStream_t s);
 
+// Device check of the graphs of a list batch, through their descriptors:
+// off[0] = 0, off[n] = m, offsets non-decreasing, ids in [0, n).
+hipError_t validate_list(const GraphDesc* descs, const int64_t* vtx_off_dev, int32_t num_graphs,
+                         int64_t N, uint32_t* flags, hipStream_t s);
+
 // 32-bit words of packed state for n vertices under `layout` (0 for words).
 int64_t state_words_for(int64_t n, int32_t layout);
 
-// What the device check needs from a batch handle.
+// What the device check needs from a batch handle (all device pointers).
 struct BatchInfo {
-  const int64_t* off;
-  const int32_t* nbr;
+  const GraphDesc* descs;
+  const int64_t* vtx_off;
   int32_t G;
   int64_t N;
   uint8_t* ws;
-  int64_t* vtx_dev;         // device scratch for the vertex-offset table
-  const int64_t* vtx_host;  // host copy of the table
 };
 BatchInfo batch_info(const mm_batch* b);
 

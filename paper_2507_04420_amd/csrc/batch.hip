@@ -68,7 +68,7 @@ __global__ void validate_batch_kernel(const int64_t* __restrict__ off, const int
     }
     const int64_t ng = vtx_off[lo + 1] - vtx_off[lo];
     const int64_t b = off[v], e = off[v + 1];
-    if (e < b) {
+    if (e < b || b < 0 || e > M) {  // never read outside the M entries
       f |= 2u;
       continue;
     }
@@ -80,31 +80,60 @@ __global__ void validate_batch_kernel(const int64_t* __restrict__ off, const int
   if (f) atomicOr(flags, f);
 }
 
+// The same check for a list batch, through the descriptors. A graph's own
+// offsets must start at 0 and end at its entry count.
+__global__ void validate_list_kernel(const GraphDesc* __restrict__ descs,
+                                     const int64_t* __restrict__ vtx_off, int32_t num_graphs,
+                                     int64_t N, uint32_t* flags) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  uint32_t f = 0;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < N; v += stride) {
+    int lo = 0, hi = num_graphs;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (vtx_off[mid] <= v) lo = mid; else hi = mid;
+    }
+    const GraphDesc d = descs[lo];
+    const int64_t x = v - vtx_off[lo];
+    const int64_t b = d.off[x], e = d.off[x + 1];
+    if ((x == 0 && b != 0) || (x == d.n - 1 && e != d.m)) f |= 1u;
+    if (e < b || b < 0 || e > d.m) {
+      f |= 2u;
+      continue;
+    }
+    for (int64_t j = b; j < e; ++j) {
+      const int32_t y = d.nbr[j];
+      if (y < 0 || (int64_t)y >= d.n) f |= 4u;
+    }
+  }
+  if (f) atomicOr(flags, f);
+}
+
 template <class Layout>
-__device__ __forceinline__ Layout layout_of(const GraphDesc& d);
+__device__ __forceinline__ Layout layout_of(const GraphDesc& d, int32_t* mate);
 template <>
-__device__ __forceinline__ LayoutU32<false> layout_of(const GraphDesc& d) {
-  return LayoutU32<false>{d.mate, Hint{d.hint}};
+__device__ __forceinline__ LayoutU32<false> layout_of(const GraphDesc& d, int32_t* mate) {
+  return LayoutU32<false>{mate + d.v0, Hint{d.hint}};
 }
 template <>
-__device__ __forceinline__ LayoutU32<true> layout_of(const GraphDesc& d) {
-  return LayoutU32<true>{d.mate, Hint{d.hint}};
+__device__ __forceinline__ LayoutU32<true> layout_of(const GraphDesc& d, int32_t* mate) {
+  return LayoutU32<true>{mate + d.v0, Hint{d.hint}};
 }
 template <>
-__device__ __forceinline__ LayoutPacked<8, false> layout_of(const GraphDesc& d) {
-  return LayoutPacked<8, false>{d.st, d.mate, Hint{d.hint}};
+__device__ __forceinline__ LayoutPacked<8, false> layout_of(const GraphDesc& d, int32_t* mate) {
+  return LayoutPacked<8, false>{d.st, mate + d.v0, Hint{d.hint}};
 }
 template <>
-__device__ __forceinline__ LayoutPacked<8, true> layout_of(const GraphDesc& d) {
-  return LayoutPacked<8, true>{d.st, d.mate, Hint{d.hint}};
+__device__ __forceinline__ LayoutPacked<8, true> layout_of(const GraphDesc& d, int32_t* mate) {
+  return LayoutPacked<8, true>{d.st, mate + d.v0, Hint{d.hint}};
 }
 template <>
-__device__ __forceinline__ LayoutPacked<2, false> layout_of(const GraphDesc& d) {
-  return LayoutPacked<2, false>{d.st, d.mate, Hint{d.hint}};
+__device__ __forceinline__ LayoutPacked<2, false> layout_of(const GraphDesc& d, int32_t* mate) {
+  return LayoutPacked<2, false>{d.st, mate + d.v0, Hint{d.hint}};
 }
 template <>
-__device__ __forceinline__ LayoutPacked<2, true> layout_of(const GraphDesc& d) {
-  return LayoutPacked<2, true>{d.st, d.mate, Hint{d.hint}};
+__device__ __forceinline__ LayoutPacked<2, true> layout_of(const GraphDesc& d, int32_t* mate) {
+  return LayoutPacked<2, true>{d.st, mate + d.v0, Hint{d.hint}};
 }
 
 // Persistent sweep: every wavefront pops items until the table is exhausted;
@@ -114,7 +143,8 @@ template <class Layout, bool HINT, bool LAZY, bool STATS>
 __global__ __launch_bounds__(256) void batch_sweep_kernel(SweepParams p,
                                                          const GraphDesc* __restrict__ descs,
                                                          const WorkItem* __restrict__ items,
-                                                         int64_t n_items, uint32_t* queue,
+                                                         int64_t n_items, int32_t* mate,
+                                                         uint32_t* queue,
                                                          unsigned long long* stats) {
   __shared__ QSlot queues[4][kQueue];
   Counters<STATS> cnt;
@@ -127,7 +157,7 @@ __global__ __launch_bounds__(256) void batch_sweep_kernel(SweepParams p,
     if ((int64_t)it >= n_items) break;
     const WorkItem w = items[it];
     const GraphDesc d = descs[w.desc];
-    const Layout L = layout_of<Layout>(d);
+    const Layout L = layout_of<Layout>(d, mate);
     sweep_block<int64_t, Layout, HINT, LAZY, STATS>(p, d.off, d.nbr, L, w.vb, (int64_t)w.nv,
                                                     queues[threadIdx.x >> 6], cnt);
   }
@@ -154,7 +184,7 @@ hipError_t launch_persistent(const BatchPlan& bp, hipStream_t s) {
   if (blocks > need) blocks = need;
   if (blocks < 1) return hipSuccess;
   hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(bp.wg_size), 0, s, bp.params, bp.descs,
-                     bp.items, bp.n_items, bp.queue, bp.stats);
+                     bp.items, bp.n_items, bp.mate, bp.queue, bp.stats);
   return hipGetLastError();
 }
 
@@ -222,6 +252,16 @@ hipError_t validate_batch(const int64_t* off, const int32_t* nbr, const int64_t*
   return hipGetLastError();
 }
 
+hipError_t validate_list(const GraphDesc* descs, const int64_t* vtx_off_dev, int32_t num_graphs,
+                         int64_t N, uint32_t* flags, hipStream_t s) {
+  int64_t blocks = (N + 255) / 256;
+  if (blocks < 1) blocks = 1;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(validate_list_kernel, dim3((unsigned)blocks), dim3(256), 0, s, descs,
+                     vtx_off_dev, num_graphs, N, flags);
+  return hipGetLastError();
+}
+
 int64_t state_words_for(int64_t n, int32_t layout) {
   if (layout == MM_LAYOUT_U8) return (n + 3) / 4;
   if (layout == MM_LAYOUT_U2) return (n + 15) / 16;
@@ -244,7 +284,7 @@ bool plan_layout(int32_t G, const int64_t* vtx_off, const mm_tuning& t, BatchLay
   for (int32_t g = 0; g < G; ++g) {
     const int64_t n = vtx_off[g + 1] - vtx_off[g];
     if (n < 0 || n > INT32_MAX) return false;
-    n_items += (n + t.wave_vertices - 1) / t.wave_vertices;
+    n_items += n <= t.whole_graph_vertices ? (n > 0) : (n + t.wave_vertices - 1) / t.wave_vertices;
     st_words += mmb::state_words_for(n, t.layout);
     if (t.hint) hint_words += (n + 31) / 32;
   }
@@ -270,19 +310,17 @@ bool plan_layout(int32_t G, const int64_t* vtx_off, const mm_tuning& t, BatchLay
 
 }  // namespace
 
+
 struct mm_batch {
-  const int64_t* off;
-  const int32_t* nbr;
   int32_t G;
-  int64_t N, M;
+  int64_t N;
   uint8_t* ws;
   uint32_t flags;
   mm_tuning tun;
   BatchLayout lay;
-  std::vector<mmb::GraphDesc> descs;  // host copy; mate pointers set per output
   std::vector<int64_t> vtx_off;
   mmb::BatchPlan plan;
-  int32_t* bound_mate = nullptr;  // output the device descriptors point into
+  int32_t* bound_mate = nullptr;  // output the captured pass writes to
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -297,122 +335,103 @@ void drop_graph(mm_batch* b) {
   b->graph = nullptr;
 }
 
-}  // namespace
-
-extern "C" {
-
-size_t mm_batch_workspace_bytes(int32_t num_graphs, const int64_t* vtx_off, const mm_tuning* tp) {
-  if (num_graphs < 0 || (!vtx_off && num_graphs > 0)) return 0;
-  mm_tuning t;
-  if (tp) t = *tp; else mm_default_tuning(&t);
-  if (mmi::check_tuning(t) != MM_OK) return 0;
-  BatchLayout L;
-  if (!plan_layout(num_graphs, vtx_off, t, &L)) return 0;
-  return L.total;
-}
-
-mm_status mm_batch_create(const int64_t* offsets_cat, const int32_t* neighbors_cat,
-                          const int64_t* vtx_off, int32_t num_graphs, int64_t M, void* workspace,
-                          size_t workspace_bytes, uint32_t flags, const mm_tuning* tuning,
-                          void* stream, mm_batch_handle* out) {
+// Checks shared by both create forms; fills the tuning to use.
+mm_status common_args(void* workspace, uint32_t flags, const mm_tuning* tuning, mm_tuning* t,
+                      mm_batch_handle* out) {
   if (!out) return fail(MM_ERR_INVALID_ARG, "out handle pointer is null");
   *out = nullptr;
-  if (num_graphs < 0) return fail(MM_ERR_INVALID_ARG, "num_graphs is negative");
-  if (!vtx_off) return fail(MM_ERR_INVALID_ARG, "vtx_off is null");
-  if (!offsets_cat) return fail(MM_ERR_INVALID_ARG, "offsets is null");
-  if (!neighbors_cat && M > 0) return fail(MM_ERR_INVALID_ARG, "neighbors is null");
-  if (M < 0) return fail(MM_ERR_INVALID_ARG, "M is negative");
   if (!workspace) return fail(MM_ERR_INVALID_ARG, "workspace is null");
   if (reinterpret_cast<uintptr_t>(workspace) % 256)
     return fail(MM_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
   if (flags & ~(uint32_t)(MM_VALIDATE | MM_SYMMETRIC | MM_STATS | MM_TIMING | MM_CAPTURE))
     return fail(MM_ERR_INVALID_ARG, "unknown flag bits 0x%x", flags);
-  if (vtx_off[0] != 0) return fail(MM_ERR_INVALID_ARG, "vtx_off[0] must be 0");
-  for (int32_t g = 0; g < num_graphs; ++g)
-    if (vtx_off[g + 1] < vtx_off[g] || vtx_off[g + 1] - vtx_off[g] > INT32_MAX)
-      return fail(MM_ERR_INVALID_ARG, "vtx_off must be non-decreasing with graphs of < 2^31 vertices");
-  mm_tuning t;
-  if (tuning) t = *tuning; else mm_default_tuning(&t);
-  mm_status st = mmi::check_tuning(t);
-  if (st != MM_OK) return st;
-  BatchLayout lay;
-  plan_layout(num_graphs, vtx_off, t, &lay);
+  if (tuning) *t = *tuning; else mm_default_tuning(t);
+  return mmi::check_tuning(*t);
+}
+
+// Completes a handle whose descriptors carry off, nbr, n, m and v0: places the
+// states and hints, uploads descriptors, vertex table and work items, runs the
+// optional device validation (concatenated or list form) and waits for it.
+mm_status finish_create(std::vector<mmb::GraphDesc>& descs, const std::vector<int64_t>& vtx,
+                        const BatchLayout& lay, const mm_tuning& t, uint8_t* ws,
+                        size_t workspace_bytes, uint32_t flags, hipStream_t s,
+                        const int64_t* concat_off, const int32_t* concat_nbr, int64_t M,
+                        mm_batch_handle* out) {
   if (workspace_bytes < lay.total)
     return fail(MM_ERR_OUT_OF_MEMORY, "workspace has %zu bytes, needs %zu", workspace_bytes, lay.total);
-  const int64_t N = vtx_off[num_graphs];
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  uint8_t* ws = static_cast<uint8_t*>(workspace);
-  HIP_TRY(hipMemsetAsync(ws, 0, kCtrlBytes, s));
-  if (flags & MM_VALIDATE) {
-    int64_t* vdev = reinterpret_cast<int64_t*>(ws + lay.vtx);
-    HIP_TRY(hipMemcpyAsync(vdev, vtx_off, sizeof(int64_t) * (num_graphs + 1), hipMemcpyHostToDevice, s));
-    uint32_t* f = reinterpret_cast<uint32_t*>(ws);
-    HIP_TRY(mmb::validate_batch(offsets_cat, neighbors_cat, vdev, num_graphs, N, M, f, s));
-    uint32_t hf = 0;
-    HIP_TRY(hipMemcpyAsync(&hf, f, sizeof(hf), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    HIP_TRY(hipMemsetAsync(ws, 0, kCtrlBytes, s));
-    if (hf)
-      return fail(MM_ERR_INVALID_GRAPH, "invalid batch CSR:%s%s%s",
-                  (hf & 1u) ? " offsets[0] != 0 or offsets[N] != M;" : "",
-                  (hf & 2u) ? " offsets decrease;" : "",
-                  (hf & 4u) ? " neighbour id outside its graph;" : "");
+  const int32_t G = (int32_t)descs.size();
+  const int64_t N = vtx[G];
+  uint32_t* st_base = reinterpret_cast<uint32_t*>(ws + lay.st);
+  uint32_t* hint_base = reinterpret_cast<uint32_t*>(ws + lay.hint);
+  int64_t st_w = 0, hint_w = 0;
+  std::vector<mmb::WorkItem> items;
+  items.reserve((size_t)lay.n_items);
+  for (int32_t g = 0; g < G; ++g) {
+    mmb::GraphDesc& d = descs[g];
+    d.st = t.layout == MM_LAYOUT_U32 ? nullptr : st_base + st_w;
+    d.hint = t.hint ? hint_base + hint_w : nullptr;
+    st_w += mmb::state_words_for(d.n, t.layout);
+    if (t.hint) hint_w += (d.n + 31) / 32;
+    // a small graph is one item (one wavefront), a larger one an item per block
+    const int64_t step = d.n <= t.whole_graph_vertices ? d.n : t.wave_vertices;
+    for (int64_t vb = 0; vb < d.n; vb += step) {
+      mmb::WorkItem w;
+      w.desc = g;
+      w.vb = vb;
+      w.nv = (int32_t)std::min<int64_t>(step, d.n - vb);
+      items.push_back(w);
+    }
   }
+  auto* descs_dev = reinterpret_cast<mmb::GraphDesc*>(ws + lay.descs);
+  auto* items_dev = reinterpret_cast<mmb::WorkItem*>(ws + lay.items);
+  auto* vtx_dev = reinterpret_cast<int64_t*>(ws + lay.vtx);
+  uint32_t* f = reinterpret_cast<uint32_t*>(ws);
+  HIP_TRY(hipMemsetAsync(ws, 0, kCtrlBytes, s));
+  if (G > 0)
+    HIP_TRY(hipMemcpyAsync(descs_dev, descs.data(), sizeof(mmb::GraphDesc) * G,
+                           hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(vtx_dev, vtx.data(), sizeof(int64_t) * (G + 1), hipMemcpyHostToDevice, s));
+  if (!items.empty())
+    HIP_TRY(hipMemcpyAsync(items_dev, items.data(), sizeof(mmb::WorkItem) * items.size(),
+                           hipMemcpyHostToDevice, s));
+  if (flags & MM_VALIDATE) {
+    if (concat_off)
+      HIP_TRY(mmb::validate_batch(concat_off, concat_nbr, vtx_dev, G, N, M, f, s));
+    else
+      HIP_TRY(mmb::validate_list(descs_dev, vtx_dev, G, N, f, s));
+  }
+  uint32_t hf = 0;
+  HIP_TRY(hipMemcpyAsync(&hf, f, sizeof(hf), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));  // the host vectors are released after this
+  if (hf) {
+    HIP_TRY(hipMemsetAsync(ws, 0, kCtrlBytes, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return fail(MM_ERR_INVALID_GRAPH, "invalid batch CSR:%s%s%s",
+                (hf & 1u) ? (concat_off ? " offsets[0] != 0 or offsets[N] != M;"
+                                        : " a graph's offsets do not run from 0 to m;")
+                          : "",
+                (hf & 2u) ? " offsets decrease;" : "",
+                (hf & 4u) ? " neighbour id outside its graph;" : "");
+  }
+  int cus = 0, dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   mm_batch* b = new (std::nothrow) mm_batch();
   if (!b) return fail(MM_ERR_OUT_OF_MEMORY, "host allocation of the batch handle failed");
-  b->off = offsets_cat;
-  b->nbr = neighbors_cat;
-  b->G = num_graphs;
+  if (flags & MM_CAPTURE) {
+    hipError_t e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      delete b;
+      return fail(MM_ERR_HIP, "capture stream: %s", hipGetErrorString(e));
+    }
+  }
+  b->G = G;
   b->N = N;
-  b->M = M;
   b->ws = ws;
   b->flags = flags;
   b->tun = t;
   b->lay = lay;
-  b->vtx_off.assign(vtx_off, vtx_off + num_graphs + 1);
-  // descriptors (mate pointers are bound at the first run) and work items
-  b->descs.resize(num_graphs);
-  std::vector<mmb::WorkItem> items;
-  items.reserve((size_t)lay.n_items);
-  uint32_t* st_base = reinterpret_cast<uint32_t*>(ws + lay.st);
-  uint32_t* hint_base = reinterpret_cast<uint32_t*>(ws + lay.hint);
-  int64_t st_w = 0, hint_w = 0;
-  for (int32_t g = 0; g < num_graphs; ++g) {
-    const int64_t n = vtx_off[g + 1] - vtx_off[g];
-    mmb::GraphDesc& d = b->descs[g];
-    d.off = offsets_cat + vtx_off[g];
-    d.nbr = neighbors_cat;
-    d.n = n;
-    d.st = t.layout == MM_LAYOUT_U32 ? nullptr : st_base + st_w;
-    d.hint = t.hint ? hint_base + hint_w : nullptr;
-    d.mate = nullptr;
-    st_w += mmb::state_words_for(n, t.layout);
-    if (t.hint) hint_w += (n + 31) / 32;
-    for (int64_t vb = 0; vb < n; vb += t.wave_vertices) {
-      mmb::WorkItem w;
-      w.desc = g;
-      w.vb = vb;
-      w.nv = (int32_t)std::min<int64_t>(t.wave_vertices, n - vb);
-      items.push_back(w);
-    }
-  }
-  mmb::WorkItem* items_dev = reinterpret_cast<mmb::WorkItem*>(ws + lay.items);
-  hipError_t e = hipSuccess;
-  if (!items.empty())
-    e = hipMemcpyAsync(items_dev, items.data(), sizeof(mmb::WorkItem) * items.size(),
-                       hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  int cus = 0;
-  if (e == hipSuccess) {
-    int dev = 0;
-    e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  }
-  if (e == hipSuccess && (flags & MM_CAPTURE)) e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
-  if (e != hipSuccess) {
-    delete b;
-    return fail(MM_ERR_HIP, "batch setup failed: %s", hipGetErrorString(e));
-  }
+  b->vtx_off = vtx;
   mmb::BatchPlan& p = b->plan;
   p.params.wave_vertices = t.wave_vertices;
   p.params.disperse = t.disperse;
@@ -420,8 +439,8 @@ mm_status mm_batch_create(const int64_t* offsets_cat, const int32_t* neighbors_c
   p.params.scan_width = t.scan_width;
   p.params.stream_loads = t.stream_loads;
   p.params.iter_cap = t.iter_cap;
-  p.params.err = reinterpret_cast<uint32_t*>(ws);
-  p.descs = reinterpret_cast<const mmb::GraphDesc*>(ws + lay.descs);
+  p.params.err = f;
+  p.descs = descs_dev;
   p.items = items_dev;
   p.n_items = lay.n_items;
   p.queue = reinterpret_cast<uint32_t*>(ws + kQueueOffset);
@@ -444,17 +463,90 @@ mm_status mm_batch_create(const int64_t* offsets_cat, const int32_t* neighbors_c
   return MM_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+size_t mm_batch_workspace_bytes(int32_t num_graphs, const int64_t* vtx_off, const mm_tuning* tp) {
+  if (num_graphs < 0 || !vtx_off) return 0;
+  mm_tuning t;
+  if (tp) t = *tp; else mm_default_tuning(&t);
+  if (mmi::check_tuning(t) != MM_OK) return 0;
+  BatchLayout L;
+  if (!plan_layout(num_graphs, vtx_off, t, &L)) return 0;
+  return L.total;
+}
+
+mm_status mm_batch_create(const int64_t* offsets_cat, const int32_t* neighbors_cat,
+                          const int64_t* vtx_off, int32_t num_graphs, int64_t M, void* workspace,
+                          size_t workspace_bytes, uint32_t flags, const mm_tuning* tuning,
+                          void* stream, mm_batch_handle* out) {
+  mm_tuning t;
+  mm_status st = common_args(workspace, flags, tuning, &t, out);
+  if (st != MM_OK) return st;
+  if (num_graphs < 0) return fail(MM_ERR_INVALID_ARG, "num_graphs is negative");
+  if (!vtx_off) return fail(MM_ERR_INVALID_ARG, "vtx_off is null");
+  if (!offsets_cat) return fail(MM_ERR_INVALID_ARG, "offsets is null");
+  if (!neighbors_cat && M > 0) return fail(MM_ERR_INVALID_ARG, "neighbors is null");
+  if (M < 0) return fail(MM_ERR_INVALID_ARG, "M is negative");
+  if (vtx_off[0] != 0) return fail(MM_ERR_INVALID_ARG, "vtx_off[0] must be 0");
+  for (int32_t g = 0; g < num_graphs; ++g)
+    if (vtx_off[g + 1] < vtx_off[g] || vtx_off[g + 1] - vtx_off[g] > INT32_MAX)
+      return fail(MM_ERR_INVALID_ARG, "vtx_off must be non-decreasing with graphs of < 2^31 vertices");
+  BatchLayout lay;
+  plan_layout(num_graphs, vtx_off, t, &lay);
+  std::vector<int64_t> vtx(vtx_off, vtx_off + num_graphs + 1);
+  std::vector<mmb::GraphDesc> descs((size_t)num_graphs);
+  for (int32_t g = 0; g < num_graphs; ++g) {
+    mmb::GraphDesc& d = descs[g];
+    d.off = offsets_cat + vtx[g];
+    d.nbr = neighbors_cat;
+    d.n = vtx[g + 1] - vtx[g];
+    d.m = -1;
+    d.v0 = vtx[g];
+  }
+  return finish_create(descs, vtx, lay, t, static_cast<uint8_t*>(workspace), workspace_bytes,
+                       flags, static_cast<hipStream_t>(stream), offsets_cat, neighbors_cat, M, out);
+}
+
+mm_status mm_batch_create_list(const int64_t* const* offsets, const int32_t* const* neighbors,
+                               const int64_t* n, const int64_t* m, int32_t num_graphs,
+                               void* workspace, size_t workspace_bytes, uint32_t flags,
+                               const mm_tuning* tuning, void* stream, mm_batch_handle* out) {
+  mm_tuning t;
+  mm_status st = common_args(workspace, flags, tuning, &t, out);
+  if (st != MM_OK) return st;
+  if (num_graphs < 0) return fail(MM_ERR_INVALID_ARG, "num_graphs is negative");
+  if (num_graphs > 0 && (!offsets || !neighbors || !n || !m))
+    return fail(MM_ERR_INVALID_ARG, "a per-graph array is null");
+  std::vector<int64_t> vtx((size_t)num_graphs + 1, 0);
+  std::vector<mmb::GraphDesc> descs((size_t)num_graphs);
+  for (int32_t g = 0; g < num_graphs; ++g) {
+    if (n[g] < 0 || n[g] > INT32_MAX) return fail(MM_ERR_INVALID_ARG, "graph %d: n out of range", g);
+    if (m[g] < 0 || (n[g] == 0 && m[g] != 0))
+      return fail(MM_ERR_INVALID_ARG, "graph %d: m out of range", g);
+    if (n[g] > 0 && !offsets[g]) return fail(MM_ERR_INVALID_ARG, "graph %d: offsets is null", g);
+    if (m[g] > 0 && !neighbors[g]) return fail(MM_ERR_INVALID_ARG, "graph %d: neighbors is null", g);
+    vtx[g + 1] = vtx[g] + n[g];
+    mmb::GraphDesc& d = descs[g];
+    d.off = offsets[g];
+    d.nbr = neighbors[g];
+    d.n = n[g];
+    d.m = m[g];
+    d.v0 = vtx[g];
+  }
+  BatchLayout lay;
+  plan_layout(num_graphs, vtx.data(), t, &lay);
+  return finish_create(descs, vtx, lay, t, static_cast<uint8_t*>(workspace), workspace_bytes,
+                       flags, static_cast<hipStream_t>(stream), nullptr, nullptr, 0, out);
+}
+
 mm_status mm_batch_run(mm_batch_handle b, void* stream, int32_t* match_out) {
   if (!b) return fail(MM_ERR_INVALID_ARG, "batch handle is null");
   if (!match_out && b->N > 0) return fail(MM_ERR_INVALID_ARG, "match_out is null");
   if (b->plan.n_items == 0) return MM_OK;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (match_out != b->bound_mate) {
-    // bind the descriptors to this output, then drop any graph captured for another one
-    for (int32_t g = 0; g < b->G; ++g) b->descs[g].mate = match_out + b->vtx_off[g];
-    HIP_TRY(hipMemcpyAsync(const_cast<mmb::GraphDesc*>(b->plan.descs), b->descs.data(),
-                           sizeof(mmb::GraphDesc) * b->descs.size(), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipStreamSynchronize(s));
+  if (match_out != b->bound_mate) {  // a captured pass is tied to its output
     b->plan.mate = match_out;
     b->bound_mate = match_out;
     drop_graph(b);
@@ -508,24 +600,6 @@ mm_status mm_batch_get_stats(mm_batch_handle b, void* stream, mm_stats* out) {
 
 int64_t mm_batch_items(mm_batch_handle b) { return b ? b->plan.n_items : -1; }
 
-}  // extern "C"
-
-namespace mmb {
-BatchInfo batch_info(const mm_batch* b) {
-  BatchInfo i;
-  i.off = b->off;
-  i.nbr = b->nbr;
-  i.G = b->G;
-  i.N = b->N;
-  i.ws = b->ws;
-  i.vtx_dev = reinterpret_cast<int64_t*>(b->ws + b->lay.vtx);
-  i.vtx_host = b->vtx_off.data();
-  return i;
-}
-}  // namespace mmb
-
-extern "C" {
-
 void mm_batch_destroy(mm_batch_handle b) {
   if (!b) return;
   drop_graph(b);
@@ -534,3 +608,15 @@ void mm_batch_destroy(mm_batch_handle b) {
 }
 
 }  // extern "C"
+
+namespace mmb {
+BatchInfo batch_info(const mm_batch* b) {
+  BatchInfo i;
+  i.descs = b->plan.descs;
+  i.vtx_off = reinterpret_cast<const int64_t*>(b->ws + b->lay.vtx);
+  i.G = b->G;
+  i.N = b->N;
+  i.ws = b->ws;
+  return i;
+}
+}  // namespace mmb

@@ -72,7 +72,7 @@ __global__ void check_kernel(const OffT* __restrict__ off, const int32_t* __rest
   flush_counts(c, out);
 }
 
-__global__ void check_batch_kernel(const int64_t* __restrict__ off, const int32_t* __restrict__ nbr,
+__global__ void check_batch_kernel(const mmb::GraphDesc* __restrict__ descs,
                                    const int64_t* __restrict__ vtx_off, int32_t num_graphs,
                                    const int32_t* __restrict__ mate, unsigned long long* out) {
   unsigned long long c[6] = {0, 0, 0, 0, 0, 0};
@@ -84,8 +84,8 @@ __global__ void check_batch_kernel(const int64_t* __restrict__ off, const int32_
       const int mid = (lo + hi) >> 1;
       if (vtx_off[mid] <= v) lo = mid; else hi = mid;
     }
-    const int64_t v0 = vtx_off[lo];
-    check_vertex(off + v0, nbr, vtx_off[lo + 1] - v0, mate + v0, v - v0, c);
+    const mmb::GraphDesc d = descs[lo];
+    check_vertex(d.off, d.nbr, d.n, mate + d.v0, v - d.v0, c);
   }
   flush_counts(c, out);
 }
@@ -138,10 +138,8 @@ mm_status mm_batch_check(mm_batch_handle b, void* stream, const int32_t* match, 
   unsigned long long* dev = reinterpret_cast<unsigned long long*>(info.ws + mmi::kCheckOffset);
   HIP_TRY(hipMemsetAsync(dev, 0, 6 * sizeof(unsigned long long), s));
   if (info.N > 0) {
-    HIP_TRY(hipMemcpyAsync(info.vtx_dev, info.vtx_host, sizeof(int64_t) * (info.G + 1),
-                           hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(check_batch_kernel, dim3(blocks_for(info.N)), dim3(256), 0, s, info.off,
-                       info.nbr, info.vtx_dev, info.G, match, dev);
+    hipLaunchKernelGGL(check_batch_kernel, dim3(blocks_for(info.N)), dim3(256), 0, s, info.descs,
+                       info.vtx_off, info.G, match, dev);
     HIP_TRY(hipGetLastError());
   }
   return finish(dev, s, counts);

@@ -3,6 +3,7 @@
 // pass (state initialisation, then the sweep of Algorithm 1).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdarg>
 #include <cstdint>
 #include <cstdio>
@@ -56,6 +57,8 @@ mm_status check_tuning(const mm_tuning& t) {
     return fail(MM_ERR_INVALID_ARG, "tuning.scan_width must be in [1, %d]", kMaxW);
   if (t.stream_loads != 0 && t.stream_loads != 1)
     return fail(MM_ERR_INVALID_ARG, "tuning.stream_loads must be 0 or 1");
+  if (t.whole_graph_vertices < 0)
+    return fail(MM_ERR_INVALID_ARG, "tuning.whole_graph_vertices must be >= 0");
   if (t.iter_cap < 0) return fail(MM_ERR_INVALID_ARG, "tuning.iter_cap must be >= 0");
   return MM_OK;
 }
@@ -220,6 +223,10 @@ SweepParams make_params(const mm_graph* g) {
   p.stream_loads = g->tun.stream_loads;
   p.iter_cap = g->tun.iter_cap;
   p.err = reinterpret_cast<uint32_t*>(g->ws);
+  if (g->n <= g->tun.whole_graph_vertices) {  // one wavefront takes the whole graph
+    p.wave_vertices = std::max<int64_t>(64, (g->n + 63) / 64 * 64);
+    p.disperse = 0;
+  }
   return p;
 }
 
@@ -328,6 +335,7 @@ void mm_default_tuning(mm_tuning* t) {
   t->assist_after = 64;
   t->lazy_init = 0;
   t->scan_width = 4;
+  t->whole_graph_vertices = 16384;
   t->iter_cap = 0;
 }
 

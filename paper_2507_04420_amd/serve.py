@@ -1,0 +1,304 @@
+"""Serving loop: a stream of matching requests over graphs resident on the GPU.
+
+A request names a resident graph (its CSR already in device memory) and asks
+for a maximal matching of it. The server
+
+* admits requests in arrival order while their device footprint (status
+  words, hint bits, mate output and workspace; the CSR is already resident)
+  fits the HBM budget, and, for large jobs, while a solo slot is free;
+* coalesces admitted small jobs into list batches (one persistent launch over
+  all of them, ``mm_batch_create_list``) that start as soon as a batch slot
+  is free, so requests that arrive while earlier ones are on the GPU join the
+  next launch (continuous batching);
+* runs large jobs alone (``mm_create``/``mm_run``) on their own streams, where
+  they overlap with the batches and with each other;
+* retires launches as their completion events fire, releases their footprint
+  and records arrival -> result-ready latency.
+
+The scheduling core (:class:`Scheduler`) is independent of the device: it
+drives an executor object, so its admission and batching rules are tested on
+the CPU with a simulated executor; :class:`GpuExecutor` is the real one.
+"""
+from __future__ import annotations
+
+import math
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import _lib
+
+
+@dataclass
+class ResidentGraph:
+    """A graph whose CSR (int64 offsets, int32 neighbours) is on the device."""
+    off: object
+    nbr: object
+    n: int
+    m: int
+    symmetric: bool = True
+    name: str = ""
+
+    @classmethod
+    def from_tensors(cls, off, nbr, symmetric=True, name=""):
+        return cls(off, nbr, off.numel() - 1, nbr.numel(), symmetric, name)
+
+
+@dataclass
+class Request:
+    rid: int
+    graph: ResidentGraph
+    arrival: float  # seconds from the start of the trace
+
+
+@dataclass
+class Completion:
+    rid: int
+    route: str          # "batch" or "solo"
+    launch: int         # id of the launch that served the request
+    arrival: float
+    admitted: float
+    launched: float
+    done: float
+    mate: object = None  # int32 device tensor of n local mates (kept if asked)
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+@dataclass
+class _Launch:
+    lid: int
+    route: str
+    reqs: list
+    slot: int
+    handle: object
+    launched: float
+    footprint: int
+
+
+@dataclass
+class Scheduler:
+    """Admission, continuous batching and retirement over an executor.
+
+    executor must provide footprint(req, route) -> bytes,
+    launch(route, reqs, slot) -> handle, done(handle) -> bool and
+    finish(handle) -> list of per-request mates (or Nones).
+    """
+    executor: object
+    hbm_budget: int
+    small_edges: int = 2_000_000
+    max_batch: int = 1024
+    batch_slots: int = 2
+    solo_slots: int = 2
+    keep_results: bool = True
+    pending: deque = field(default_factory=deque)   # arrived, not admitted
+    ready: deque = field(default_factory=deque)     # admitted small jobs awaiting a batch
+    inflight: list = field(default_factory=list)
+    completions: list = field(default_factory=list)
+    in_use: int = 0
+    peak_in_use: int = 0
+    _admit_time: dict = field(default_factory=dict)
+    _fp: dict = field(default_factory=dict)
+    _free_batch: list = None
+    _free_solo: list = None
+    _next_lid: int = 0
+
+    def __post_init__(self):
+        self._free_batch = list(range(self.batch_slots))
+        self._free_solo = list(range(self.solo_slots))
+
+    def route(self, req) -> str:
+        return "batch" if req.graph.m <= self.small_edges else "solo"
+
+    def submit(self, req) -> None:
+        fp = self.executor.footprint(req, self.route(req))
+        if fp > self.hbm_budget:
+            raise ValueError("request %d needs %d bytes, more than the whole budget" % (req.rid, fp))
+        self._fp[req.rid] = fp
+        self.pending.append(req)
+
+    def idle(self) -> bool:
+        return not (self.pending or self.ready or self.inflight)
+
+    def step(self, now: float) -> int:
+        """One scheduling round; returns the number of requests completed."""
+        done = self._retire(now)
+        self._admit(now)
+        self._launch_batches(now)
+        return done
+
+    def _retire(self, now):
+        count = 0
+        still = []
+        for L in self.inflight:
+            if not self.executor.done(L.handle):
+                still.append(L)
+                continue
+            mates = self.executor.finish(L.handle)
+            for r, mt in zip(L.reqs, mates):
+                self.completions.append(Completion(
+                    r.rid, L.route, L.lid, r.arrival, self._admit_time.pop(r.rid), L.launched, now,
+                    mt if self.keep_results else None))
+                count += 1
+            self.in_use -= L.footprint
+            (self._free_batch if L.route == "batch" else self._free_solo).append(L.slot)
+        self.inflight = still
+        return count
+
+    def _admit(self, now):
+        # strict arrival order: a request that does not fit blocks those behind
+        # it, so a large job is never starved by a stream of small ones
+        while self.pending:
+            r = self.pending[0]
+            fp = self._fp[r.rid]
+            route = self.route(r)
+            if self.in_use + fp > self.hbm_budget:
+                break
+            if route == "solo" and not self._free_solo:
+                break
+            self.pending.popleft()
+            self.in_use += fp
+            self.peak_in_use = max(self.peak_in_use, self.in_use)
+            self._admit_time[r.rid] = now
+            if route == "solo":
+                slot = self._free_solo.pop(0)
+                self._start("solo", [r], slot, now, fp)
+            else:
+                self.ready.append(r)
+
+    def _launch_batches(self, now):
+        while self.ready and self._free_batch:
+            take = []
+            while self.ready and len(take) < self.max_batch:
+                take.append(self.ready.popleft())
+            slot = self._free_batch.pop(0)
+            self._start("batch", take, slot, now, sum(self._fp[r.rid] for r in take))
+
+    def _start(self, route, reqs, slot, now, fp):
+        h = self.executor.launch(route, reqs, slot)
+        self.inflight.append(_Launch(self._next_lid, route, reqs, slot, h, now, fp))
+        self._next_lid += 1
+        for r in reqs:
+            del self._fp[r.rid]
+
+
+class GpuExecutor:
+    """Runs launches through the library: list batches for small jobs, one
+    graph handle per large job, each slot on its own stream."""
+
+    def __init__(self, batch_slots=2, solo_slots=2, tuning_batch=None, tuning_solo=None,
+                 device="cuda"):
+        import torch
+        from . import Batch, Graph, Tuning  # noqa: F401
+        self.torch = torch
+        self.device = torch.device(device)
+        self.batch_streams = [torch.cuda.Stream(device=self.device) for _ in range(batch_slots)]
+        self.solo_streams = [torch.cuda.Stream(device=self.device) for _ in range(solo_slots)]
+        self.tuning_batch = tuning_batch if tuning_batch is not None else Tuning.default()
+        self.tuning_solo = tuning_solo if tuning_solo is not None else Tuning.default()
+        self._lib = _lib.load()
+
+    def footprint(self, req, route) -> int:
+        """Device bytes the request holds while admitted: its mate output plus
+        the workspace it alone would need (state words, hint bits, control
+        block, descriptors and work items)."""
+        n = req.graph.n
+        if route == "solo":
+            ct = self.tuning_solo.to_c()
+            ws = self._lib.mm_workspace_bytes(n, _byref(ct))
+        else:
+            ct = self.tuning_batch.to_c()
+            vtx = np.array([0, n], dtype=np.int64)
+            ws = self._lib.mm_batch_workspace_bytes(1, _ptr(vtx), _byref(ct))
+        return int(ws) + 256 + 4 * n
+
+    def launch(self, route, reqs, slot):
+        from . import Batch, Graph
+        torch = self.torch
+        if route == "solo":
+            r = reqs[0]
+            s = self.solo_streams[slot]
+            with torch.cuda.stream(s):
+                g = Graph(r.graph.off, r.graph.nbr, symmetric=r.graph.symmetric,
+                          tuning=self.tuning_solo, stream=s)
+                out = torch.empty(r.graph.n, dtype=torch.int32, device=self.device)
+                g.run(out, stream=s)
+                ev = torch.cuda.Event()
+                ev.record(s)
+            return ("solo", g, out, ev, s, None)
+        s = self.batch_streams[slot]
+        sym = all(r.graph.symmetric for r in reqs)
+        with torch.cuda.stream(s):
+            b = Batch.from_list([(r.graph.off, r.graph.nbr) for r in reqs], symmetric=sym,
+                                tuning=self.tuning_batch, stream=s)
+            out = torch.empty(b.N, dtype=torch.int32, device=self.device)
+            b.run(out, stream=s)
+            ev = torch.cuda.Event()
+            ev.record(s)
+        return ("batch", b, out, ev, s, b.vtx_off)
+
+    def done(self, h) -> bool:
+        return h[3].query()
+
+    def finish(self, h):
+        kind, obj, out, ev, s, vtx = h
+        obj.sync(stream=s)  # raises if a wavefront ran out of its loop budget
+        obj.close()
+        if kind == "solo":
+            return [out]
+        return [out[int(vtx[g]):int(vtx[g + 1])] for g in range(len(vtx) - 1)]
+
+
+def _byref(ct):
+    import ctypes
+    return ctypes.byref(ct)
+
+
+def _ptr(a):
+    import ctypes
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def poisson_arrivals(count: int, rate: float, seed: int) -> np.ndarray:
+    """Arrival times (s) of a Poisson process of `rate` requests per second."""
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate, size=count))
+
+
+def run_trace(scheduler: Scheduler, requests, clock=time.perf_counter, timeout: float = 120.0):
+    """Feeds requests to the scheduler at their arrival times (real time) and
+    steps it until every request completed. Returns (completions, wall s)."""
+    reqs = sorted(requests, key=lambda r: r.arrival)
+    t0 = clock()
+    i = 0
+    total = len(reqs)
+    done = 0
+    while done < total:
+        now = clock() - t0
+        while i < total and reqs[i].arrival <= now:
+            scheduler.submit(reqs[i])
+            i += 1
+        done += scheduler.step(now)
+        if now > timeout:
+            raise TimeoutError("trace did not finish in %.0f s (%d of %d done)" % (timeout, done, total))
+    return scheduler.completions, clock() - t0
+
+
+def summarize(completions, wall: float, edges: int) -> dict:
+    lat = np.array([c.latency for c in completions]) * 1e3
+    batches = {c.launch for c in completions if c.route == "batch"}
+    per_batch = len([c for c in completions if c.route == "batch"]) / max(1, len(batches))
+    return {"requests": len(completions),
+            "p50_ms": float(np.percentile(lat, 50)) if len(lat) else math.nan,
+            "p99_ms": float(np.percentile(lat, 99)) if len(lat) else math.nan,
+            "mean_ms": float(lat.mean()) if len(lat) else math.nan,
+            "req_per_s": len(completions) / wall if wall > 0 else math.nan,
+            "gedges_per_s": edges / wall / 1e9 if wall > 0 else math.nan,
+            "batch_launches": len(batches),
+            "mean_jobs_per_batch": per_batch,
+            "solo_launches": len([c for c in completions if c.route == "solo"]),
+            "wall_s": wall}

@@ -39,6 +39,11 @@ def test_version_and_defaults():
     lib.mm_default_tuning(ctypes.byref(t))
     assert t.layout in (_lib.MM_LAYOUT_U8, _lib.MM_LAYOUT_U32, _lib.MM_LAYOUT_U2)
     assert t.wg_size % 64 == 0 and t.wave_vertices % 64 == 0
+    # the ctypes mirror has the C layout: the last fields read back as written
+    assert t.whole_graph_vertices == 16384 and t.iter_cap == 0
+    assert ctypes.sizeof(_lib.mm_tuning) == 56
+    from paper_2507_04420_amd import Tuning
+    assert Tuning.default() == Tuning()  # the Python defaults mirror the library's
 
 
 def test_workspace_bytes():
@@ -101,7 +106,8 @@ def test_create_bad_tuning():
     assert st == _lib.MM_ERR_INVALID_ARG
     assert b"wave_vertices" in lib.mm_last_error()
     for field, bad in (("protocol", 2), ("hint", 3), ("scan_width", 0), ("scan_width", 9),
-                       ("layout", 5), ("stream_loads", 2), ("iter_cap", -1)):
+                       ("layout", 5), ("stream_loads", 2), ("whole_graph_vertices", -1),
+                       ("iter_cap", -1)):
         lib.mm_default_tuning(ctypes.byref(t))
         setattr(t, field, bad)
         st, _ = _create(lib, tuning=ctypes.pointer(t))
@@ -120,6 +126,30 @@ def test_null_handle_calls():
     assert lib.mm_check(None, None, None, c) == _lib.MM_ERR_INVALID_ARG
     assert lib.mm_batch_check(None, None, None, c) == _lib.MM_ERR_INVALID_ARG
     lib.mm_destroy(None)
+
+
+def test_list_batch_argument_errors():
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    t = _lib.mm_tuning()
+    lib.mm_default_tuning(ctypes.byref(t))
+    ws = ctypes.c_void_p(4096 * 256)  # aligned, never dereferenced: creation fails first
+    n = (ctypes.c_int64 * 1)(-1)
+    m = (ctypes.c_int64 * 1)(0)
+    ptrs = (ctypes.c_void_p * 1)(None)
+    st = lib.mm_batch_create_list(ptrs, ptrs, n, m, 1, ws, 1 << 20, 0, ctypes.byref(t), None,
+                                  ctypes.byref(h))
+    assert st == _lib.MM_ERR_INVALID_ARG and not h.value
+    n[0], m[0] = 0, 5  # an empty graph with entries
+    assert lib.mm_batch_create_list(ptrs, ptrs, n, m, 1, ws, 1 << 20, 0, ctypes.byref(t), None,
+                                    ctypes.byref(h)) == _lib.MM_ERR_INVALID_ARG
+    n[0], m[0] = 4, 2  # null device pointers
+    assert lib.mm_batch_create_list(ptrs, ptrs, n, m, 1, ws, 1 << 20, 0, ctypes.byref(t), None,
+                                    ctypes.byref(h)) == _lib.MM_ERR_INVALID_ARG
+    assert lib.mm_batch_create_list(ptrs, ptrs, n, m, -1, ws, 1 << 20, 0, ctypes.byref(t), None,
+                                    ctypes.byref(h)) == _lib.MM_ERR_INVALID_ARG
+    assert lib.mm_batch_create_list(ptrs, ptrs, n, m, 1, ctypes.c_void_p(4096 * 256 + 8), 1 << 20,
+                                    0, ctypes.byref(t), None, ctypes.byref(h)) == _lib.MM_ERR_INVALID_ARG
 
 
 def test_error_raises_python_exception():

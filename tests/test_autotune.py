@@ -1,0 +1,75 @@
+"""Autotuner logic on the CPU: the coordinate search with a synthetic
+objective (no device), rejection of candidates that fail the check, the
+stored-JSON lookup and the degree-based graph classes."""
+import json
+
+import numpy as np
+
+import graphgen
+from paper_2507_04420_amd import Tuning, _lib, autotune
+
+
+class FakeTarget:
+    unit = "x/s"
+    sample = "synthetic"
+
+    def __init__(self, bad_layout=None):
+        self.calls = 0
+        self.bad_layout = bad_layout
+
+    def measure(self, t):
+        self.calls += 1
+        if t.layout == self.bad_layout:
+            return None  # fails the check
+        # best at wave 2048, wg 128, assist 32, hint on, U8 layout
+        score = 100.0
+        score -= abs(np.log2(t.wave_vertices / 2048)) * 5
+        score -= abs(np.log2(t.wg_size / 128)) * 3
+        score -= abs(np.log2(t.assist_after / 32)) * 2
+        score += 4 * t.hint
+        score += {_lib.MM_LAYOUT_U8: 6, _lib.MM_LAYOUT_U32: 0, _lib.MM_LAYOUT_U2: 1}[t.layout]
+        return score
+
+
+def test_search_finds_separable_optimum():
+    r = autotune.search(FakeTarget(), passes=3, log=lambda s: None)
+    t = r["tuning"]
+    assert t["wave_vertices"] == 2048 and t["wg_size"] == 128 and t["assist_after"] == 32
+    assert t["hint"] == 1 and t["layout"] == _lib.MM_LAYOUT_U8
+    assert r["objective"] > r["default_objective"]
+    assert r["rejected"] == 0
+
+
+def test_search_never_keeps_a_rejected_candidate():
+    r = autotune.search(FakeTarget(bad_layout=_lib.MM_LAYOUT_U8), passes=2, log=lambda s: None)
+    assert r["tuning"]["layout"] != _lib.MM_LAYOUT_U8
+    assert r["rejected"] >= 1
+
+
+def test_tuned_lookup(tmp_path, monkeypatch):
+    monkeypatch.setattr(autotune, "TUNED_DIR", str(tmp_path))
+    assert autotune.tuned("rmat", key="dev_1cu") == Tuning.default()
+    t = Tuning.default().as_dict()
+    t["wave_vertices"] = 512
+    (tmp_path / "dev_1cu.json").write_text(json.dumps({"device": "dev_1cu", "classes": {"rmat": {"tuning": t}}}))
+    assert autotune.tuned("rmat", key="dev_1cu").wave_vertices == 512
+    assert autotune.tuned("grid", key="dev_1cu") == Tuning.default()
+
+
+def test_classify():
+    assert autotune.classify(graphgen.grid(50, 60).off) == "grid"
+    assert autotune.classify(graphgen.er(20000, 16, seed=1).off) == "er"
+    assert autotune.classify(graphgen.rmat(16, seed=1).off) == "rmat"
+
+
+def test_stored_tunings_are_valid():
+    # every committed tuning must be accepted by the library's own check
+    import glob
+    import ctypes
+    lib = _lib.load()
+    for path in glob.glob(autotune.TUNED_DIR + "/*.json"):
+        with open(path) as f:
+            doc = json.load(f)
+        for cls, entry in doc["classes"].items():
+            ct = Tuning(**entry["tuning"]).to_c()
+            assert lib.mm_workspace_bytes(1000, ctypes.byref(ct)) > 0, (path, cls)

@@ -133,3 +133,75 @@ def test_batch_stats():
     check_members(mix, mate)
     assert st["sources"] == mix.n
     assert st["pairs"] == int((mate >= 0).sum()) // 2
+
+
+def list_of(parts):
+    return [(torch.from_numpy(p.off.astype(np.int64)).cuda(), torch.from_numpy(p.nbr).cuda())
+            for p in parts]
+
+
+@pytest.mark.parametrize("name", ["u32_cas", "u8_cas", "u2_two_hint"])
+def test_list_batch_mixture(name):
+    mix = mixture_small(G=30, seed=12)
+    parts = [mix.member(g) for g in range(mix.num_graphs)]
+    b = mm.Batch.from_list(list_of(parts), symmetric=True, validate=True, tuning=TUNINGS[name])
+    np.testing.assert_array_equal(b.vtx_off, mix.vtx_off)
+    out = b.run()
+    b.sync()
+    check_members(mix, out.cpu().numpy())
+    assert b.check(out)["ok"]
+
+
+def test_list_batch_edge_cases_and_capture():
+    parts = [graphgen.from_edges(8, [(0, 1), (2, 3), (4, 5), (6, 7)]),
+             graphgen.from_edges(0, np.zeros((0, 2))),
+             graphgen.from_edges(5, np.zeros((0, 2))),
+             graphgen.from_edges(3, [(0, 1), (1, 2), (0, 2)]),
+             graphgen.rmat(12, seed=4)]
+    b = mm.Batch.from_list(list_of(parts), symmetric=True, validate=True, capture=True)
+    out = torch.empty(b.N, dtype=torch.int32, device="cuda")
+    for rep in range(3):
+        out.fill_(-77)
+        b.run(out)
+        b.sync()
+        torch.cuda.synchronize()
+        mate = out.cpu().numpy()
+        np.testing.assert_array_equal(mate[0:8], np.arange(8) ^ 1)
+        np.testing.assert_array_equal(mate[8:13], -1)
+        v = b.vtx_off
+        for g, p in enumerate(parts):
+            assert oracle.check(p, mate[v[g]:v[g + 1]]).ok, (rep, g)
+
+
+def test_empty_list_batch():
+    b = mm.Batch.from_list([], symmetric=True)
+    assert b.N == 0 and b.items == 0
+    b.run(torch.empty(0, dtype=torch.int32, device="cuda"))
+    b.sync()
+
+
+@pytest.mark.parametrize("bad", ["foreign_id", "offsets_end", "offsets_start"])
+def test_list_batch_validate_rejects(bad):
+    good = graphgen.from_edges(4, [(0, 1), (2, 3)])
+    off = good.off.astype(np.int64).copy()
+    nbr = good.nbr.copy()
+    if bad == "foreign_id":
+        nbr[1] = 4
+    elif bad == "offsets_end":
+        off[-1] -= 1
+    else:
+        off[0] = 1
+    parts = [(torch.from_numpy(good.off.astype(np.int64)).cuda(), torch.from_numpy(good.nbr).cuda()),
+             (torch.from_numpy(off).cuda(), torch.from_numpy(nbr).cuda())]
+    with pytest.raises(mm.MMError) as ei:
+        mm.Batch.from_list(parts, validate=True)
+    assert ei.value.status == _lib.MM_ERR_INVALID_GRAPH
+
+
+def test_batch_validate_rejects_offsets_beyond_m():
+    # offsets that point past the neighbour array are reported, never followed
+    off = torch.tensor([0, 5000000, 2, 3], dtype=torch.int64, device="cuda")
+    nbr = torch.tensor([1, 0, 0], dtype=torch.int32, device="cuda")
+    with pytest.raises(mm.MMError) as ei:
+        mm.Batch(off, nbr, [0, 2, 3], validate=True)
+    assert ei.value.status == _lib.MM_ERR_INVALID_GRAPH

@@ -40,6 +40,8 @@ def corrupt(csr, mate, kind, rng, k=5):
         mt[mt[idx]] = -1
         mt[idx] = -1
     elif kind == "nonedge":  # a symmetric pair between two unmatched non-adjacent vertices
+        if np.count_nonzero(mt == -1) < 4 * k:  # near-perfect matchings: free some pairs first
+            mt = corrupt(csr, mt, "unmatch", rng, k=4 * k)
         free = np.flatnonzero(mt == -1)
         done = 0
         for a in rng.permutation(free):

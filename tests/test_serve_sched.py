@@ -1,0 +1,148 @@
+"""Scheduling rules of the serving loop, on the CPU with a simulated
+executor (launch durations are a function of the jobs; nothing touches a
+device): arrival-order admission within the memory budget, small jobs
+coalesced into the next free batch slot, large jobs on solo slots, every
+request completed exactly once."""
+import numpy as np
+import pytest
+
+from paper_2507_04420_amd.serve import Completion, Request, ResidentGraph, Scheduler, run_trace
+
+
+class FakeExecutor:
+    def __init__(self):
+        self.now = 0.0
+        self.launches = []
+        self.live = 0
+        self.peak_live = 0
+
+    def footprint(self, req, route):
+        return 8 * req.graph.n + 4096
+
+    def launch(self, route, reqs, slot):
+        dur = 1e-3 + 1e-9 * sum(r.graph.m for r in reqs)
+        h = {"route": route, "reqs": [r.rid for r in reqs], "slot": slot, "end": self.now + dur}
+        self.launches.append(h)
+        self.live += 1
+        self.peak_live = max(self.peak_live, self.live)
+        return h
+
+    def done(self, h):
+        return self.now >= h["end"]
+
+    def finish(self, h):
+        self.live -= 1
+        return [("mate", rid) for rid in h["reqs"]]
+
+
+def graph(n, m):
+    return ResidentGraph(None, None, n, m)
+
+
+def drive(sched, ex, reqs, dt=1e-4):
+    reqs = sorted(reqs, key=lambda r: r.arrival)
+    i, t, done = 0, 0.0, 0
+    seen_in_use = []
+    while done < len(reqs):
+        ex.now = t
+        while i < len(reqs) and reqs[i].arrival <= t:
+            sched.submit(reqs[i])
+            i += 1
+        done += sched.step(t)
+        seen_in_use.append(sched.in_use)
+        t += dt
+        assert t < 100
+    return seen_in_use
+
+
+def test_every_request_completes_once_and_budget_holds():
+    rng = np.random.default_rng(1)
+    ex = FakeExecutor()
+    budget = 8 * 3_000_000
+    s = Scheduler(ex, hbm_budget=budget, small_edges=100_000, max_batch=16)
+    reqs = []
+    t = 0.0
+    for rid in range(400):
+        t += rng.exponential(1 / 2000)
+        m = int(np.exp(rng.uniform(np.log(1e4), np.log(5e6))))
+        reqs.append(Request(rid, graph(max(2, m // 8), m), t))
+    in_use = drive(s, ex, reqs)
+    assert max(in_use) <= budget and s.peak_in_use <= budget
+    assert sorted(c.rid for c in s.completions) == list(range(400))
+    assert s.in_use == 0 and not s.inflight
+    for c in s.completions:
+        assert c.arrival <= c.admitted <= c.launched <= c.done
+        assert c.mate == ("mate", c.rid)
+        route = "batch" if reqs[c.rid].graph.m <= 100_000 else "solo"
+        assert c.route == route
+
+
+def test_small_jobs_arriving_during_a_batch_join_the_next_launch():
+    ex = FakeExecutor()
+    s = Scheduler(ex, hbm_budget=1 << 40, small_edges=10**6, batch_slots=1, max_batch=100)
+    # one job at t=0 occupies the only batch slot for ~1 ms + 1e-9*m s
+    reqs = [Request(0, graph(1000, 900_000), 0.0)]
+    reqs += [Request(k, graph(100, 1000), 1e-4 * k) for k in range(1, 6)]  # arrive while busy
+    drive(s, ex, reqs)
+    first, second = ex.launches[0], ex.launches[1]
+    assert first["reqs"] == [0]
+    assert second["reqs"] == [1, 2, 3, 4, 5]  # coalesced into one launch
+    assert len(ex.launches) == 2
+
+
+def test_batch_size_cap_and_parallel_slots():
+    ex = FakeExecutor()
+    s = Scheduler(ex, hbm_budget=1 << 40, small_edges=10**6, batch_slots=2, max_batch=3)
+    reqs = [Request(k, graph(100, 1000), 0.0) for k in range(7)]
+    drive(s, ex, reqs)
+    sizes = [len(L["reqs"]) for L in ex.launches]
+    assert sizes[:2] == [3, 3] and sum(sizes) == 7
+    assert ex.peak_live == 2  # both batch slots were busy at once
+
+
+def test_large_jobs_use_solo_slots_and_overlap():
+    ex = FakeExecutor()
+    s = Scheduler(ex, hbm_budget=1 << 40, small_edges=1000, solo_slots=2)
+    reqs = [Request(k, graph(10**5, 10**6), 0.0) for k in range(3)]
+    reqs.append(Request(3, graph(10, 100), 0.0))
+    drive(s, ex, reqs)
+    solo = [L for L in ex.launches if L["route"] == "solo"]
+    assert len(solo) == 3 and {L["slot"] for L in solo} == {0, 1}
+    # the third solo job waited for a slot; the small job behind it waited too (arrival order)
+    assert ex.launches[0]["reqs"] == [0] and ex.launches[1]["reqs"] == [1]
+
+
+def test_head_of_line_blocks_on_memory():
+    ex = FakeExecutor()
+    budget = 8 * 200_000 + 4096 * 3
+    s = Scheduler(ex, hbm_budget=budget, small_edges=10**9, batch_slots=4)
+    reqs = [Request(0, graph(150_000, 10**6), 0.0),   # takes most of the budget
+            Request(1, graph(100_000, 10**5), 1e-5),  # does not fit until 0 is done
+            Request(2, graph(10, 100), 2e-5)]         # fits, but must not pass 1
+    drive(s, ex, reqs)
+    order = [rid for L in ex.launches for rid in L["reqs"]]
+    assert order == [0, 1, 2]
+    c = {x.rid: x for x in s.completions}
+    assert c[1].admitted >= c[0].done and c[2].admitted >= c[1].admitted
+
+
+def test_oversized_request_is_rejected():
+    s = Scheduler(FakeExecutor(), hbm_budget=1000)
+    with pytest.raises(ValueError):
+        s.submit(Request(0, graph(10**6, 10), 0.0))
+
+
+def test_run_trace_with_simulated_clock():
+    ex = FakeExecutor()
+    s = Scheduler(ex, hbm_budget=1 << 40, small_edges=10**6)
+    clock = {"t": 0.0}
+
+    def tick():
+        clock["t"] += 5e-5
+        ex.now = clock["t"]
+        return clock["t"]
+
+    reqs = [Request(k, graph(100, 1000), 1e-3 * k) for k in range(20)]
+    comps, wall = run_trace(s, reqs, clock=tick)
+    assert len(comps) == 20 and all(isinstance(c, Completion) for c in comps)
+    assert wall > 0.019
