@@ -10,6 +10,11 @@ roofline: the sweep kernel's algorithmic bytes per launch
           T_seq = ids SGMM reads) over its mean duration from HIP events
           recorded on the launch stream, against 8 TB/s.
 cpu_baseline: the oracle's single-thread SGMM on the host, on the same graph.
+batch: the 4096-graph mixture in one captured persistent launch against one
+       launch per graph; serve: Poisson request streams over resident graphs
+       (p50/p99 arrival-to-result latency, GEdges/s).
+Tunings come from the package's autotuned table for this device and graph
+class (library defaults where it has none).
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -92,6 +97,57 @@ def cpu_baseline(csr, budget_s: float = 30.0):
             break
     t = float(np.median(times))
     return res, t, len(times)
+
+
+def bench_serve(args, dev):
+    """Serving: Poisson streams of requests over a pool of resident graphs
+    whose entry counts are log-uniform in [1e4, 5e7] (ER, grid and R-MAT
+    kinds); small jobs are batched continuously, large ones run alone."""
+    import torch
+    import graphgen
+    from paper_2507_04420_amd import autotune, serve
+
+    t0 = time.perf_counter()
+    pool = graphgen.serve_pool(args.serve_pool, seed=args.seed)
+    graphs = []
+    for g in range(pool.num_graphs):
+        sub = pool.member(g)
+        off = torch.from_numpy(sub.off).to(dev)
+        nbr = torch.from_numpy(sub.nbr).to(dev)
+        cls = autotune.classify(sub.off)
+        graphs.append(serve.ResidentGraph.from_tensors(off, nbr, True, sub.name,
+                                                       tuning=autotune.tuned(cls)))
+    torch.cuda.synchronize()
+    log("serving pool: %d graphs, M=%d, generated and resident in %.1fs" % (
+        pool.num_graphs, pool.m, time.perf_counter() - t0))
+    free, _ = torch.cuda.mem_get_info()
+    rng = np.random.default_rng(args.seed + 101)
+    out = {"pool_graphs": pool.num_graphs, "pool_entries": int(pool.m), "small_edges": 2_000_000,
+           "hbm_budget_bytes": int(free // 2), "rates": []}
+
+    def scheduler():
+        ex = serve.GpuExecutor(batch_slots=2, solo_slots=2, tuning_batch=autotune.tuned("batch"))
+        return serve.Scheduler(ex, hbm_budget=free // 2, small_edges=2_000_000, max_batch=1024,
+                               batch_slots=2, solo_slots=2, keep_results=False)
+
+    # warm-up: every graph once, so the kernels are loaded and the allocator is primed
+    serve.run_trace(scheduler(), [serve.Request(i, g, 0.0) for i, g in enumerate(graphs)])
+    for rate in args.serve_rates:
+        count = max(20, int(rate * args.serve_seconds))
+        gid = rng.integers(0, len(graphs), size=count)
+        arr = serve.poisson_arrivals(count, rate, seed=args.seed + int(rate))
+        reqs = [serve.Request(i, graphs[g], float(arr[i])) for i, g in enumerate(gid)]
+        s = scheduler()
+        comps, wall = serve.run_trace(s, reqs, timeout=120)
+        edges = int(sum(graphs[g].m for g in gid))
+        r = serve.summarize(comps, wall, edges)
+        r["rate_req_per_s"] = rate
+        r["peak_in_use_bytes"] = int(s.peak_in_use)
+        out["rates"].append({k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()})
+        log("serve %5d req/s: p50 %.3f ms p99 %.3f ms, %.1f GEdges/s, %d batches (%.1f jobs each), %d solo" % (
+            rate, r["p50_ms"], r["p99_ms"], r["gedges_per_s"], r["batch_launches"],
+            r["mean_jobs_per_batch"], r["solo_launches"]))
+    return out
 
 
 def bench_batch(args, tun, dev):
@@ -198,6 +254,12 @@ def main():
     ap.add_argument("--no-stats", action="store_true")
     ap.add_argument("--batch-graphs", type=int, default=4096)
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-rates", type=float, nargs="+", default=[200.0, 1000.0, 2000.0])
+    ap.add_argument("--serve-seconds", type=float, default=1.5)
+    ap.add_argument("--serve-pool", type=int, default=48)
+    ap.add_argument("--untuned", action="store_true",
+                    help="library default tunings instead of the autotuned table")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (read + write of known size), so that "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE can be scaled")
@@ -227,7 +289,8 @@ def main():
     nbr = torch.from_numpy(csr.nbr).to(dev)
     torch.cuda.synchronize()
 
-    tun = mm.Tuning.default()
+    from paper_2507_04420_amd import autotune
+    tun = mm.Tuning.default() if args.untuned else autotune.tuned(config["workload"])
     if args.layout is not None:
         tun.layout = {"u8": _lib.MM_LAYOUT_U8, "u32": _lib.MM_LAYOUT_U32, "u2": _lib.MM_LAYOUT_U2}[args.layout]
     if args.lazy is not None:
@@ -279,7 +342,7 @@ def main():
     chk = oracle.check(csr, mate)
     log("checker: violations=%d size=%d (SGMM %d)" % (chk.violations, chk.size, ref.pairs))
 
-    counters = None
+    counters = conflicts = None
     if not args.no_stats:
         gs = mm.Graph(off, nbr, symmetric=True, stats=True, tuning=tun)
         o2 = gs.run()
@@ -289,8 +352,17 @@ def main():
         counters["checker_violations"] = c2.violations
         gs.close()
         log("counters: %s" % counters)
+        # Table II on this graph: worst (most conflicting edges) of five passes
+        conflicts = mm.conflict_table(off, nbr, runs=5, tuning=tun)
+        log("conflicts (Table II): %s" % conflicts)
 
-    batch = None if args.no_batch else bench_batch(args, tun, dev)
+    del g
+    batch = None
+    if not args.no_batch:
+        tb = mm.Tuning.default() if args.untuned else autotune.tuned("batch")
+        batch = bench_batch(args, tb, dev)
+        batch["tuning"] = tb.as_dict()
+    serving = None if args.no_serve else bench_serve(args, dev)
 
     n, m = csr.n, csr.m
     w = csr.off.dtype.itemsize
@@ -326,6 +398,10 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 5),
             "traffic": traffic,
+            # measured HBM bytes per launch over the same duration: how close the
+            # kernel's real traffic comes to the peak
+            "traffic_frac": (round(traffic / sweep_s / 1e9 / HBM_PEAK_GBS, 5)
+                             if traffic and sweep_s > 0 else None),
             "alg_bytes_per_launch": int(b_sweep),
             "sweep_ms": round(sweep["mean_ms"], 5),
             "pass_alg_bytes": int(b_pass),
@@ -341,7 +417,9 @@ def main():
         "checker": {"violations": chk.violations, "size": chk.size, "size_sgmm": ref.pairs,
                     "t_seq": t_seq},
         "counters": counters,
+        "conflicts": conflicts,
         "batch": batch,
+        "serve": serving,
     }
     print(json.dumps(result), flush=True)
 

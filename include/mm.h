@@ -125,7 +125,9 @@ typedef struct {
 } mm_tuning;
 
 /* Counters of the instrumented kernels (MM_STATS). Conflicts follow Table II
-   of the paper: a failed CAS while reserving u or matching v. */
+   of the paper: a failed CAS while reserving u (Algorithm 1 L11) or taking v
+   (L14). An edge's conflicts are those met from the moment a lane picks the
+   edge (x, y) as its candidate until the edge is matched or found dead. */
 typedef struct {
   uint64_t sources;           /* source vertices visited */
   uint64_t sources_skipped;   /* sources already matched when visited */
@@ -141,7 +143,10 @@ typedef struct {
                                  the same 32-bit word changed (not a conflict) */
   uint64_t pairs;             /* matched pairs committed */
   uint64_t loop_trips;        /* sum over wavefronts of loop trips */
-  uint64_t reserved_[3];
+  uint64_t conflict_max;      /* most conflicts met by one edge */
+  uint64_t conflict_hist[10]; /* edges by conflicts met: 1, 2, 3-4, 5-8, 9-16,
+                                 17-32, 33-64, 65-128, 129-256, >256 (Table II) */
+  uint64_t reserved_[8];
 } mm_stats;
 
 /* Fills *t with the defaults. */
@@ -267,6 +272,17 @@ void mm_batch_destroy(mm_batch_handle h);
  */
 mm_status mm_check(mm_handle h, void* stream, const int32_t* match, int64_t* counts);
 mm_status mm_batch_check(mm_batch_handle h, void* stream, const int32_t* match, int64_t* counts);
+
+/* ------------------------------------------------------------------ pair list
+ * The matched pairs of a mate array as a list (the `matches` output of
+ * Algorithm 1): pairs (device, 2 x cap int32) receives (u, v), u < v, for
+ * every matched pair, each once, in no particular order; *count (host)
+ * receives the number of pairs. Waits for `stream`. If count > cap, only cap
+ * pairs are written and MM_ERR_OUT_OF_MEMORY is returned with *count set.
+ * n / 2 pairs always suffice.
+ */
+mm_status mm_pairs(mm_handle h, void* stream, const int32_t* match, int32_t* pairs, int64_t cap,
+                   int64_t* count);
 
 /* Thread-local description of the last non-OK status returned on this thread. */
 const char* mm_last_error(void);

@@ -17,7 +17,8 @@ import numpy as np
 from . import _lib
 from ._lib import MMError  # noqa: F401
 
-__all__ = ["Graph", "Batch", "Tuning", "MMError", "maximal_matching", "library_path", "version"]
+__all__ = ["Graph", "Batch", "Tuning", "MMError", "maximal_matching", "conflict_table", "conflict_row",
+           "library_path", "version"]
 
 
 def library_path() -> str:
@@ -157,7 +158,7 @@ class Graph:
     def stats(self, stream=None) -> dict:
         s = _lib.mm_stats()
         _lib.check(_lib.load().mm_get_stats(self.handle, _stream_ptr(stream), ctypes.byref(s)))
-        return {f: int(getattr(s, f)) for f, _ in _lib.mm_stats._fields_ if not f.startswith("reserved")}
+        return _lib.stats_dict(s)
 
     def timing(self) -> dict:
         """Sweep-kernel durations of the passes since the last call (ms)."""
@@ -176,6 +177,19 @@ class Graph:
         _lib.check(_lib.load().mm_check(self.handle, _stream_ptr(stream),
                                          ctypes.c_void_p(mate.data_ptr()), c))
         return _check_result(c)
+
+    def pairs(self, mate, stream=None):
+        """The matched pairs of a mate tensor as an (P, 2) int32 tensor of
+        (u, v), u < v (mm_pairs); the order of the rows is not specified."""
+        import torch
+        _check_mate(mate, self.n)
+        cap = self.n // 2
+        out = torch.empty(max(cap, 1) * 2, dtype=torch.int32, device=self.device)
+        cnt = ctypes.c_int64()
+        _lib.check(_lib.load().mm_pairs(self.handle, _stream_ptr(stream),
+                                        ctypes.c_void_p(mate.data_ptr()),
+                                        ctypes.c_void_p(out.data_ptr()), cap, ctypes.byref(cnt)))
+        return out[:2 * cnt.value].view(-1, 2)
 
     def reset_stats(self, stream=None) -> None:
         _lib.check(_lib.load().mm_reset_stats(self.handle, _stream_ptr(stream)))
@@ -310,7 +324,7 @@ class Batch:
     def stats(self, stream=None) -> dict:
         s = _lib.mm_stats()
         _lib.check(_lib.load().mm_batch_get_stats(self._h, _stream_ptr(stream), ctypes.byref(s)))
-        return {f: int(getattr(s, f)) for f, _ in _lib.mm_stats._fields_ if not f.startswith("reserved")}
+        return _lib.stats_dict(s)
 
     def close(self) -> None:
         if getattr(self, "_h", None) is not None:
@@ -322,6 +336,44 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+CONFLICT_BINS = ("1", "2", "3-4", "5-8", "9-16", "17-32", "33-64", "65-128", "129-256", ">256")
+
+
+def conflict_row(stats: dict) -> dict:
+    """Table II's columns from one instrumented pass: the most conflicts met
+    by one edge, the total conflicts (failed reserves of u plus failed takes
+    of v), the edges that met at least one, their mean, and the distribution
+    of those edges over the table's bins."""
+    hist = list(stats["conflict_hist"])
+    edges = sum(hist)
+    total = stats["reserve_conflicts"] + stats["match_conflicts"]
+    return {"max_per_edge": stats["conflict_max"], "total": total, "edges": edges,
+            "avg_per_edge": (total / edges) if edges else 0.0,
+            "distribution": dict(zip(CONFLICT_BINS, hist))}
+
+
+def conflict_table(offsets, neighbors, *, runs: int = 5, symmetric: bool = True,
+                   tuning: Tuning | None = None) -> dict:
+    """Table II for one graph: `runs` instrumented passes, keeping the one in
+    which the most edges met a conflict (the paper's selection rule)."""
+    best = None
+    g = Graph(offsets, neighbors, symmetric=symmetric, stats=True, tuning=tuning)
+    try:
+        for _ in range(runs):
+            g.reset_stats()
+            g.run()
+            g.sync()
+            row = conflict_row(g.stats())
+            if best is None or row["edges"] > best["edges"]:
+                best = row
+    finally:
+        g.close()
+    best["runs"] = runs
+    best["entries"] = int(neighbors.numel())
+    best["edge_ratio"] = best["edges"] / max(1, int(neighbors.numel()))
+    return best
 
 
 def maximal_matching(offsets, neighbors, *, symmetric: bool = False, tuning: Tuning | None = None,

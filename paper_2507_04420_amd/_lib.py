@@ -54,8 +54,15 @@ class mm_stats(ctypes.Structure):
     _fields_ = [(name, ctypes.c_uint64) for name in (
         "sources", "sources_skipped", "touched", "assist_reads", "reserve_attempts",
         "reserve_conflicts", "reserve_matched", "match_attempts", "match_conflicts",
-        "match_matched", "word_retries", "pairs", "loop_trips", "reserved0", "reserved1",
-        "reserved2")]
+        "match_matched", "word_retries", "pairs", "loop_trips", "conflict_max")] + [
+        ("conflict_hist", ctypes.c_uint64 * 10), ("reserved_", ctypes.c_uint64 * 8)]
+
+
+def stats_dict(s: mm_stats) -> dict:
+    d = {f: int(getattr(s, f)) for f, _ in mm_stats._fields_
+         if f not in ("conflict_hist", "reserved_")}
+    d["conflict_hist"] = [int(v) for v in s.conflict_hist]
+    return d
 
 
 # Every entry point declared in include/mm.h, with its ctypes signature.
@@ -85,6 +92,7 @@ SIGNATURES = {
     "mm_batch_destroy": (None, [_P]),
     "mm_check": (_I32, [_P, _P, _P, ctypes.POINTER(_I64)]),
     "mm_batch_check": (_I32, [_P, _P, _P, ctypes.POINTER(_I64)]),
+    "mm_pairs": (_I32, [_P, _P, _P, _P, _I64, ctypes.POINTER(_I64)]),
     "mm_last_error": (ctypes.c_char_p, []),
     "mm_version": (ctypes.c_char_p, []),
 }

@@ -178,18 +178,18 @@ def search(target, start: Tuning | None = None, passes: int = 2, dims=None, log=
             "rejected": rejected}
 
 
-def _targets(classes, seed):
+def _targets(classes, seed, rmat_scale=27, grid_side=16384):
     import graphgen
     out = {}
     for c in classes:
         if c == "rmat":
-            out[c] = lambda: SingleTarget(graphgen.rmat(24, seed=seed))
+            out[c] = lambda: SingleTarget(graphgen.rmat(rmat_scale, seed=seed))
         elif c == "grid":
-            out[c] = lambda: SingleTarget(graphgen.grid(8192, 8192))
+            out[c] = lambda: SingleTarget(graphgen.grid(grid_side, grid_side))
         elif c == "er":
             out[c] = lambda: SingleTarget(graphgen.er(1 << 22, 16, seed=seed))
         elif c == "batch":
-            out[c] = lambda: BatchTarget(graphgen.mixture(1024, seed=seed))
+            out[c] = lambda: BatchTarget(graphgen.mixture(4096, seed=seed))
         else:
             raise ValueError("unknown graph class %r" % c)
     return out
@@ -225,6 +225,8 @@ def main(argv=None):
     ap.add_argument("--classes", default="batch,rmat,grid,er")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--passes", type=int, default=2)
+    ap.add_argument("--rmat-scale", type=int, default=27)
+    ap.add_argument("--grid-side", type=int, default=16384)
     ap.add_argument("--out", default=None, help="JSON file (default: the package's tuned/ entry)")
     a = ap.parse_args(argv)
     key = device_key()
@@ -233,7 +235,7 @@ def main(argv=None):
     if os.path.exists(out):
         with open(out) as f:
             doc = json.load(f)
-    for c, make in _targets(a.classes.split(","), a.seed).items():
+    for c, make in _targets(a.classes.split(","), a.seed, a.rmat_scale, a.grid_side).items():
         t0 = time.time()
         print("== %s" % c, flush=True)
         r = search(make(), passes=a.passes, log=lambda s: print(s, flush=True))

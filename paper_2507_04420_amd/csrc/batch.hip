@@ -591,7 +591,7 @@ mm_status mm_batch_get_stats(mm_batch_handle b, void* stream, mm_stats* out) {
   if (!b || !out) return fail(MM_ERR_INVALID_ARG, "null argument");
   if (!(b->flags & MM_STATS)) return fail(MM_ERR_UNSUPPORTED, "batch was created without MM_STATS");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  unsigned long long c[16] = {};
+  unsigned long long c[mmi::kStatWords] = {};
   HIP_TRY(hipMemcpyAsync(c, b->ws + kStatsOffset, sizeof(c), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   mmi::stats_from_counters(c, out);

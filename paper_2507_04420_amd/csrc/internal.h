@@ -39,6 +39,7 @@ constexpr size_t kCtrlBytes = 4096;
 constexpr size_t kStatsOffset = 256;
 constexpr size_t kQueueOffset = 1024;
 constexpr size_t kCheckOffset = 2048;
+constexpr int kStatWords = 32;  // 64-bit counters at kStatsOffset
 
 }  // namespace mmi
 

@@ -19,6 +19,7 @@ using namespace mmk;
 using mmi::fail;
 using mmi::kCtrlBytes;
 using mmi::kStatsOffset;
+using mmi::kStatWords;
 using mmi::round_up;
 #define HIP_TRY MMI_HIP_TRY
 
@@ -88,6 +89,8 @@ void stats_from_counters(const unsigned long long* c, mm_stats* out) {
   out->word_retries = c[S_WORD_RETRY];
   out->pairs = c[S_PAIRS];
   out->loop_trips = c[S_TRIPS];
+  out->conflict_max = c[S_CMAX];
+  for (int b = 0; b < 10; ++b) out->conflict_hist[b] = c[S_H0 + b];
 }
 
 }  // namespace mmi
@@ -470,7 +473,7 @@ mm_status mm_get_stats(mm_handle g, void* stream, mm_stats* out) {
   if (!g || !out) return fail(MM_ERR_INVALID_ARG, "null argument");
   if (!(g->flags & MM_STATS)) return fail(MM_ERR_UNSUPPORTED, "handle was created without MM_STATS");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  unsigned long long c[16] = {};
+  unsigned long long c[kStatWords] = {};
   HIP_TRY(hipMemcpyAsync(c, g->ws + kStatsOffset, sizeof(c), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   mmi::stats_from_counters(c, out);
@@ -479,7 +482,7 @@ mm_status mm_get_stats(mm_handle g, void* stream, mm_stats* out) {
 
 mm_status mm_reset_stats(mm_handle g, void* stream) {
   if (!g) return fail(MM_ERR_INVALID_ARG, "handle is null");
-  HIP_TRY(hipMemsetAsync(g->ws + kStatsOffset, 0, 16 * sizeof(unsigned long long),
+  HIP_TRY(hipMemsetAsync(g->ws + kStatsOffset, 0, kStatWords * sizeof(unsigned long long),
                          static_cast<hipStream_t>(stream)));
   return MM_OK;
 }

@@ -73,24 +73,47 @@ struct SweepParams {
   uint32_t* err;           // bit 0: loop-trip budget exceeded
 };
 
+// Counters of the instrumented build. S_H0 .. S_H0+9: edges by the number of
+// conflicts they met, in Table II's bins (1, 2, 3-4, ..., 129-256, >256);
+// S_CMAX: the most conflicts one edge met.
 enum : int {
   S_SOURCES = 0, S_SKIPPED, S_TOUCHED, S_ASSIST, S_RES_ATT, S_RES_CONF, S_RES_MCHD, S_MAT_ATT,
-  S_MAT_CONF, S_MAT_MCHD, S_WORD_RETRY, S_PAIRS, S_TRIPS, S_NUM
+  S_MAT_CONF, S_MAT_MCHD, S_WORD_RETRY, S_PAIRS, S_TRIPS, S_H0, S_CMAX = S_H0 + 10, S_NUM
 };
 
 template <bool ON>
 struct Counters {
   __device__ __forceinline__ void add(int, uint32_t) {}
+  __device__ __forceinline__ void edge_done(uint32_t) {}
   __device__ __forceinline__ void flush(unsigned long long*) {}
 };
 template <>
 struct Counters<true> {
   uint32_t c[S_NUM] = {};
   __device__ __forceinline__ void add(int k, uint32_t v) { c[k] += v; }
+  // An edge's processing ended after `conf` conflicts.
+  __device__ __forceinline__ void edge_done(uint32_t conf) {
+    if (!conf) return;
+    const int bin = conf == 1 ? 0 : min(9, 32 - __clz((int)(conf - 1)));  // ceil(log2 conf)
+#pragma unroll
+    for (int b = 0; b < 10; ++b)
+      if (b == bin) c[S_H0 + b] += 1;  // unrolled: the array stays in registers
+    c[S_CMAX] = conf > c[S_CMAX] ? conf : c[S_CMAX];
+  }
   __device__ __forceinline__ void flush(unsigned long long* out) {
 #pragma unroll
     for (int k = 0; k < S_NUM; ++k) {
       unsigned long long s = c[k];
+      if (k == S_CMAX) {
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) {
+          const unsigned long long o = __shfl_xor(s, d, 64);
+          s = o > s ? o : s;
+        }
+        if ((threadIdx.x & 63) == 0 && s)
+          __hip_atomic_fetch_max(out + k, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        continue;
+      }
 #pragma unroll
       for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d, 64);
       if ((threadIdx.x & 63) == 0 && s)
@@ -179,6 +202,7 @@ __device__ __forceinline__ void sweep_block(const SweepParams& a, const OffT* __
   }
   int k = 0, nids = 0, steps = 0;
   uint32_t xword = 0, vguess = 0;
+  uint32_t econf = 0;  // conflicts met by the current edge (instrumented build)
   // Results of the operations issued on a trip, one register per phase:
   // different lanes issue different phases on the same trip, and a shared
   // destination register would force a wait between them.
@@ -216,6 +240,10 @@ __device__ __forceinline__ void sweep_block(const SweepParams& a, const OffT* __
   };
   // The current edge cannot be matched because w (u or v) is matched.
   auto edge_dead = [&](int64_t w) {
+    if (STATS) {
+      cnt.edge_done(econf);
+      econf = 0;
+    }
     if (w == x) phase = P_IDLE; else advance();
   };
 
@@ -248,7 +276,10 @@ __device__ __forceinline__ void sweep_block(const SweepParams& a, const OffT* __
           if (STATS) cnt.add(S_RES_MCHD, 1);
           edge_dead(u);
         } else {
-          if (STATS) cnt.add(S_RES_CONF, 1);
+          if (STATS) {
+            cnt.add(S_RES_CONF, 1);
+            ++econf;
+          }
           phase = P_CHK;
         }
         break;
@@ -276,13 +307,20 @@ __device__ __forceinline__ void sweep_block(const SweepParams& a, const OffT* __
         }
         if (won) {
           L.commit(u, v);
-          if (STATS) cnt.add(S_PAIRS, 1);
+          if (STATS) {
+            cnt.add(S_PAIRS, 1);
+            cnt.edge_done(econf);
+            econf = 0;
+          }
           phase = P_IDLE;
         } else if (s == R_ACC) {  // CAS lost to a change in another byte of the word
           if (STATS) cnt.add(S_WORD_RETRY, 1);
           vguess = mat_w;
         } else if (s == R_RSVD) {
-          if (STATS) cnt.add(S_MAT_CONF, 1);
+          if (STATS) {
+            cnt.add(S_MAT_CONF, 1);
+            ++econf;
+          }
           phase = P_MATW;
         } else {
           if (STATS) cnt.add(S_MAT_MCHD, 1);

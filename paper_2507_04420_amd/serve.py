@@ -40,10 +40,11 @@ class ResidentGraph:
     m: int
     symmetric: bool = True
     name: str = ""
+    tuning: object = None  # used when the graph runs alone (large jobs)
 
     @classmethod
-    def from_tensors(cls, off, nbr, symmetric=True, name=""):
-        return cls(off, nbr, off.numel() - 1, nbr.numel(), symmetric, name)
+    def from_tensors(cls, off, nbr, symmetric=True, name="", tuning=None):
+        return cls(off, nbr, off.numel() - 1, nbr.numel(), symmetric, name, tuning)
 
 
 @dataclass
@@ -208,7 +209,7 @@ class GpuExecutor:
         block, descriptors and work items)."""
         n = req.graph.n
         if route == "solo":
-            ct = self.tuning_solo.to_c()
+            ct = (req.graph.tuning or self.tuning_solo).to_c()
             ws = self._lib.mm_workspace_bytes(n, _byref(ct))
         else:
             ct = self.tuning_batch.to_c()
@@ -224,7 +225,7 @@ class GpuExecutor:
             s = self.solo_streams[slot]
             with torch.cuda.stream(s):
                 g = Graph(r.graph.off, r.graph.nbr, symmetric=r.graph.symmetric,
-                          tuning=self.tuning_solo, stream=s)
+                          tuning=r.graph.tuning or self.tuning_solo, stream=s)
                 out = torch.empty(r.graph.n, dtype=torch.int32, device=self.device)
                 g.run(out, stream=s)
                 ev = torch.cuda.Event()

@@ -156,3 +156,17 @@ def test_error_raises_python_exception():
     with pytest.raises(_lib.MMError) as ei:
         _lib.check(_lib.MM_ERR_INVALID_ARG)
     assert ei.value.status == _lib.MM_ERR_INVALID_ARG
+
+
+def test_stats_struct_and_conflict_row():
+    import paper_2507_04420_amd as mm
+    assert ctypes.sizeof(_lib.mm_stats) == 32 * 8
+    s = _lib.mm_stats()
+    s.reserve_conflicts, s.match_conflicts, s.conflict_max = 7, 3, 5
+    for b, c in enumerate([4, 1, 0, 1]):
+        s.conflict_hist[b] = c
+    d = _lib.stats_dict(s)
+    row = mm.conflict_row(d)
+    assert row["total"] == 10 and row["edges"] == 6 and row["max_per_edge"] == 5
+    assert row["distribution"]["1"] == 4 and row["distribution"]["5-8"] == 1
+    assert abs(row["avg_per_edge"] - 10 / 6) < 1e-12

@@ -12,6 +12,7 @@ Several maximal matchings are correct and the method is non-deterministic
   * the size is reported beside SGMM's and is at least half of it (a maximal
     matching has at least half the pairs of any matching).
 """
+import ctypes
 import itertools
 import random
 
@@ -291,3 +292,89 @@ def test_loop_budget_reports_no_progress():
     out = h2.run()
     h2.sync()
     assert_parity(g, out.cpu().numpy(), same_size_as=150)
+
+
+# ---------------------------------------------------------------- Table II instrumentation
+
+def check_conflict_row(row, st):
+    hist = st["conflict_hist"]
+    edges = sum(hist)
+    total = st["reserve_conflicts"] + st["match_conflicts"]
+    assert row["edges"] == edges and row["total"] == total
+    # each conflicting edge met at least its bin's lower bound, at most its upper
+    lo = [1, 2, 3, 5, 9, 17, 33, 65, 129, 257]
+    hi = [1, 2, 4, 8, 16, 32, 64, 128, 256, None]
+    assert sum(l * c for l, c in zip(lo, hist)) <= total
+    if hist[-1] == 0:
+        assert total <= sum(h * c for h, c in zip(hi, hist))
+    if edges == 0:
+        assert total == 0 and st["conflict_max"] == 0
+    else:
+        top = max(b for b in range(10) if hist[b])
+        assert lo[top] <= st["conflict_max"] and (hi[top] is None or st["conflict_max"] <= hi[top])
+        assert st["conflict_max"] <= total
+
+
+@pytest.mark.parametrize("graph", ["star", "clique", "rmat_unpermuted", "rmat"])
+def test_conflict_histogram_invariants(graph):
+    if graph == "star":
+        g = graphgen.from_edges(100_001, [(0, j) for j in range(1, 100_001)])
+    elif graph == "clique":
+        g = graphgen.from_edges(400, list(itertools.combinations(range(400), 2)))
+    elif graph == "rmat_unpermuted":
+        g = graphgen.rmat(16, seed=3, permute=False)
+    else:
+        g = graphgen.rmat(18, seed=2)
+    for t in (mm.Tuning(), mm.Tuning(layout=_lib.MM_LAYOUT_U8, lazy_init=1)):
+        mate, st = gpu_match(g, t, stats=True)
+        assert_parity(g, mate)
+        check_conflict_row(mm.conflict_row(st), st)
+
+
+def test_conflict_table_worst_of_runs():
+    g = graphgen.from_edges(600, list(itertools.combinations(range(600), 2)))
+    off, nbr = to_dev(g)
+    row = mm.conflict_table(off, nbr, runs=5)
+    assert row["runs"] == 5 and row["entries"] == g.m
+    assert 0 <= row["edge_ratio"] <= 1
+    assert sum(row["distribution"].values()) == row["edges"]
+
+
+# ---------------------------------------------------------------- pair-list output
+
+@pytest.mark.parametrize("graph", ["rmat", "grid", "empty", "single_edge"])
+def test_pair_list_matches_mates(graph):
+    if graph == "rmat":
+        g = graphgen.rmat(16, seed=5)
+    elif graph == "grid":
+        g = graphgen.grid(129, 77)
+    elif graph == "empty":
+        g = graphgen.from_edges(7, np.zeros((0, 2)))
+    else:
+        g = graphgen.from_edges(2, [(0, 1)])
+    off, nbr = to_dev(g)
+    h = mm.Graph(off, nbr, symmetric=True)
+    mate = h.run()
+    h.sync()
+    pairs = h.pairs(mate).cpu().numpy()
+    mt = mate.cpu().numpy()
+    c = assert_parity(g, mt)
+    assert pairs.shape == (c.size, 2)
+    assert (pairs[:, 0] < pairs[:, 1]).all()
+    assert (mt[pairs[:, 0]] == pairs[:, 1]).all() and (mt[pairs[:, 1]] == pairs[:, 0]).all()
+    assert len(set(map(tuple, pairs.tolist()))) == c.size  # each pair once
+
+
+def test_pair_list_small_buffer_reports_count():
+    g = graphgen.from_edges(8, [(0, 1), (2, 3), (4, 5), (6, 7)])
+    off, nbr = to_dev(g)
+    h = mm.Graph(off, nbr, symmetric=True)
+    mate = h.run()
+    h.sync()
+    buf = torch.full((4,), -5, dtype=torch.int32, device="cuda")  # room for 2 pairs
+    cnt = ctypes.c_int64()
+    st = _lib.load().mm_pairs(h.handle, None, ctypes.c_void_p(mate.data_ptr()),
+                              ctypes.c_void_p(buf.data_ptr()), 2, ctypes.byref(cnt))
+    assert st == _lib.MM_ERR_OUT_OF_MEMORY and cnt.value == 4
+    b = buf.cpu().numpy().reshape(2, 2)
+    assert all(row[1] == row[0] + 1 and row[0] % 2 == 0 for row in b)
