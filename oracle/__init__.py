@@ -13,6 +13,11 @@ Functions (all CPU; see ``oracle.c`` for the definitions they follow):
                               (Section II-B's two conditions, plus mate-array
                               well-formedness), with per-class counts.
 * ``enumerate_matchings(csr, maximal_only)``  brute force, n <= 20.
+* ``greedy_weighted(csr, seed)``  the matching iterated Endpoints Mutual
+                              Selection (Section II-C) reaches with fixed
+                              pseudo-random edge weights: the greedy matching
+                              in descending weight order.
+* ``edge_weight(u, v, seed)``, ``splitmix64(x)``  its weights.
 
 Pins (tests/test_oracle.py): the worked example of Fig. 1 / Fig. 6, closed
 forms on paths, stars, cliques, complete bipartite graphs, grids and disjoint
@@ -61,6 +66,12 @@ def _load():
         lib.oracle_check.argtypes = [I64, P, I32, P, P, P]
         lib.oracle_enumerate.restype = I64
         lib.oracle_enumerate.argtypes = [I64, P, I32, P, I32, P, I64]
+        lib.oracle_greedy_weighted.restype = I64
+        lib.oracle_greedy_weighted.argtypes = [I64, P, I32, P, ctypes.c_uint64, P]
+        lib.oracle_edge_weight.restype = ctypes.c_uint64
+        lib.oracle_edge_weight.argtypes = [I64, I64, ctypes.c_uint64]
+        lib.oracle_splitmix64.restype = ctypes.c_uint64
+        lib.oracle_splitmix64.argtypes = [ctypes.c_uint64]
         _lib = lib
         return lib
 
@@ -142,3 +153,23 @@ def enumerate_matchings(csr, maximal_only: bool = True) -> np.ndarray:
     lib.oracle_enumerate(n, off.ctypes.data, off64, nbr.ctypes.data, int(maximal_only),
                          out.ctypes.data, cnt)
     return out[:, :n]
+
+
+def greedy_weighted(csr, seed: int):
+    """(mate, pairs): the greedy matching over undirected edges in descending
+    order of edge_weight (ties: smaller (min, max) key first)."""
+    off, off64, nbr = _graph_args(csr)
+    mate = np.empty(csr.n, dtype=np.int32)
+    pairs = _load().oracle_greedy_weighted(csr.n, off.ctypes.data, off64, nbr.ctypes.data,
+                                           seed, mate.ctypes.data)
+    if pairs < 0:
+        raise MemoryError("oracle_greedy_weighted ran out of memory")
+    return mate, int(pairs)
+
+
+def edge_weight(u: int, v: int, seed: int) -> int:
+    return int(_load().oracle_edge_weight(u, v, seed))
+
+
+def splitmix64(x: int) -> int:
+    return int(_load().oracle_splitmix64(x))

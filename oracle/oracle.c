@@ -23,6 +23,17 @@
  *                   Violations are counted, never short-circuited.
  *   oracle_enumerate  Brute force over all matchings of a graph with at most
  *                   20 vertices, optionally keeping only the maximal ones.
+ *   oracle_greedy_weighted  The matching that iterated Endpoints Mutual
+ *                   Selection (Section II-C) reaches when every vertex selects
+ *                   its heaviest free edge under fixed pseudo-random edge
+ *                   weights: an edge selected by both ends is always the
+ *                   heaviest free edge at both, so the process ends in the
+ *                   greedy matching over edges in descending weight order.
+ *                   This is that greedy matching, computed directly: sort the
+ *                   undirected edges, then take each whose ends are free.
+ *   oracle_edge_weight  The edge weight used by it: SplitMix64 (Steele, Lea
+ *                   and Flood, OOPSLA 2014) of the seed, xor the edge key
+ *                   (min << 32 | max), passed through SplitMix64 again.
  *
  * Graph format (Section II-A): CSR offsets (n+1 entries, int32 or int64) and
  * neighbours (int32). A non-symmetric CSR is read as the undirected union of
@@ -128,6 +139,68 @@ void oracle_check(int64_t n, const void *off, int32_t off64, const int32_t *nbr,
   out[5] = matched / 2;
   out[6] = bad_in;
   out[7] = matched;
+}
+
+/* ---- weighted greedy (the fixed point of iterated mutual selection) ---- */
+
+/* One SplitMix64 output for state x: the state advanced by the golden gamma,
+   then the published mixing function. */
+static uint64_t splitmix64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+uint64_t oracle_splitmix64(uint64_t x) { return splitmix64(x); }
+
+uint64_t oracle_edge_weight(int64_t a, int64_t b, uint64_t seed) {
+  const uint64_t u = (uint64_t)(a < b ? a : b), v = (uint64_t)(a < b ? b : a);
+  return splitmix64(splitmix64(seed) ^ ((u << 32) | v));
+}
+
+typedef struct {
+  uint64_t w, key;
+} wedge;
+
+/* heavier first; equal weights: smaller key first */
+static int wedge_cmp(const void *pa, const void *pb) {
+  const wedge *a = (const wedge *)pa, *b = (const wedge *)pb;
+  if (a->w != b->w) return a->w > b->w ? -1 : 1;
+  if (a->key != b->key) return a->key < b->key ? -1 : 1;
+  return 0;
+}
+
+/* mt receives the mate of every vertex (-1: unmatched); returns the number
+   of pairs, or -1 if memory runs out. Entries are read as undirected edges. */
+int64_t oracle_greedy_weighted(int64_t n, const void *off, int32_t off64, const int32_t *nbr,
+                               uint64_t seed, int32_t *mt) {
+  const int64_t m = off_at(off, off64, n);
+  wedge *e = (wedge *)malloc(sizeof(wedge) * (size_t)(m > 0 ? m : 1));
+  if (!e) return -1;
+  int64_t k = 0;
+  for (int64_t x = 0; x < n; ++x)
+    for (int64_t i = off_at(off, off64, x); i < off_at(off, off64, x + 1); ++i) {
+      const int64_t y = nbr[i];
+      if (y == x) continue;
+      const uint64_t u = (uint64_t)(x < y ? x : y), v = (uint64_t)(x < y ? y : x);
+      e[k].key = (u << 32) | v;
+      e[k].w = oracle_edge_weight(x, y, seed);
+      ++k;
+    }
+  qsort(e, (size_t)k, sizeof(wedge), wedge_cmp); /* both orientations sort together */
+  for (int64_t v = 0; v < n; ++v) mt[v] = -1;
+  int64_t pairs = 0;
+  for (int64_t j = 0; j < k; ++j) {
+    const int64_t u = (int64_t)(e[j].key >> 32), v = (int64_t)(e[j].key & 0xffffffffu);
+    if (mt[u] == -1 && mt[v] == -1) {
+      mt[u] = (int32_t)v;
+      mt[v] = (int32_t)u;
+      ++pairs;
+    }
+  }
+  free(e);
+  return pairs;
 }
 
 /* ---- brute-force enumeration (n <= 20) ---- */

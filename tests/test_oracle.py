@@ -343,3 +343,92 @@ def test_checker_int32_offsets():
     g32 = g.with_int32_offsets()
     assert oracle.check(g32, mate).ok
     np.testing.assert_array_equal(oracle.sgmm(g32).mate, oracle.sgmm(g).mate)
+
+
+# ---------------------------------------------------------------- weighted greedy (EMS fixed point)
+
+def test_splitmix64_published_sequence():
+    # SplitMix64 from seed 1234567: the first outputs of the published reference
+    # generator (state advanced by the golden gamma before each output)
+    want = [6457827717110365317, 3203168211198807973, 9817491932198370423,
+            4593380528125082431, 16408922859458223821]
+    state = 1234567
+    got = []
+    for _ in range(5):
+        got.append(oracle.splitmix64(state))
+        state = (state + 0x9E3779B97F4A7C15) % (1 << 64)
+    assert got == want
+
+
+def test_edge_weight_is_symmetric_and_seeded():
+    for a, b in [(0, 1), (5, 3), (1000, 7), (2**31 - 2, 2**31 - 1)]:
+        assert oracle.edge_weight(a, b, 9) == oracle.edge_weight(b, a, 9)
+    assert oracle.edge_weight(0, 1, 1) != oracle.edge_weight(0, 1, 2)
+    assert oracle.edge_weight(0, 1, 1) != oracle.edge_weight(0, 2, 1)
+    # the published mix of the seed, xor the key, mixed again
+    assert oracle.edge_weight(3, 5, 7) == oracle.splitmix64(oracle.splitmix64(7) ^ ((3 << 32) | 5))
+
+
+def weight_rank(csr, seed):
+    ws = {}
+    for x in range(csr.n):
+        for i in range(int(csr.off[x]), int(csr.off[x + 1])):
+            y = int(csr.nbr[i])
+            if y != x:
+                e = (min(x, y), max(x, y))
+                ws[e] = oracle.edge_weight(x, y, seed)
+    order = sorted(ws, key=lambda e: (-ws[e], e))
+    return {e: r for r, e in enumerate(order)}
+
+
+def lex_first_by(rank, matchings):
+    best = None
+    for m in matchings:
+        key = sorted(rank[e] for e in pairs_of(m))
+        if best is None or key < best[0]:
+            best = (key, m)
+    return best[1]
+
+
+@pytest.mark.parametrize("seed", range(25))
+def test_greedy_weighted_is_lex_first_under_weight_order(seed):
+    rng = random.Random(seed)
+    n = rng.randint(1, 10)
+    edges = [(a, b) for a in range(n) for b in range(a + 1, n) if rng.random() < 0.45]
+    if rng.random() < 0.3 and n > 1:
+        edges.append((0, 0))  # loops are never selected
+    g = graphgen.from_edges(n, edges or np.zeros((0, 2)), drop_loops=False)
+    mate, pairs = oracle.greedy_weighted(g, seed)
+    assert oracle.check(g, mate).ok
+    mm = oracle.enumerate_matchings(g, maximal_only=True)
+    np.testing.assert_array_equal(mate, lex_first_by(weight_rank(g, seed), mm))
+    assert pairs == int((mate >= 0).sum()) // 2
+
+
+def test_greedy_weighted_closed_forms():
+    # every maximal matching of K_n has floor(n/2) pairs, of a star 1, of a
+    # disjoint K2 union all of them (the unique one)
+    for n in (2, 3, 8, 11):
+        k = graphgen.from_edges(n, [(i, j) for i in range(n) for j in range(i + 1, n)])
+        assert oracle.greedy_weighted(k, 3)[1] == n // 2
+    star = graphgen.from_edges(50, [(0, j) for j in range(1, 50)])
+    mate, pairs = oracle.greedy_weighted(star, 4)
+    assert pairs == 1 and mate[0] > 0
+    # the star's heaviest edge is the one taken
+    ws = [oracle.edge_weight(0, j, 4) for j in range(1, 50)]
+    assert mate[0] == 1 + int(np.argmax(ws))
+    k2 = graphgen.from_edges(10, [(0, 1), (2, 3), (4, 5), (6, 7), (8, 9)])
+    np.testing.assert_array_equal(oracle.greedy_weighted(k2, 1)[0], np.arange(10) ^ 1)
+
+
+def test_greedy_weighted_orientation_free():
+    # the result depends on the undirected edge set only: list order,
+    # duplicates and one-sided entries do not change it
+    g = graphgen.er(300, 5, seed=2)
+    e = [(x, int(y)) for x in range(g.n) for y in g.nbr[g.off[x]:g.off[x + 1]] if x < y]
+    one_sided = graphgen.from_edges(g.n, e, symmetric=False)
+    shuffled = graphgen.from_edges(g.n, list(reversed(e)) + e[:50], symmetric=True, dedup=False,
+                                   sort=False)
+    a = oracle.greedy_weighted(g, 8)[0]
+    np.testing.assert_array_equal(a, oracle.greedy_weighted(one_sided, 8)[0])
+    np.testing.assert_array_equal(a, oracle.greedy_weighted(shuffled, 8)[0])
