@@ -284,6 +284,31 @@ mm_status mm_batch_check(mm_batch_handle h, void* stream, const int32_t* match, 
 mm_status mm_pairs(mm_handle h, void* stream, const int32_t* match, int32_t* pairs, int64_t cap,
                    int64_t* count);
 
+/* ------------------------------------------------------------------ baseline
+ * Iterated Endpoints Mutual Selection (Section II-C): the multi-pass scheme
+ * the paper compares Skipper with, for measuring the work-efficiency contrast
+ * (ids read, passes) on the same GPU. Each iteration, every unmatched vertex
+ * selects its heaviest edge to an unmatched neighbour, and mutually selected
+ * edges become matches, until no unmatched vertex has an unmatched
+ * neighbour. Edge weights: w(u, v) = SplitMix64(SplitMix64(seed) ^ (min << 32
+ * | max)); the result is the greedy matching in descending weight order (ties:
+ * smaller key), the same on every run. Needs a handle created with
+ * MM_SYMMETRIC (on a one-sided list an edge may never be selected by both
+ * ends). Synchronous: waits for `stream` after every iteration. scratch:
+ * device, 256-byte aligned, mm_ems_scratch_bytes(n) bytes. match_out: device,
+ * n int32. stats (host, may be null): iterations run (the last one finds
+ * nothing to select), ids read over all iterations, pairs.
+ */
+typedef struct {
+  int64_t iterations;
+  int64_t touched;
+  int64_t pairs;
+  int64_t reserved_[5];
+} mm_ems_stats;
+size_t mm_ems_scratch_bytes(int64_t n);
+mm_status mm_ems_run(mm_handle h, void* stream, uint64_t seed, void* scratch,
+                     size_t scratch_bytes, int32_t* match_out, mm_ems_stats* stats);
+
 /* Thread-local description of the last non-OK status returned on this thread. */
 const char* mm_last_error(void);
 

@@ -191,6 +191,22 @@ class Graph:
                                         ctypes.c_void_p(out.data_ptr()), cap, ctypes.byref(cnt)))
         return out[:2 * cnt.value].view(-1, 2)
 
+    def ems(self, seed: int = 1, out=None, stream=None):
+        """The iterated mutual-selection baseline (mm_ems_run) on this graph:
+        returns (mate tensor, {"iterations", "touched", "pairs"})."""
+        import torch
+        lib = _lib.load()
+        nb = lib.mm_ems_scratch_bytes(self.n)
+        scratch = torch.empty(nb + 256, dtype=torch.uint8, device=self.device)
+        aligned = (scratch.data_ptr() + 255) // 256 * 256
+        if out is None:
+            out = torch.empty(max(self.n, 1), dtype=torch.int32, device=self.device)[:self.n]
+        st = _lib.mm_ems_stats()
+        _lib.check(lib.mm_ems_run(self.handle, _stream_ptr(stream), ctypes.c_uint64(seed),
+                                  ctypes.c_void_p(aligned), nb, ctypes.c_void_p(out.data_ptr()),
+                                  ctypes.byref(st)))
+        return out, {"iterations": st.iterations, "touched": st.touched, "pairs": st.pairs}
+
     def reset_stats(self, stream=None) -> None:
         _lib.check(_lib.load().mm_reset_stats(self.handle, _stream_ptr(stream)))
 

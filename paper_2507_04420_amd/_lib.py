@@ -58,6 +58,11 @@ class mm_stats(ctypes.Structure):
         ("conflict_hist", ctypes.c_uint64 * 10), ("reserved_", ctypes.c_uint64 * 8)]
 
 
+class mm_ems_stats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int64), ("touched", ctypes.c_int64),
+                ("pairs", ctypes.c_int64), ("reserved_", ctypes.c_int64 * 5)]
+
+
 def stats_dict(s: mm_stats) -> dict:
     d = {f: int(getattr(s, f)) for f, _ in mm_stats._fields_
          if f not in ("conflict_hist", "reserved_")}
@@ -93,6 +98,8 @@ SIGNATURES = {
     "mm_check": (_I32, [_P, _P, _P, ctypes.POINTER(_I64)]),
     "mm_batch_check": (_I32, [_P, _P, _P, ctypes.POINTER(_I64)]),
     "mm_pairs": (_I32, [_P, _P, _P, _P, _I64, ctypes.POINTER(_I64)]),
+    "mm_ems_scratch_bytes": (_SZ, [_I64]),
+    "mm_ems_run": (_I32, [_P, _P, ctypes.c_uint64, _P, _SZ, _P, ctypes.POINTER(mm_ems_stats)]),
     "mm_last_error": (ctypes.c_char_p, []),
     "mm_version": (ctypes.c_char_p, []),
 }

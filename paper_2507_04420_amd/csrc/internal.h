@@ -28,6 +28,7 @@ int handle_off64(const mm_graph* h);
 const void* handle_off(const mm_graph* h);
 const int32_t* handle_nbr(const mm_graph* h);
 uint8_t* handle_ws(const mm_graph* h);
+uint32_t handle_flags(const mm_graph* h);
 
 // Copies the raw device counters (sweep.h order) into the ABI struct.
 void stats_from_counters(const unsigned long long* c, mm_stats* out);

@@ -213,6 +213,7 @@ int handle_off64(const mm_graph* h) { return h->off64; }
 const void* handle_off(const mm_graph* h) { return h->off; }
 const int32_t* handle_nbr(const mm_graph* h) { return h->nbr; }
 uint8_t* handle_ws(const mm_graph* h) { return h->ws; }
+uint32_t handle_flags(const mm_graph* h) { return h->flags; }
 }  // namespace mmi
 
 namespace {

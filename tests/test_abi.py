@@ -125,6 +125,10 @@ def test_null_handle_calls():
     c = (ctypes.c_int64 * 6)()
     assert lib.mm_check(None, None, None, c) == _lib.MM_ERR_INVALID_ARG
     assert lib.mm_batch_check(None, None, None, c) == _lib.MM_ERR_INVALID_ARG
+    assert lib.mm_ems_run(None, None, 1, None, 0, None, None) == _lib.MM_ERR_INVALID_ARG
+    assert lib.mm_ems_scratch_bytes(-1) == 0 and lib.mm_ems_scratch_bytes(1000) >= 4000
+    cnt = ctypes.c_int64()
+    assert lib.mm_pairs(None, None, None, None, 0, ctypes.byref(cnt)) == _lib.MM_ERR_INVALID_ARG
     lib.mm_destroy(None)
 
 
