@@ -102,7 +102,10 @@ typedef struct {
                             "matched" hint (set after a vertex is matched)
                             instead of reading its state */
   int32_t wg_size;       /* threads per workgroup: 64, 128, 192 or 256 */
-  int32_t wave_vertices; /* source vertices handed to one wavefront, >= 64, multiple of 64 */
+  int32_t wave_vertices; /* source vertices handed to one wavefront, >= 64, multiple of 64;
+                            mm_run shortens it for a graph too small to give
+                            2048 wavefronts (not for batches, whose graphs
+                            together fill the GPU) */
   int32_t disperse;      /* 0: a wavefront's lanes take consecutive sources;
                             1: concurrently active lanes of a wavefront take sources
                             wave_vertices/64 apart (for high-locality graphs) */

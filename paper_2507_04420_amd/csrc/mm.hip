@@ -218,6 +218,8 @@ uint32_t handle_flags(const mm_graph* h) { return h->flags; }
 
 namespace {
 
+constexpr int64_t kMinWaves = 2048;
+
 SweepParams make_params(const mm_graph* g) {
   SweepParams p;
   p.wave_vertices = g->tun.wave_vertices;
@@ -229,6 +231,11 @@ SweepParams make_params(const mm_graph* g) {
   p.err = reinterpret_cast<uint32_t*>(g->ws);
   if (g->n <= g->tun.whole_graph_vertices) {  // one wavefront takes the whole graph
     p.wave_vertices = std::max<int64_t>(64, (g->n + 63) / 64 * 64);
+    p.disperse = 0;
+  } else if (g->n < kMinWaves * p.wave_vertices) {
+    // a small graph alone on the GPU: shorter blocks, so that at least
+    // kMinWaves wavefronts (8 per CU) share the sweep and its latency
+    p.wave_vertices = std::max<int64_t>(64, (g->n / kMinWaves + 63) / 64 * 64);
     p.disperse = 0;
   }
   return p;
