@@ -98,9 +98,10 @@ typedef enum {
 typedef struct {
   int32_t layout;        /* mm_layout */
   int32_t protocol;      /* mm_protocol */
-  int32_t hint;          /* 1: skip matched neighbours by a one-bit-per-vertex
-                            "matched" hint (set after a vertex is matched)
-                            instead of reading its state */
+  int32_t hint;          /* skip matched neighbours by a "matched" hint (set after
+                            a vertex is matched) instead of reading its state:
+                            0 none, 1 one bit per vertex (atomic or), 2 one byte
+                            per vertex (plain byte store) */
   int32_t wg_size;       /* threads per workgroup: 64, 128, 192 or 256 */
   int32_t wave_vertices; /* source vertices handed to one wavefront, >= 64, multiple of 64;
                             mm_run shortens it for a graph too small to give
@@ -122,6 +123,14 @@ typedef struct {
                             by one wavefront (one work item of a batch), which makes
                             its result independent of concurrent work: the same
                             alone as inside any batch; 0 disables */
+  int32_t relabel;       /* 1 (single graphs only): mm_create builds, in the
+                            workspace, a copy of the graph with vertices renumbered
+                            by ascending log2-degree bucket (isolated first, given
+                            order kept inside a bucket). The sweep runs on it: low-
+                            degree sources first, hub states packed into few cache
+                            lines. Output stays in the given ids. Workspace from
+                            mm_workspace_bytes_graph; create allocates temporary
+                            device memory for the sort */
   int64_t iter_cap;      /* loop-trip budget per wavefront; 0 = default of
                             65536 + 8 x (neighbour entries of its block);
                             exceeding it raises MM_ERR_NO_PROGRESS */
@@ -155,8 +164,13 @@ typedef struct {
 /* Fills *t with the defaults. */
 void mm_default_tuning(mm_tuning* t);
 
+/* Bytes of device workspace a graph of n vertices and m entries needs under
+   tuning t (any tuning); 0 if the arguments are invalid. */
+size_t mm_workspace_bytes_graph(int64_t n, int64_t m, const mm_tuning* t);
+
 /* Bytes of device workspace a graph of n vertices needs under tuning t
-   (NULL = defaults). Returns 0 if n or t is invalid. */
+   (NULL = defaults). Returns 0 if n or t is invalid, and for t.relabel = 1,
+   whose workspace depends on m (use mm_workspace_bytes_graph). */
 size_t mm_workspace_bytes(int64_t n, const mm_tuning* t);
 
 /*

@@ -43,6 +43,7 @@ class Tuning:
     scan_width: int = 4
     stream_loads: int = 0
     whole_graph_vertices: int = 16384
+    relabel: int = 0
     iter_cap: int = 0
 
     @classmethod
@@ -119,7 +120,7 @@ class Graph:
         self.m = neighbors.numel()
         self.tuning = tuning if tuning is not None else Tuning.default()
         ct = self.tuning.to_c()
-        nbytes = lib.mm_workspace_bytes(self.n, ctypes.byref(ct))
+        nbytes = lib.mm_workspace_bytes_graph(self.n, self.m, ctypes.byref(ct))
         if nbytes == 0:
             raise MMError(_lib.MM_ERR_INVALID_ARG, "invalid n or tuning")
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=offsets.device)

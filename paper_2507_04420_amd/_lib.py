@@ -46,6 +46,7 @@ class mm_tuning(ctypes.Structure):
         ("scan_width", ctypes.c_int32),
         ("stream_loads", ctypes.c_int32),
         ("whole_graph_vertices", ctypes.c_int32),
+        ("relabel", ctypes.c_int32),
         ("iter_cap", ctypes.c_int64),
     ]
 
@@ -76,6 +77,7 @@ _P, _I32, _I64, _U32, _SZ = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ct
 SIGNATURES = {
     "mm_default_tuning": (None, [ctypes.POINTER(mm_tuning)]),
     "mm_workspace_bytes": (_SZ, [_I64, ctypes.POINTER(mm_tuning)]),
+    "mm_workspace_bytes_graph": (_SZ, [_I64, _I64, ctypes.POINTER(mm_tuning)]),
     "mm_create": (_I32, [_P, _I32, _P, _I64, _I64, _P, _SZ, _U32, ctypes.POINTER(mm_tuning), _P,
                          ctypes.POINTER(_P)]),
     "mm_run": (_I32, [_P, _P, _P]),

@@ -1,10 +1,10 @@
 """Autotuner for the sweep's launch and layout parameters.
 
 The matching itself has no parameters; what is tuned is how the sweep maps to
-the device: the status layout and reservation protocol, the matched-hint
-bitmap, vertices per wavefront item, workgroup size, the list length after
-which a wavefront scans one source together, the per-lane scan width and lazy
-output. A coordinate search starts from the library defaults and, dimension
+the device: the status layout and reservation protocol, degree relabelling
+(single graphs), the matched hint (none, bits, bytes), vertices per wavefront
+item, workgroup size, the list length after which a wavefront scans one
+source together, the per-lane scan width and lazy output. A coordinate search starts from the library defaults and, dimension
 by dimension, keeps the fastest value; every candidate's output must pass the
 device check (zero violations) or the candidate is discarded.
 
@@ -33,7 +33,8 @@ SPACE = {
                         (_lib.MM_LAYOUT_U8, _lib.MM_PROTOCOL_CAS),
                         (_lib.MM_LAYOUT_U2, _lib.MM_PROTOCOL_TWO_PHASE),
                         (_lib.MM_LAYOUT_U32, _lib.MM_PROTOCOL_TWO_PHASE)],
-    "hint": [0, 1],
+    "relabel": [0, 1],
+    "hint": [0, 1, 2],
     "disperse": [0, 1],
     "wave_vertices": [256, 512, 1024, 2048, 4096],
     "wg_size": [64, 128, 256],
@@ -67,6 +68,7 @@ class SingleTarget:
     """One resident graph; objective = GEdges/s of a whole pass."""
 
     unit = "GEdges/s"
+    dims = list(SPACE)
 
     def __init__(self, csr, reps: int = 5):
         import torch
@@ -104,6 +106,7 @@ class BatchTarget:
     """A many-graph batch; objective = graphs/s of a captured pass."""
 
     unit = "graphs/s"
+    dims = [d for d in SPACE if d != "relabel"]  # relabelling is for single graphs
 
     def __init__(self, mix, reps: int = 5):
         import torch
@@ -158,7 +161,7 @@ def search(target, start: Tuning | None = None, passes: int = 2, dims=None, log=
     if default_obj is None:
         raise RuntimeError("the starting tuning fails the check")
     best_obj = default_obj
-    dims = dims or list(SPACE)
+    dims = dims or getattr(target, "dims", list(SPACE))
     for p in range(passes):
         changed = False
         for dim in dims:

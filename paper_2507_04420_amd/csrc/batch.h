@@ -21,6 +21,8 @@ struct GraphDesc {
   int64_t v0;      // first global vertex
   uint32_t* st;    // packed states, or null for the word layout
   uint32_t* hint;  // matched hint words, or null
+  uint32_t hint_lg;  // log2 of vertices per hint word
+  uint32_t pad_;
 };
 
 // One wavefront block: sources vb .. vb+nv-1 of graph `desc`.

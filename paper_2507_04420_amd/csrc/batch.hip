@@ -113,27 +113,27 @@ template <class Layout>
 __device__ __forceinline__ Layout layout_of(const GraphDesc& d, int32_t* mate);
 template <>
 __device__ __forceinline__ LayoutU32<false> layout_of(const GraphDesc& d, int32_t* mate) {
-  return LayoutU32<false>{mate + d.v0, Hint{d.hint}};
+  return LayoutU32<false>{mate + d.v0, Hint{d.hint, d.hint_lg}};
 }
 template <>
 __device__ __forceinline__ LayoutU32<true> layout_of(const GraphDesc& d, int32_t* mate) {
-  return LayoutU32<true>{mate + d.v0, Hint{d.hint}};
+  return LayoutU32<true>{mate + d.v0, Hint{d.hint, d.hint_lg}};
 }
 template <>
 __device__ __forceinline__ LayoutPacked<8, false> layout_of(const GraphDesc& d, int32_t* mate) {
-  return LayoutPacked<8, false>{d.st, mate + d.v0, Hint{d.hint}};
+  return LayoutPacked<8, false>{d.st, mate + d.v0, Hint{d.hint, d.hint_lg}};
 }
 template <>
 __device__ __forceinline__ LayoutPacked<8, true> layout_of(const GraphDesc& d, int32_t* mate) {
-  return LayoutPacked<8, true>{d.st, mate + d.v0, Hint{d.hint}};
+  return LayoutPacked<8, true>{d.st, mate + d.v0, Hint{d.hint, d.hint_lg}};
 }
 template <>
 __device__ __forceinline__ LayoutPacked<2, false> layout_of(const GraphDesc& d, int32_t* mate) {
-  return LayoutPacked<2, false>{d.st, mate + d.v0, Hint{d.hint}};
+  return LayoutPacked<2, false>{d.st, mate + d.v0, Hint{d.hint, d.hint_lg}};
 }
 template <>
 __device__ __forceinline__ LayoutPacked<2, true> layout_of(const GraphDesc& d, int32_t* mate) {
-  return LayoutPacked<2, true>{d.st, mate + d.v0, Hint{d.hint}};
+  return LayoutPacked<2, true>{d.st, mate + d.v0, Hint{d.hint, d.hint_lg}};
 }
 
 // Persistent sweep: every wavefront pops items until the table is exhausted;
@@ -286,7 +286,7 @@ bool plan_layout(int32_t G, const int64_t* vtx_off, const mm_tuning& t, BatchLay
     if (n < 0 || n > INT32_MAX) return false;
     n_items += n <= t.whole_graph_vertices ? (n > 0) : (n + t.wave_vertices - 1) / t.wave_vertices;
     st_words += mmb::state_words_for(n, t.layout);
-    if (t.hint) hint_words += (n + 31) / 32;
+    hint_words += mmk::hint_words(n, t.hint);
   }
   BatchLayout L;
   L.n_items = n_items;
@@ -346,7 +346,10 @@ mm_status common_args(void* workspace, uint32_t flags, const mm_tuning* tuning, 
   if (flags & ~(uint32_t)(MM_VALIDATE | MM_SYMMETRIC | MM_STATS | MM_TIMING | MM_CAPTURE))
     return fail(MM_ERR_INVALID_ARG, "unknown flag bits 0x%x", flags);
   if (tuning) *t = *tuning; else mm_default_tuning(t);
-  return mmi::check_tuning(*t);
+  const mm_status st = mmi::check_tuning(*t);
+  if (st != MM_OK) return st;
+  if (t->relabel) return fail(MM_ERR_UNSUPPORTED, "tuning.relabel applies to single graphs only");
+  return MM_OK;
 }
 
 // Completes a handle whose descriptors carry off, nbr, n, m and v0: places the
@@ -370,8 +373,9 @@ mm_status finish_create(std::vector<mmb::GraphDesc>& descs, const std::vector<in
     mmb::GraphDesc& d = descs[g];
     d.st = t.layout == MM_LAYOUT_U32 ? nullptr : st_base + st_w;
     d.hint = t.hint ? hint_base + hint_w : nullptr;
+    d.hint_lg = mmk::hint_lg(t.hint);
     st_w += mmb::state_words_for(d.n, t.layout);
-    if (t.hint) hint_w += (d.n + 31) / 32;
+    hint_w += mmk::hint_words(d.n, t.hint);
     // a small graph is one item (one wavefront), a larger one an item per block
     const int64_t step = d.n <= t.whole_graph_vertices ? d.n : t.wave_vertices;
     for (int64_t vb = 0; vb < d.n; vb += step) {
@@ -471,7 +475,7 @@ size_t mm_batch_workspace_bytes(int32_t num_graphs, const int64_t* vtx_off, cons
   if (num_graphs < 0 || !vtx_off) return 0;
   mm_tuning t;
   if (tp) t = *tp; else mm_default_tuning(&t);
-  if (mmi::check_tuning(t) != MM_OK) return 0;
+  if (mmi::check_tuning(t) != MM_OK || t.relabel) return 0;
   BatchLayout L;
   if (!plan_layout(num_graphs, vtx_off, t, &L)) return 0;
   return L.total;

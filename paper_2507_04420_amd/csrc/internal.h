@@ -30,6 +30,18 @@ const int32_t* handle_nbr(const mm_graph* h);
 uint8_t* handle_ws(const mm_graph* h);
 uint32_t handle_flags(const mm_graph* h);
 
+// A graph relabelled by degree (see relabel.hip), in a workspace region of
+// relabel_bytes(n, m) bytes: int64 offsets, new -> given id map, neighbours.
+struct RelabelView {
+  int64_t* off;
+  int32_t* orig;
+  int32_t* nbr;
+  int64_t n_isolated;  // new ids 0 .. n_isolated-1 have no entries
+};
+size_t relabel_bytes(int64_t n, int64_t m);
+hipError_t build_relabel(const void* off, int off64, const int32_t* nbr, int64_t n, int64_t m,
+                         uint8_t* region, RelabelView* view, hipStream_t s);
+
 // Copies the raw device counters (sweep.h order) into the ABI struct.
 void stats_from_counters(const unsigned long long* c, mm_stats* out);
 

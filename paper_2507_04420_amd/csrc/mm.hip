@@ -44,7 +44,7 @@ mm_status check_tuning(const mm_tuning& t) {
     return fail(MM_ERR_INVALID_ARG, "tuning.layout must be MM_LAYOUT_U8, MM_LAYOUT_U32 or MM_LAYOUT_U2");
   if (t.protocol != MM_PROTOCOL_CAS && t.protocol != MM_PROTOCOL_TWO_PHASE)
     return fail(MM_ERR_INVALID_ARG, "tuning.protocol must be MM_PROTOCOL_CAS or MM_PROTOCOL_TWO_PHASE");
-  if (t.hint != 0 && t.hint != 1) return fail(MM_ERR_INVALID_ARG, "tuning.hint must be 0 or 1");
+  if (t.hint < 0 || t.hint > 2) return fail(MM_ERR_INVALID_ARG, "tuning.hint must be 0, 1 or 2");
   if (t.wg_size < 64 || t.wg_size > 256 || t.wg_size % 64)
     return fail(MM_ERR_INVALID_ARG, "tuning.wg_size must be 64, 128, 192 or 256 (got %d)",
                 t.wg_size);
@@ -60,6 +60,8 @@ mm_status check_tuning(const mm_tuning& t) {
     return fail(MM_ERR_INVALID_ARG, "tuning.stream_loads must be 0 or 1");
   if (t.whole_graph_vertices < 0)
     return fail(MM_ERR_INVALID_ARG, "tuning.whole_graph_vertices must be >= 0");
+  if (t.relabel != 0 && t.relabel != 1)
+    return fail(MM_ERR_INVALID_ARG, "tuning.relabel must be 0 or 1");
   if (t.iter_cap < 0) return fail(MM_ERR_INVALID_ARG, "tuning.iter_cap must be >= 0");
   return MM_OK;
 }
@@ -71,7 +73,7 @@ size_t state_bytes(int64_t n, const mm_tuning& t) {
 }
 
 size_t hint_bytes(int64_t n, const mm_tuning& t) {
-  return t.hint ? round_up((size_t)((n + 31) / 32) * 4, 256) : 0;
+  return round_up((size_t)hint_words(n, t.hint) * 4, 256);
 }
 
 void stats_from_counters(const unsigned long long* c, mm_stats* out) {
@@ -141,13 +143,14 @@ __global__ void validate_kernel(const OffT* __restrict__ off, const int32_t* __r
   if (f) atomicOr(flags, f);
 }
 
-// One graph: wavefront w sweeps sources [w * wave_vertices, ...).
+// One graph: wavefront w sweeps sources [v_begin + w * wave_vertices, ...).
 template <typename OffT, class Layout, bool HINT, bool LAZY, bool STATS>
 __global__ __launch_bounds__(256) void sweep_kernel(SweepParams p, const OffT* __restrict__ off,
                                                    const int32_t* __restrict__ nbr, int64_t n,
-                                                   Layout L, unsigned long long* stats) {
+                                                   int64_t v_begin, Layout L,
+                                                   unsigned long long* stats) {
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const int64_t vb = wave * p.wave_vertices;
+  const int64_t vb = v_begin + wave * p.wave_vertices;
   if (vb >= n) return;
   const int64_t nv = (n - vb < p.wave_vertices) ? (n - vb) : p.wave_vertices;
   __shared__ QSlot queues[4][kQueue];  // one ring per wavefront (wg_size <= 256)
@@ -200,6 +203,9 @@ struct mm_graph {
   bool lazy;  // effective lazy output
   int device;
   TimingRing* timing;
+  bool relabel;         // sweep the graph relabelled by degree (relabel.hip)
+  mmi::RelabelView rl;  // its arrays, in the workspace
+  int32_t* rl_state;    // word-layout states in the new ids (relabel only)
   uint32_t* st() const { return reinterpret_cast<uint32_t*>(ws + kCtrlBytes); }
   uint32_t* hint() const {
     return tun.hint ? reinterpret_cast<uint32_t*>(ws + kCtrlBytes + mmi::state_bytes(n, tun))
@@ -220,6 +226,9 @@ namespace {
 
 constexpr int64_t kMinWaves = 2048;
 
+// Sources the sweep visits: all vertices, or, relabelled, those with entries.
+int64_t sweep_begin(const mm_graph* g) { return g->relabel ? g->rl.n_isolated : 0; }
+
 SweepParams make_params(const mm_graph* g) {
   SweepParams p;
   p.wave_vertices = g->tun.wave_vertices;
@@ -229,13 +238,14 @@ SweepParams make_params(const mm_graph* g) {
   p.stream_loads = g->tun.stream_loads;
   p.iter_cap = g->tun.iter_cap;
   p.err = reinterpret_cast<uint32_t*>(g->ws);
-  if (g->n <= g->tun.whole_graph_vertices) {  // one wavefront takes the whole graph
-    p.wave_vertices = std::max<int64_t>(64, (g->n + 63) / 64 * 64);
+  const int64_t ns = g->n - sweep_begin(g);
+  if (ns <= g->tun.whole_graph_vertices) {  // one wavefront takes the whole graph
+    p.wave_vertices = std::max<int64_t>(64, (ns + 63) / 64 * 64);
     p.disperse = 0;
-  } else if (g->n < kMinWaves * p.wave_vertices) {
+  } else if (ns < kMinWaves * p.wave_vertices) {
     // a small graph alone on the GPU: shorter blocks, so that at least
     // kMinWaves wavefronts (8 per CU) share the sweep and its latency
-    p.wave_vertices = std::max<int64_t>(64, (g->n / kMinWaves + 63) / 64 * 64);
+    p.wave_vertices = std::max<int64_t>(64, (ns / kMinWaves + 63) / 64 * 64);
     p.disperse = 0;
   }
   return p;
@@ -245,7 +255,11 @@ template <typename OffT, class Layout, bool HINT, bool LAZY, bool STATS>
 hipError_t launch_sweep(const mm_graph* g, const Layout& L, hipStream_t s) {
   const SweepParams p = make_params(g);
   unsigned long long* stats = reinterpret_cast<unsigned long long*>(g->ws + kStatsOffset);
-  const int64_t waves = (g->n + p.wave_vertices - 1) / p.wave_vertices;
+  const int64_t v_begin = sweep_begin(g);
+  const OffT* off = g->relabel ? reinterpret_cast<const OffT*>(g->rl.off)
+                               : static_cast<const OffT*>(g->off);
+  const int32_t* nbr = g->relabel ? g->rl.nbr : g->nbr;
+  const int64_t waves = (g->n - v_begin + p.wave_vertices - 1) / p.wave_vertices;
   const int wpb = g->tun.wg_size / 64;
   const int64_t blocks = (waves + wpb - 1) / wpb;
   if (blocks == 0) return hipSuccess;
@@ -254,8 +268,7 @@ hipError_t launch_sweep(const mm_graph* g, const Layout& L, hipStream_t s) {
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL((sweep_kernel<OffT, Layout, HINT, LAZY, STATS>), dim3((unsigned)blocks),
-                     dim3(g->tun.wg_size), 0, s, p, static_cast<const OffT*>(g->off), g->nbr, g->n,
-                     L, stats);
+                     dim3(g->tun.wg_size), 0, s, p, off, nbr, g->n, v_begin, L, stats);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (g->timing) {
@@ -286,12 +299,50 @@ void fill(uint32_t* p, int64_t words, uint32_t value, hipStream_t s) {
     hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(words)), dim3(256), 0, s, p, words, value);
 }
 
+// Relabelled graph: states in the new ids, output written in the given ids
+// (filled with -1 first). The relabelled offsets are int64.
+template <bool STATS>
+hipError_t run_relabelled(const mm_graph* g, int32_t* out, hipStream_t s) {
+  const int64_t n = g->n;
+  Hint hint{g->hint(), hint_lg(g->tun.hint)};
+  if (hint.bits) fill(hint.bits, hint_words(n, g->tun.hint), 0u, s);
+  fill(reinterpret_cast<uint32_t*>(out), n, 0xffffffffu, s);
+  const bool two = g->tun.protocol == MM_PROTOCOL_TWO_PHASE;
+  const int32_t* orig = g->rl.orig;
+  if (g->tun.layout == MM_LAYOUT_U32) {
+    uint32_t* st = reinterpret_cast<uint32_t*>(g->rl_state);
+    if (two) {
+      using L = Relabelled<LayoutU32<true>>;
+      fill(st, n, LayoutU32<true>::kAcc, s);
+      return dispatch_flags<int64_t, L, STATS>(g, L{{g->rl_state, hint}, out, orig}, s);
+    }
+    using L = Relabelled<LayoutU32<false>>;
+    fill(st, n, LayoutU32<false>::kAcc, s);
+    return dispatch_flags<int64_t, L, STATS>(g, L{{g->rl_state, hint}, out, orig}, s);
+  }
+  // packed layouts keep their mate entries in the new ids too (in the region
+  // the word layout uses for its states); the wrapper writes the output
+  int32_t* mate_new = g->rl_state;
+  if (g->tun.layout == MM_LAYOUT_U2) {
+    fill(g->st(), (n + 15) / 16, 0u, s);
+    using LT = Relabelled<LayoutPacked<2, true>>;
+    using LC = Relabelled<LayoutPacked<2, false>>;
+    if (two) return dispatch_flags<int64_t, LT, STATS>(g, LT{{g->st(), mate_new, hint}, out, orig}, s);
+    return dispatch_flags<int64_t, LC, STATS>(g, LC{{g->st(), mate_new, hint}, out, orig}, s);
+  }
+  fill(g->st(), (n + 3) / 4, 0u, s);
+  using LT = Relabelled<LayoutPacked<8, true>>;
+  using LC = Relabelled<LayoutPacked<8, false>>;
+  if (two) return dispatch_flags<int64_t, LT, STATS>(g, LT{{g->st(), mate_new, hint}, out, orig}, s);
+  return dispatch_flags<int64_t, LC, STATS>(g, LC{{g->st(), mate_new, hint}, out, orig}, s);
+}
+
 template <typename OffT, bool STATS>
 hipError_t run_typed(const mm_graph* g, int32_t* mate, hipStream_t s) {
   const int64_t n = g->n;
   uint32_t* mate_w = reinterpret_cast<uint32_t*>(mate);
-  Hint hint{g->hint()};
-  if (hint.bits) fill(hint.bits, (n + 31) / 32, 0u, s);
+  Hint hint{g->hint(), hint_lg(g->tun.hint)};
+  if (hint.bits) fill(hint.bits, hint_words(n, g->tun.hint), 0u, s);
   const bool two = g->tun.protocol == MM_PROTOCOL_TWO_PHASE;
   hipError_t e;
   if (g->tun.layout == MM_LAYOUT_U32) {
@@ -350,11 +401,20 @@ void mm_default_tuning(mm_tuning* t) {
   t->iter_cap = 0;
 }
 
+size_t mm_workspace_bytes_graph(int64_t n, int64_t m, const mm_tuning* tp) {
+  mm_tuning t;
+  if (tp) t = *tp; else mm_default_tuning(&t);
+  if (n < 0 || n > INT32_MAX || m < 0 || check_tuning(t) != MM_OK) return 0;
+  size_t b = kCtrlBytes + mmi::state_bytes(n, t) + mmi::hint_bytes(n, t);
+  if (t.relabel) b += mmi::round_up(sizeof(int32_t) * (size_t)n, 256) + mmi::relabel_bytes(n, m);
+  return b;
+}
+
 size_t mm_workspace_bytes(int64_t n, const mm_tuning* tp) {
   mm_tuning t;
   if (tp) t = *tp; else mm_default_tuning(&t);
-  if (n < 0 || n > INT32_MAX || check_tuning(t) != MM_OK) return 0;
-  return kCtrlBytes + mmi::state_bytes(n, t) + mmi::hint_bytes(n, t);
+  if (t.relabel) return 0;  // the relabelled copy depends on m
+  return mm_workspace_bytes_graph(n, 0, &t);
 }
 
 mm_status mm_create(const void* offsets, mm_offset_type off_type, const int32_t* neighbors,
@@ -380,7 +440,7 @@ mm_status mm_create(const void* offsets, mm_offset_type off_type, const int32_t*
   if (tuning) t = *tuning; else mm_default_tuning(&t);
   mm_status st = check_tuning(t);
   if (st != MM_OK) return st;
-  const size_t need = kCtrlBytes + mmi::state_bytes(n, t) + mmi::hint_bytes(n, t);
+  const size_t need = mm_workspace_bytes_graph(n, m, &t);
   if (workspace_bytes < need)
     return fail(MM_ERR_OUT_OF_MEMORY, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
 
@@ -413,8 +473,20 @@ mm_status mm_create(const void* offsets, mm_offset_type off_type, const int32_t*
                   (hf & 4u) ? " neighbour id out of [0, n);" : "");
     }
   }
+  mmi::RelabelView rl{};
+  int32_t* rl_state = nullptr;
+  if (t.relabel) {
+    const size_t base = kCtrlBytes + mmi::state_bytes(n, t) + mmi::hint_bytes(n, t);
+    rl_state = reinterpret_cast<int32_t*>(ws + base);
+    uint8_t* region = ws + base + mmi::round_up(sizeof(int32_t) * (size_t)n, 256);
+    hipError_t e = mmi::build_relabel(offsets, off_type == MM_OFF_I64, neighbors, n, m, region, &rl, s);
+    if (e != hipSuccess) return fail(MM_ERR_HIP, "relabelling failed: %s", hipGetErrorString(e));
+  }
   mm_graph* g = new (std::nothrow) mm_graph();
   if (!g) return fail(MM_ERR_OUT_OF_MEMORY, "host allocation of the handle failed");
+  g->relabel = t.relabel != 0;
+  g->rl = rl;
+  g->rl_state = rl_state;
   g->off = offsets;
   g->off64 = off_type == MM_OFF_I64;
   g->nbr = neighbors;
@@ -425,7 +497,7 @@ mm_status mm_create(const void* offsets, mm_offset_type off_type, const int32_t*
   g->flags = flags;
   g->tun = t;
   // Lazy output is only sound when every edge is in both endpoints' lists.
-  g->lazy = t.lazy_init && (flags & MM_SYMMETRIC) &&
+  g->lazy = t.lazy_init && (flags & MM_SYMMETRIC) && !t.relabel &&
             !(t.layout == MM_LAYOUT_U32 && t.protocol == MM_PROTOCOL_CAS);
   g->device = dev;
   g->timing = nullptr;
@@ -454,7 +526,9 @@ mm_status mm_run(mm_handle g, void* stream, int32_t* match_out) {
   hipStream_t s = static_cast<hipStream_t>(stream);
   const bool stats = (g->flags & MM_STATS) != 0;
   hipError_t e;
-  if (g->off64)
+  if (g->relabel)
+    e = stats ? run_relabelled<true>(g, match_out, s) : run_relabelled<false>(g, match_out, s);
+  else if (g->off64)
     e = stats ? run_typed<int64_t, true>(g, match_out, s) : run_typed<int64_t, false>(g, match_out, s);
   else
     e = stats ? run_typed<int32_t, true>(g, match_out, s) : run_typed<int32_t, false>(g, match_out, s);

@@ -49,15 +49,31 @@ __device__ __forceinline__ void or_agent(uint32_t* p, uint32_t bits) {
   __hip_atomic_fetch_or(p, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Matched-vertex hint: one bit per vertex, set after a vertex becomes MCHD.
-// Read with cached loads to skip matched neighbours; a clear bit proves
-// nothing (the state word decides).
+// Matched-vertex hint, set after a vertex becomes MCHD: one bit per vertex
+// (lg = 5: 32 vertices per word, set with an atomic or) or one byte per
+// vertex (lg = 2: set with a plain byte store, no atomic). Read with cached
+// loads to skip matched neighbours; a clear entry proves nothing (the state
+// word decides), so a late or lost update is harmless.
 struct Hint {
   uint32_t* bits;  // null: no hint, the state word itself is read
+  uint32_t lg;     // log2 of vertices per 32-bit word: 5 (bits) or 2 (bytes)
+  __device__ __forceinline__ const uint32_t* word(int64_t v) const { return bits + (v >> lg); }
+  __device__ __forceinline__ uint32_t shift(int64_t v) const {
+    return (uint32_t)(v & ((1 << lg) - 1)) << (5 - lg);
+  }
   __device__ __forceinline__ void set(int64_t v) const {
-    or_agent(bits + (v >> 5), 1u << (uint32_t)(v & 31));
+    if (lg == 2)
+      reinterpret_cast<uint8_t*>(bits)[v] = 1;
+    else
+      or_agent(bits + (v >> 5), 1u << (uint32_t)(v & 31));
   }
 };
+
+// 32-bit words of a hint of mode `mode` (1: bits, 2: bytes) for n vertices.
+__host__ __device__ __forceinline__ int64_t hint_words(int64_t n, int mode) {
+  return mode == 2 ? (n + 3) / 4 : mode == 1 ? (n + 31) / 32 : 0;
+}
+__host__ __device__ __forceinline__ uint32_t hint_lg(int mode) { return mode == 2 ? 2u : 5u; }
 
 // Packed layouts: BITS = 8 (one state byte per vertex, four per 32-bit word)
 // or BITS = 2 (sixteen vertices per word). Field encoding ACC = 0, RSVD = 1,
@@ -202,6 +218,23 @@ struct LayoutU32 {
   __device__ __forceinline__ void write_unmatched(int64_t x) const {
     if (TWO_PHASE)
       __hip_atomic_store(mate + x, (int32_t)-1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+};
+
+// A layout over relabelled vertex ids whose output is in the caller's ids:
+// the base layout keeps the states (and, for the word layout, the mates) in
+// the new ids; each committed pair is also written to `out` through the map
+// from new to given ids. `out` is filled with -1 before the sweep, so the
+// lazy output paths are not used with it.
+template <class Base>
+struct Relabelled : Base {
+  int32_t* out;
+  const int32_t* orig;
+  __device__ __forceinline__ void commit(int64_t u, int64_t v) const {
+    Base::commit(u, v);
+    const int32_t ou = orig[u], ov = orig[v];
+    out[ou] = ov;
+    out[ov] = ou;
   }
 };
 

@@ -1,0 +1,177 @@
+// Create-time relabelling of a graph by degree (tuning.relabel).
+//
+// New ids list the vertices by ascending log2-degree bucket (isolated
+// vertices first), keeping the given order inside a bucket. Two effects:
+//   * the sweep visits low-degree sources first, which shortens the scans
+//     (a low-degree source reaches a free neighbour early, and hubs are
+//     usually matched as neighbours before their own turn comes);
+//   * the high-degree vertices, whose states most scans read, get the
+//     highest ids, so their status words and hint bits share few cache lines
+//     and stay in L2.
+// The relabelled CSR (int64 offsets, neighbour lists in the given order with
+// ids mapped) and the map from new to given ids live in the workspace; the
+// sweep writes its output in the given ids. Temporary buffers of the sort are
+// allocated and freed here (create time only).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
+#include <rocprim/iterator/counting_iterator.hpp>
+
+#include "internal.h"
+
+namespace {
+
+__device__ __forceinline__ uint32_t bucket_of(int64_t d) {
+  return d <= 0 ? 0u : 64u - (uint32_t)__clzll((unsigned long long)d);  // 1 + floor(log2 d)
+}
+
+template <typename OffT>
+__global__ void degree_keys_kernel(const OffT* __restrict__ off, int64_t n, uint32_t* __restrict__ keys) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride)
+    keys[v] = bucket_of((int64_t)off[v + 1] - (int64_t)off[v]);
+}
+
+// inv[orig[v]] = v; rdeg[v] = degree of new vertex v; rdeg[n] = 0.
+template <typename OffT>
+__global__ void invert_kernel(const OffT* __restrict__ off, const int32_t* __restrict__ orig,
+                              int64_t n, int32_t* __restrict__ inv, int64_t* __restrict__ rdeg) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v <= n; v += stride) {
+    if (v == n) {
+      rdeg[n] = 0;
+      continue;
+    }
+    const int64_t x = orig[v];
+    inv[x] = (int32_t)v;
+    rdeg[v] = (int64_t)off[x + 1] - (int64_t)off[x];
+  }
+}
+
+// Number of isolated vertices: the sorted keys start with them.
+__global__ void count_isolated_kernel(const uint32_t* __restrict__ keys, int64_t n,
+                                      unsigned long long* out) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride)
+    if (keys[v] == 0 && (v + 1 == n || keys[v + 1] != 0)) *out = (unsigned long long)(v + 1);
+}
+
+// Copies the lists: one wavefront per 64 new vertices, taking them one after
+// the other with its lanes spread over the list.
+template <typename OffT>
+__global__ void copy_lists_kernel(const OffT* __restrict__ off, const int32_t* __restrict__ nbr,
+                                  const int32_t* __restrict__ orig, const int32_t* __restrict__ inv,
+                                  const int64_t* __restrict__ roff, int32_t* __restrict__ rnbr,
+                                  int64_t n) {
+  const int lane = (int)(threadIdx.x & 63);
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t base = wave * 64; base < n; base += waves * 64) {
+    const int64_t cnt = n - base < 64 ? n - base : 64;
+    for (int64_t k = 0; k < cnt; ++k) {
+      const int64_t v = base + k;
+      const int64_t x = orig[v];
+      const int64_t b = (int64_t)off[x], e = (int64_t)off[x + 1];
+      const int64_t d = roff[v] - b;
+      for (int64_t j = b + lane; j < e; j += 64) rnbr[d + j] = inv[nbr[j]];
+    }
+  }
+}
+
+int blocks_for(int64_t n) {
+  int64_t b = (n + 255) / 256;
+  if (b < 1) b = 1;
+  if (b > 16384) b = 16384;
+  return (int)b;
+}
+
+template <typename OffT>
+hipError_t build_typed(const OffT* off, const int32_t* nbr, int64_t n, int64_t* roff,
+                       int32_t* rnbr, int32_t* orig, int64_t* n_isolated, hipStream_t s) {
+  uint32_t *keys = nullptr, *keys_sorted = nullptr;
+  int32_t* inv = nullptr;
+  int64_t* rdeg = nullptr;
+  void* tmp = nullptr;
+  unsigned long long* iso = nullptr;
+  size_t tmp_bytes = 0, sort_bytes = 0, scan_bytes = 0;
+  hipError_t e = hipSuccess;
+  auto ids = rocprim::counting_iterator<int32_t>(0);
+  e = rocprim::radix_sort_pairs(nullptr, sort_bytes, keys, keys_sorted, ids, orig, (size_t)n, 0, 7, s);
+  if (e == hipSuccess)
+    e = rocprim::exclusive_scan(nullptr, scan_bytes, rdeg, roff, (int64_t)0, (size_t)(n + 1),
+                                rocprim::plus<int64_t>(), s);
+  tmp_bytes = sort_bytes > scan_bytes ? sort_bytes : scan_bytes;
+  if (e == hipSuccess) e = hipMalloc(&keys, sizeof(uint32_t) * (size_t)n);
+  if (e == hipSuccess) e = hipMalloc(&keys_sorted, sizeof(uint32_t) * (size_t)n);
+  if (e == hipSuccess) e = hipMalloc(&inv, sizeof(int32_t) * (size_t)n);
+  if (e == hipSuccess) e = hipMalloc(&rdeg, sizeof(int64_t) * (size_t)(n + 1));
+  if (e == hipSuccess) e = hipMalloc(&tmp, tmp_bytes > 0 ? tmp_bytes : 1);
+  if (e == hipSuccess) e = hipMalloc(&iso, sizeof(unsigned long long));
+  if (e == hipSuccess) e = hipMemsetAsync(iso, 0, sizeof(unsigned long long), s);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL((degree_keys_kernel<OffT>), dim3(blocks_for(n)), dim3(256), 0, s, off, n, keys);
+    e = hipGetLastError();
+  }
+  // 7 key bits cover every bucket 0 .. 64; the sort is stable
+  if (e == hipSuccess)
+    e = rocprim::radix_sort_pairs(tmp, sort_bytes, keys, keys_sorted, ids, orig, (size_t)n, 0, 7, s);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL((invert_kernel<OffT>), dim3(blocks_for(n + 1)), dim3(256), 0, s, off, orig, n,
+                       inv, rdeg);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess)
+    e = rocprim::exclusive_scan(tmp, scan_bytes, rdeg, roff, (int64_t)0, (size_t)(n + 1),
+                                rocprim::plus<int64_t>(), s);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(count_isolated_kernel, dim3(blocks_for(n)), dim3(256), 0, s, keys_sorted, n, iso);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL((copy_lists_kernel<OffT>), dim3(blocks_for(n)), dim3(256), 0, s,
+                       off, nbr, orig, inv, roff, rnbr, n);
+    e = hipGetLastError();
+  }
+  unsigned long long h_iso = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&h_iso, iso, sizeof(h_iso), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  *n_isolated = (int64_t)h_iso;
+  hipFree(keys);
+  hipFree(keys_sorted);
+  hipFree(inv);
+  hipFree(rdeg);
+  hipFree(tmp);
+  hipFree(iso);
+  return e;
+}
+
+}  // namespace
+
+namespace mmi {
+
+size_t relabel_bytes(int64_t n, int64_t m) {
+  return round_up(sizeof(int64_t) * (size_t)(n + 1), 256) + round_up(sizeof(int32_t) * (size_t)n, 256) +
+         round_up(sizeof(int32_t) * (size_t)m, 256);
+}
+
+hipError_t build_relabel(const void* off, int off64, const int32_t* nbr, int64_t n, int64_t m,
+                         uint8_t* region, RelabelView* view, hipStream_t s) {
+  view->off = reinterpret_cast<int64_t*>(region);
+  view->orig = reinterpret_cast<int32_t*>(region + round_up(sizeof(int64_t) * (size_t)(n + 1), 256));
+  view->nbr = reinterpret_cast<int32_t*>(reinterpret_cast<uint8_t*>(view->orig) +
+                                         round_up(sizeof(int32_t) * (size_t)n, 256));
+  view->n_isolated = 0;
+  (void)m;
+  if (n == 0) return hipSuccess;
+  if (off64)
+    return build_typed(static_cast<const int64_t*>(off), nbr, n, view->off, view->nbr, view->orig,
+                       &view->n_isolated, s);
+  return build_typed(static_cast<const int32_t*>(off), nbr, n, view->off, view->nbr, view->orig,
+                     &view->n_isolated, s);
+}
+
+}  // namespace mmi

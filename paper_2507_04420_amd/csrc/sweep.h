@@ -151,7 +151,7 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
 // Sweeps the sources vb .. vb+nv-1 of one graph with one wavefront.
 // off: the graph's offsets (entries index `nbr`); L: its state layout (with
 // its mate array and hint, all based at the graph's first vertex).
-// HINT: skip matched neighbours by the one-bit-per-vertex hint instead of the
+// HINT: skip matched neighbours by the matched hint (a bit or byte per vertex) instead of the
 // state word.
 // q: this wavefront's LDS ring of kQueue slots.
 template <typename OffT, class Layout, bool HINT, bool LAZY, bool STATS>
@@ -172,11 +172,11 @@ __device__ __forceinline__ void sweep_block(const SweepParams& a, const OffT* __
 
   // Filter reads: the hint bit, or the vertex's own state word.
   auto filter_word = [&](int64_t y) -> uint32_t {
-    if (HINT) return ld_cached(L.hint.bits + (y >> 5));
+    if (HINT) return ld_cached(L.hint.word(y));
     return L.word_cached(y);
   };
   auto filter_matched = [&](uint32_t word, int64_t y) -> bool {
-    if (HINT) return ((word >> (uint32_t)(y & 31)) & 1u) != 0;
+    if (HINT) return ((word >> L.hint.shift(y)) & 1u) != 0;
     return Layout::matched(word, y);
   };
 

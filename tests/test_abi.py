@@ -105,8 +105,8 @@ def test_create_bad_tuning():
     st, _ = _create(lib, tuning=ctypes.pointer(t))
     assert st == _lib.MM_ERR_INVALID_ARG
     assert b"wave_vertices" in lib.mm_last_error()
-    for field, bad in (("protocol", 2), ("hint", 3), ("scan_width", 0), ("scan_width", 9),
-                       ("layout", 5), ("stream_loads", 2), ("whole_graph_vertices", -1),
+    for field, bad in (("protocol", 2), ("hint", 3), ("hint", -1), ("scan_width", 0), ("scan_width", 9),
+                       ("layout", 5), ("stream_loads", 2), ("whole_graph_vertices", -1), ("relabel", 2),
                        ("iter_cap", -1)):
         lib.mm_default_tuning(ctypes.byref(t))
         setattr(t, field, bad)
@@ -174,3 +174,18 @@ def test_stats_struct_and_conflict_row():
     assert row["total"] == 10 and row["edges"] == 6 and row["max_per_edge"] == 5
     assert row["distribution"]["1"] == 4 and row["distribution"]["5-8"] == 1
     assert abs(row["avg_per_edge"] - 10 / 6) < 1e-12
+
+
+def test_workspace_bytes_graph():
+    lib = _lib.load()
+    t = _lib.mm_tuning()
+    lib.mm_default_tuning(ctypes.byref(t))
+    base = lib.mm_workspace_bytes(1000, ctypes.byref(t))
+    assert lib.mm_workspace_bytes_graph(1000, 5000, ctypes.byref(t)) == base
+    t.relabel = 1
+    assert lib.mm_workspace_bytes(1000, ctypes.byref(t)) == 0
+    big = lib.mm_workspace_bytes_graph(1000, 5000, ctypes.byref(t))
+    assert big >= base + 4 * 1000 + 8 * 1001 + 4 * 1000 + 4 * 5000
+    assert lib.mm_workspace_bytes_graph(1000, -1, ctypes.byref(t)) == 0
+    vtx = (ctypes.c_int64 * 2)(0, 10)
+    assert lib.mm_batch_workspace_bytes(1, vtx, ctypes.byref(t)) == 0

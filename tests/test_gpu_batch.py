@@ -26,6 +26,7 @@ TUNINGS = {
                               lazy_init=1),
     "u8_small": mm.Tuning(layout=_lib.MM_LAYOUT_U8, wave_vertices=64, wg_size=64, assist_after=2,
                           lazy_init=1),
+    "u32_bytehint": mm.Tuning(hint=2, whole_graph_vertices=0),
 }
 
 
@@ -205,3 +206,11 @@ def test_batch_validate_rejects_offsets_beyond_m():
     with pytest.raises(mm.MMError) as ei:
         mm.Batch(off, nbr, [0, 2, 3], validate=True)
     assert ei.value.status == _lib.MM_ERR_INVALID_GRAPH
+
+
+def test_batch_rejects_relabel():
+    mix = mixture_small(G=3, seed=1)
+    with pytest.raises(mm.MMError) as ei:
+        mm.Batch(torch.from_numpy(mix.off).cuda(), torch.from_numpy(mix.nbr).cuda(), mix.vtx_off,
+                 tuning=mm.Tuning(relabel=1))
+    assert ei.value.status in (_lib.MM_ERR_UNSUPPORTED, _lib.MM_ERR_INVALID_ARG)

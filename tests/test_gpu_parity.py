@@ -48,6 +48,15 @@ TUNINGS = {
     "u2_two_lazy": mm.Tuning(layout=U2, protocol=TWO, scan_width=2, lazy_init=1),
     "u2_cas_hint": mm.Tuning(layout=U2, protocol=CAS, hint=1, lazy_init=0),
     "u32_cas_hint_nt": mm.Tuning(layout=U32, hint=1, stream_loads=1),
+    "relabel_u32_cas": mm.Tuning(relabel=1),
+    "relabel_u32_cas_hint": mm.Tuning(relabel=1, hint=1, whole_graph_vertices=0,
+                                      wave_vertices=64, wg_size=128),
+    "relabel_u32_two": mm.Tuning(relabel=1, protocol=TWO, lazy_init=1, scan_width=2),
+    "relabel_u8_cas": mm.Tuning(relabel=1, layout=U8, lazy_init=1, whole_graph_vertices=0),
+    "relabel_u2_two_hint": mm.Tuning(relabel=1, layout=U2, protocol=TWO, hint=1, assist_after=4),
+    "relabel_u32_bytehint": mm.Tuning(relabel=1, hint=2),
+    "u8_two_bytehint": mm.Tuning(layout=U8, protocol=TWO, hint=2, lazy_init=1),
+    "u32_cas_bytehint_w2": mm.Tuning(hint=2, scan_width=2, wave_vertices=128),
 }
 
 
@@ -378,3 +387,33 @@ def test_pair_list_small_buffer_reports_count():
     assert st == _lib.MM_ERR_OUT_OF_MEMORY and cnt.value == 4
     b = buf.cpu().numpy().reshape(2, 2)
     assert all(row[1] == row[0] + 1 and row[0] % 2 == 0 for row in b)
+
+
+# ---------------------------------------------------------------- relabelled sweep
+
+def test_relabel_all_isolated_and_stats():
+    # every vertex isolated: the relabelled sweep has no source at all
+    g = graphgen.from_edges(1000, np.zeros((0, 2)))
+    mate, st = gpu_match(g, mm.Tuning(relabel=1), stats=True)
+    assert (mate == -1).all() and st["sources"] == 0
+    # sources visited = vertices with entries
+    g = graphgen.rmat(14, seed=6)
+    mate, st = gpu_match(g, mm.Tuning(relabel=1, whole_graph_vertices=0), stats=True)
+    assert_parity(g, mate)
+    assert st["sources"] == int((np.diff(g.off) > 0).sum())
+    assert st["pairs"] == oracle.check(g, mate).size
+
+
+def test_relabel_workspace_sizing():
+    g = graphgen.rmat(12, seed=2)
+    off, nbr = to_dev(g)
+    t = mm.Tuning(relabel=1).to_c()
+    lib = _lib.load()
+    assert lib.mm_workspace_bytes(g.n, ctypes.byref(t)) == 0
+    need = lib.mm_workspace_bytes_graph(g.n, g.m, ctypes.byref(t))
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    h = ctypes.c_void_p()
+    st = lib.mm_create(ctypes.c_void_p(off.data_ptr()), _lib.MM_OFF_I64, ctypes.c_void_p(nbr.data_ptr()),
+                       g.n, g.m, ctypes.c_void_p(ws.data_ptr()), need - 256, 0, ctypes.byref(t), None,
+                       ctypes.byref(h))
+    assert st == _lib.MM_ERR_OUT_OF_MEMORY and not h.value
