@@ -231,6 +231,8 @@ def main(argv=None):
     ap.add_argument("--rmat-scale", type=int, default=27)
     ap.add_argument("--grid-side", type=int, default=16384)
     ap.add_argument("--out", default=None, help="JSON file (default: the package's tuned/ entry)")
+    ap.add_argument("--from-defaults", action="store_true",
+                    help="start every search from the library defaults instead of the stored table")
     a = ap.parse_args(argv)
     key = device_key()
     out = a.out or tuned_path(key)
@@ -241,7 +243,8 @@ def main(argv=None):
     for c, make in _targets(a.classes.split(","), a.seed, a.rmat_scale, a.grid_side).items():
         t0 = time.time()
         print("== %s" % c, flush=True)
-        r = search(make(), passes=a.passes, log=lambda s: print(s, flush=True))
+        start = None if a.from_defaults else tuned(c, key)
+        r = search(make(), start=start, passes=a.passes, log=lambda s: print(s, flush=True))
         r["seconds"] = round(time.time() - t0, 1)
         doc["classes"][c] = r
         print(json.dumps({c: r}), flush=True)

@@ -26,7 +26,7 @@ class FakeTarget:
         score -= abs(np.log2(t.wave_vertices / 2048)) * 5
         score -= abs(np.log2(t.wg_size / 128)) * 3
         score -= abs(np.log2(t.assist_after / 32)) * 2
-        score += 4 * t.hint
+        score += 4 * (t.hint == 1)
         score += {_lib.MM_LAYOUT_U8: 6, _lib.MM_LAYOUT_U32: 0, _lib.MM_LAYOUT_U2: 1}[t.layout]
         return score
 
