@@ -115,9 +115,12 @@ def bench_serve(args, dev):
         sub = pool.member(g)
         off = torch.from_numpy(sub.off).to(dev)
         nbr = torch.from_numpy(sub.nbr).to(dev)
-        cls = autotune.classify(sub.off)
-        graphs.append(serve.ResidentGraph.from_tensors(off, nbr, True, sub.name,
-                                                       tuning=autotune.tuned(cls)))
+        # the class's tuned launch parameters, without relabelling: a request
+        # creates its own handle, and relabelling pays off only when a handle
+        # runs many passes
+        t = autotune.tuned(autotune.classify(sub.off))
+        t.relabel = 0
+        graphs.append(serve.ResidentGraph.from_tensors(off, nbr, True, sub.name, tuning=t))
     torch.cuda.synchronize()
     log("serving pool: %d graphs, M=%d, generated and resident in %.1fs" % (
         pool.num_graphs, pool.m, time.perf_counter() - t0))

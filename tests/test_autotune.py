@@ -72,4 +72,4 @@ def test_stored_tunings_are_valid():
             doc = json.load(f)
         for cls, entry in doc["classes"].items():
             ct = Tuning(**entry["tuning"]).to_c()
-            assert lib.mm_workspace_bytes(1000, ctypes.byref(ct)) > 0, (path, cls)
+            assert lib.mm_workspace_bytes_graph(1000, 5000, ctypes.byref(ct)) > 0, (path, cls)
