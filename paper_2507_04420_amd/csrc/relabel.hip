@@ -60,8 +60,9 @@ __global__ void count_isolated_kernel(const uint32_t* __restrict__ keys, int64_t
     if (keys[v] == 0 && (v + 1 == n || keys[v + 1] != 0)) *out = (unsigned long long)(v + 1);
 }
 
-// Copies the lists: one wavefront per 64 new vertices, taking them one after
-// the other with its lanes spread over the list.
+// Copies the lists. A wavefront takes 64 new vertices: each lane copies its
+// own vertex's list when it has at most 64 entries; longer lists are then
+// copied by the whole wavefront, one after the other, lanes spread over it.
 template <typename OffT>
 __global__ void copy_lists_kernel(const OffT* __restrict__ off, const int32_t* __restrict__ nbr,
                                   const int32_t* __restrict__ orig, const int32_t* __restrict__ inv,
@@ -71,13 +72,23 @@ __global__ void copy_lists_kernel(const OffT* __restrict__ off, const int32_t* _
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
   for (int64_t base = wave * 64; base < n; base += waves * 64) {
-    const int64_t cnt = n - base < 64 ? n - base : 64;
-    for (int64_t k = 0; k < cnt; ++k) {
-      const int64_t v = base + k;
+    const int64_t v = base + lane;
+    int64_t b = 0, e = 0, d = 0;
+    if (v < n) {
       const int64_t x = orig[v];
-      const int64_t b = (int64_t)off[x], e = (int64_t)off[x + 1];
-      const int64_t d = roff[v] - b;
-      for (int64_t j = b + lane; j < e; j += 64) rnbr[d + j] = inv[nbr[j]];
+      b = (int64_t)off[x];
+      e = (int64_t)off[x + 1];
+      d = roff[v] - b;
+    }
+    const bool longl = e - b > 64;
+    if (!longl)
+      for (int64_t j = b; j < e; ++j) rnbr[d + j] = inv[nbr[j]];
+    uint64_t lm = __ballot(longl);
+    while (lm) {
+      const int l = __builtin_ctzll(lm);
+      lm &= lm - 1;
+      const int64_t lb = __shfl(b, l, 64), le = __shfl(e, l, 64), ld = __shfl(d, l, 64);
+      for (int64_t j = lb + lane; j < le; j += 64) rnbr[ld + j] = inv[nbr[j]];
     }
   }
 }
