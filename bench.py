@@ -106,6 +106,7 @@ def bench_serve(args, dev):
     kinds); small jobs are batched continuously, large ones run alone."""
     import torch
     import graphgen
+    import paper_2507_04420_amd as mm
     from paper_2507_04420_amd import autotune, serve
 
     t0 = time.perf_counter()
@@ -129,8 +130,13 @@ def bench_serve(args, dev):
     out = {"pool_graphs": pool.num_graphs, "pool_entries": int(pool.m), "small_edges": 2_000_000,
            "hbm_budget_bytes": int(free // 2), "rates": []}
 
+    # batches keep the library's whole-graph threshold: a small graph's result
+    # must not depend on the jobs it shares a launch with
+    tb = autotune.tuned("batch")
+    tb.whole_graph_vertices = mm.Tuning().whole_graph_vertices
+
     def scheduler():
-        ex = serve.GpuExecutor(batch_slots=2, solo_slots=2, tuning_batch=autotune.tuned("batch"))
+        ex = serve.GpuExecutor(batch_slots=2, solo_slots=2, tuning_batch=tb)
         return serve.Scheduler(ex, hbm_budget=free // 2, small_edges=2_000_000, max_batch=1024,
                                batch_slots=2, solo_slots=2, keep_results=False)
 
