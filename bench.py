@@ -85,6 +85,15 @@ def make_workload(name: str, seed: int):
     raise SystemExit("unknown workload %r" % name)
 
 
+def host_cpu() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "?")
+    except OSError:
+        model = "?"
+    return "%s, %d logical CPUs visible" % (model, os.cpu_count() or 0)
+
+
 def cpu_baseline(csr, budget_s: float = 30.0):
     """Times the oracle's single-thread SGMM (untuned) on the host."""
     import oracle
@@ -428,6 +437,7 @@ def main():
             "cores": 1,
             "kind": "oracle",
             "sample": "full graph, SGMM single thread, median of %d run(s), %.3f s each" % (reps, t_sgmm),
+            "host": host_cpu(),
         },
         "checker": {"violations": chk.violations, "size": chk.size, "size_sgmm": ref.pairs,
                     "t_seq": t_seq},
