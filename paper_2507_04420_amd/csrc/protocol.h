@@ -96,6 +96,7 @@ struct LayoutPacked {
   Hint hint;
   static constexpr bool kTwoPhase = TWO_PHASE;
   static constexpr bool kStateIsMate = false;
+  static constexpr bool kRelabelled = false;
   static constexpr int kPerWord = 32 / BITS;
   static constexpr int kLog = BITS == 8 ? 2 : 4;
   static constexpr uint32_t kMask = BITS == 8 ? 0xffu : 0x3u;
@@ -168,6 +169,7 @@ struct LayoutU32 {
   Hint hint;
   static constexpr bool kTwoPhase = TWO_PHASE;
   static constexpr bool kStateIsMate = true;
+  static constexpr bool kRelabelled = false;
   static constexpr uint32_t kAcc = TWO_PHASE ? 0x7fffffffu : 0xffffffffu;
   static constexpr uint32_t kRsvd = TWO_PHASE ? 0x7ffffffeu : 0xfffffffeu;
 
@@ -226,15 +228,25 @@ struct LayoutU32 {
 // the new ids; each committed pair is also written to `out` through the map
 // from new to given ids. `out` is filled with -1 before the sweep, so the
 // lazy output paths are not used with it.
+// The source's given id is read with its block (coalesced) and passed to the
+// commit, so that only the neighbour's is looked up there.
 template <class Base>
 struct Relabelled : Base {
   int32_t* out;
   const int32_t* orig;
+  static constexpr bool kRelabelled = true;
   __device__ __forceinline__ void commit(int64_t u, int64_t v) const {
     Base::commit(u, v);
     const int32_t ou = orig[u], ov = orig[v];
     out[ou] = ov;
     out[ov] = ou;
+  }
+  // x is u or v, and ox its given id
+  __device__ __forceinline__ void commit_src(int64_t u, int64_t v, int64_t x, int32_t ox) const {
+    Base::commit(u, v);
+    const int32_t oy = orig[u == x ? v : u];
+    out[ox] = oy;
+    out[oy] = ox;
   }
 };
 

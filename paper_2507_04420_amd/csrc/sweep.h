@@ -132,7 +132,7 @@ __device__ __forceinline__ int64_t readlane64(int64_t v, int l) {
 struct QSlot {
   int64_t x, b, e;
   uint32_t word;  // the filter word read for x (a first guess for a CAS on x)
-  uint32_t pad;
+  uint32_t orig;  // relabelled graphs: x's given id
 };
 constexpr int kQueue = 128;  // ring entries per wavefront (power of two)
 
@@ -189,7 +189,7 @@ __device__ __forceinline__ void sweep_block(const SweepParams& a, const OffT* __
   bool chunk_pending = false;
   uint32_t q_head = 0, q_tail = 0;
   int64_t cb_b = 0, cb_e = 0;  // this lane's source of the pending chunk
-  uint32_t cb_w = 0;
+  uint32_t cb_w = 0, cb_o = 0;  // its filter word and (relabelled graphs) given id
   int64_t trips = 0;
   int phase = P_IDLE;
   int64_t x = 0, i = 0, e = 0, u = 0, v = 0;
@@ -202,6 +202,7 @@ __device__ __forceinline__ void sweep_block(const SweepParams& a, const OffT* __
   }
   int k = 0, nids = 0, steps = 0;
   uint32_t xword = 0, vguess = 0;
+  uint32_t xorig = 0;  // relabelled graphs: the source's given id
   uint32_t econf = 0;  // conflicts met by the current edge (instrumented build)
   // Results of the operations issued on a trip, one register per phase:
   // different lanes issue different phases on the same trip, and a shared
@@ -306,7 +307,10 @@ __device__ __forceinline__ void sweep_block(const SweepParams& a, const OffT* __
           s = won ? R_ACC : Layout::decode(mat_w, v);
         }
         if (won) {
-          L.commit(u, v);
+          if constexpr (Layout::kRelabelled)
+            L.commit_src(u, v, x, (int32_t)xorig);
+          else
+            L.commit(u, v);
           if (STATS) {
             cnt.add(S_PAIRS, 1);
             cnt.edge_done(econf);
@@ -399,6 +403,7 @@ __device__ __forceinline__ void sweep_block(const SweepParams& a, const OffT* __
         slot.b = cb_b;
         slot.e = cb_e;
         slot.word = cb_w;
+        slot.orig = cb_o;
       }
       q_tail += (uint32_t)__popcll(nm);
       chunk_pending = false;
@@ -417,6 +422,7 @@ __device__ __forceinline__ void sweep_block(const SweepParams& a, const OffT* __
           i = slot.b;
           e = slot.e;
           xword = HINT ? 0u : slot.word;
+          xorig = slot.orig;
           steps = 0;
           phase = P_IDS;
         }
@@ -442,6 +448,7 @@ __device__ __forceinline__ void sweep_block(const SweepParams& a, const OffT* __
         cb_b = (int64_t)ld_stream(off + xs, nt);
         cb_e = (int64_t)ld_stream(off + xs + 1, nt);
         cb_w = filter_word(xs);
+        if constexpr (Layout::kRelabelled) cb_o = (uint32_t)L.orig[xs];
       }
       chunk_pending = true;
     }
