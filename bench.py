@@ -36,7 +36,7 @@ METRIC = "GEdges/s single-pass MM + % HBM roofline; batched vs per-graph graphs/
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_kernel_traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2507_04420_amd", "csrc", f)
-                  for f in ("protocol.h", "sweep.h", "mm.hip")]
+                  for f in ("protocol.h", "sweep.h", "mm.hip", "relabel.hip")]
 
 
 def kernel_sources_sha256() -> str:

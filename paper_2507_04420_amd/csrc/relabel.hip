@@ -61,13 +61,19 @@ __global__ void count_isolated_kernel(const uint32_t* __restrict__ keys, int64_t
 }
 
 // Copies the lists. A wavefront takes 64 new vertices: each lane copies its
-// own vertex's list when it has at most 64 entries; longer lists are then
-// copied by the whole wavefront, one after the other, lanes spread over it.
+// own vertex's list when it has at most 64 entries, sorted by new id (an
+// insertion sort in LDS, element k of lane l at k * 64 + l so that the lanes
+// use different banks); longer lists are then copied by the whole wavefront,
+// one after the other, lanes spread over it, in their given order. Ascending
+// new ids put a list's low-degree neighbours first, and those are the ones
+// still free when a low-degree source is swept: the sweep reads fewer ids.
 template <typename OffT>
-__global__ void copy_lists_kernel(const OffT* __restrict__ off, const int32_t* __restrict__ nbr,
-                                  const int32_t* __restrict__ orig, const int32_t* __restrict__ inv,
-                                  const int64_t* __restrict__ roff, int32_t* __restrict__ rnbr,
-                                  int64_t n) {
+__global__ __launch_bounds__(256) void copy_lists_kernel(
+    const OffT* __restrict__ off, const int32_t* __restrict__ nbr, const int32_t* __restrict__ orig,
+    const int32_t* __restrict__ inv, const int64_t* __restrict__ roff, int32_t* __restrict__ rnbr,
+    int64_t n) {
+  __shared__ int32_t sort_s[4][64 * 64];
+  int32_t* srt = sort_s[threadIdx.x >> 6];
   const int lane = (int)(threadIdx.x & 63);
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -81,8 +87,19 @@ __global__ void copy_lists_kernel(const OffT* __restrict__ off, const int32_t* _
       d = roff[v] - b;
     }
     const bool longl = e - b > 64;
-    if (!longl)
-      for (int64_t j = b; j < e; ++j) rnbr[d + j] = inv[nbr[j]];
+    if (!longl) {
+      const int len = (int)(e - b);
+      for (int k = 0; k < len; ++k) {
+        const int32_t key = inv[nbr[b + k]];
+        int j = k - 1;
+        while (j >= 0 && srt[j * 64 + lane] > key) {
+          srt[(j + 1) * 64 + lane] = srt[j * 64 + lane];
+          --j;
+        }
+        srt[(j + 1) * 64 + lane] = key;
+      }
+      for (int k = 0; k < len; ++k) rnbr[d + b + k] = srt[k * 64 + lane];
+    }
     uint64_t lm = __ballot(longl);
     while (lm) {
       const int l = __builtin_ctzll(lm);
