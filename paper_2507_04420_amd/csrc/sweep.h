@@ -130,9 +130,11 @@ __device__ __forceinline__ int64_t readlane64(int64_t v, int l) {
 
 // One queued source of a wavefront's front end (kept in LDS).
 struct QSlot {
-  int64_t x, b, e;
+  int64_t b, e;
+  int32_t x;
   uint32_t word;  // the filter word read for x (a first guess for a CAS on x)
   uint32_t orig;  // relabelled graphs: x's given id
+  uint32_t pad;
 };
 constexpr int kQueue = 128;  // ring entries per wavefront (power of two)
 
@@ -192,7 +194,9 @@ __device__ __forceinline__ void sweep_block(const SweepParams& a, const OffT* __
   uint32_t cb_w = 0, cb_o = 0;  // its filter word and (relabelled graphs) given id
   int64_t trips = 0;
   int phase = P_IDLE;
-  int64_t x = 0, i = 0, e = 0, u = 0, v = 0;
+  // vertex ids (local to the graph, < 2^31) in 32 bits, list positions in 64
+  int32_t x = 0, u = 0, v = 0;
+  int64_t i = 0, e = 0;
   int32_t ids[kMaxW];
   uint32_t rw[kMaxW];
 #pragma unroll
@@ -210,7 +214,8 @@ __device__ __forceinline__ void sweep_block(const SweepParams& a, const OffT* __
   uint32_t res_w = 0, chk_u = 0, chk_v = 0, mat_w = 0, matw_w = 0, fin_w = 0;
   // wavefront assist (uniform state)
   int asst = 0, al = 0;
-  int64_t ai = 0, ae = 0, ax = 0;
+  int64_t ai = 0, ae = 0;
+  int32_t ax = 0;
   int32_t aid = -1;
   uint32_t aw = 0, axw = 0;
 
@@ -228,7 +233,7 @@ __device__ __forceinline__ void sweep_block(const SweepParams& a, const OffT* __
       }
     }
     if (found >= 0) {
-      const int64_t y = fy;
+      const int32_t y = fy;
       k = found + 1;
       u = x < y ? x : y;
       v = x < y ? y : x;
@@ -240,7 +245,7 @@ __device__ __forceinline__ void sweep_block(const SweepParams& a, const OffT* __
     }
   };
   // The current edge cannot be matched because w (u or v) is matched.
-  auto edge_dead = [&](int64_t w) {
+  auto edge_dead = [&](int32_t w) {
     if (STATS) {
       cnt.edge_done(econf);
       econf = 0;
@@ -399,7 +404,7 @@ __device__ __forceinline__ void sweep_block(const SweepParams& a, const OffT* __
       const uint64_t nm = __ballot(need);
       if (need) {
         QSlot& slot = q[(q_tail + lanes_below(nm)) & (kQueue - 1)];
-        slot.x = xs;
+        slot.x = (int32_t)xs;
         slot.b = cb_b;
         slot.e = cb_e;
         slot.word = cb_w;
@@ -466,7 +471,7 @@ __device__ __forceinline__ void sweep_block(const SweepParams& a, const OffT* __
         al = __builtin_ctzll(lm);
         ai = readlane64(i, al);
         ae = readlane64(e, al);
-        ax = readlane64(x, al);
+        ax = __builtin_amdgcn_readlane(x, al);
         if (lane == al) phase = P_ASST;
         aid = (ai + lane < ae) ? ld_stream(nbr + ai + lane, nt) : -1;
         asst = 1;
