@@ -103,16 +103,58 @@ namespace {
 
 // ---------------------------------------------------------------- kernels
 
+// A region to fill, split into a scalar head up to 16-byte alignment, whole
+// 16-byte quads, and a scalar tail.
+struct FillRegion {
+  uint32_t* head;
+  int64_t head_words;
+  uint4* quads;
+  int64_t n_quads;
+  uint32_t* tail;
+  int64_t tail_words;
+  uint32_t value;
+};
+
+__host__ __device__ inline FillRegion fill_region(uint32_t* p, int64_t words, uint32_t value) {
+  FillRegion r;
+  const int64_t mis = (int64_t)((reinterpret_cast<uintptr_t>(p) >> 2) & 3);
+  r.head = p;
+  r.head_words = mis ? (4 - mis < words ? 4 - mis : words) : 0;
+  r.quads = reinterpret_cast<uint4*>(p + r.head_words);
+  r.n_quads = (words - r.head_words) >> 2;
+  r.tail = p + r.head_words + 4 * r.n_quads;
+  r.tail_words = words - r.head_words - 4 * r.n_quads;
+  r.value = value;
+  return r;
+}
+
 // Fills `words` 32-bit words with `value` (state and mate initialisation,
-// Alg. 1 L3-4).
-__global__ void fill_u32_kernel(uint32_t* __restrict__ p, int64_t words, uint32_t value) {
+// Alg. 1 L3-4). Any 4-byte alignment.
+__global__ void fill_u32_kernel(FillRegion r) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t quads = words >> 2;
-  uint4* q = reinterpret_cast<uint4*>(p);
-  const uint4 vv = make_uint4(value, value, value, value);
-  for (int64_t j = t; j < quads; j += stride) q[j] = vv;
-  for (int64_t j = (quads << 2) + t; j < words; j += stride) p[j] = value;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint4 vv = make_uint4(r.value, r.value, r.value, r.value);
+  for (int64_t j = t; j < r.n_quads; j += stride) r.quads[j] = vv;
+  if (t < r.head_words) r.head[t] = r.value;
+  if (t < r.tail_words) r.tail[t] = r.value;
+}
+
+// Two fills in one launch: the output and the states of a relabelled pass.
+__global__ void fill2_u32_kernel(FillRegion a, FillRegion b) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint4 va = make_uint4(a.value, a.value, a.value, a.value);
+  const uint4 vb = make_uint4(b.value, b.value, b.value, b.value);
+  for (int64_t j = t; j < a.n_quads + b.n_quads; j += stride) {
+    if (j < a.n_quads)
+      a.quads[j] = va;
+    else
+      b.quads[j - a.n_quads] = vb;
+  }
+  if (t < a.head_words) a.head[t] = a.value;
+  if (t < a.tail_words) a.tail[t] = a.value;
+  if (t < b.head_words) b.head[t] = b.value;
+  if (t < b.tail_words) b.tail[t] = b.value;
 }
 
 // Rewrites every word equal to `from` as `to` (word layout, two-phase
@@ -296,7 +338,8 @@ hipError_t dispatch_flags(const mm_graph* g, const Layout& L, hipStream_t s) {
 
 void fill(uint32_t* p, int64_t words, uint32_t value, hipStream_t s) {
   if (words > 0)
-    hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(words)), dim3(256), 0, s, p, words, value);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(words)), dim3(256), 0, s,
+                       fill_region(p, words, value));
 }
 
 // Relabelled graph: states in the new ids, output written in the given ids
@@ -306,18 +349,23 @@ hipError_t run_relabelled(const mm_graph* g, int32_t* out, hipStream_t s) {
   const int64_t n = g->n;
   Hint hint{g->hint(), hint_lg(g->tun.hint)};
   if (hint.bits) fill(hint.bits, hint_words(n, g->tun.hint), 0u, s);
-  fill(reinterpret_cast<uint32_t*>(out), n, 0xffffffffu, s);
+  if (g->tun.layout != MM_LAYOUT_U32) fill(reinterpret_cast<uint32_t*>(out), n, 0xffffffffu, s);
   const bool two = g->tun.protocol == MM_PROTOCOL_TWO_PHASE;
   const int32_t* orig = g->rl.orig;
   if (g->tun.layout == MM_LAYOUT_U32) {
-    uint32_t* st = reinterpret_cast<uint32_t*>(g->rl_state);
+    // On symmetric input an isolated vertex is nobody's neighbour, so the
+    // states from the first vertex with entries (rounded down to 4) suffice.
+    const int64_t s0 = (g->flags & MM_SYMMETRIC) ? (g->rl.n_isolated & ~(int64_t)3) : 0;
+    uint32_t* st = reinterpret_cast<uint32_t*>(g->rl_state) + s0;
+    const uint32_t acc = two ? LayoutU32<true>::kAcc : LayoutU32<false>::kAcc;
+    hipLaunchKernelGGL(fill2_u32_kernel, dim3(grid_for(2 * n - s0)), dim3(256), 0, s,
+                       fill_region(reinterpret_cast<uint32_t*>(out), n, 0xffffffffu),
+                       fill_region(st, n - s0, acc));
     if (two) {
       using L = Relabelled<LayoutU32<true>>;
-      fill(st, n, LayoutU32<true>::kAcc, s);
       return dispatch_flags<int64_t, L, STATS>(g, L{{g->rl_state, hint}, out, orig}, s);
     }
     using L = Relabelled<LayoutU32<false>>;
-    fill(st, n, LayoutU32<false>::kAcc, s);
     return dispatch_flags<int64_t, L, STATS>(g, L{{g->rl_state, hint}, out, orig}, s);
   }
   // packed layouts keep their mate entries in the new ids too (in the region

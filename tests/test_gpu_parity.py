@@ -417,3 +417,20 @@ def test_relabel_workspace_sizing():
                        g.n, g.m, ctypes.c_void_p(ws.data_ptr()), need - 256, 0, ctypes.byref(t), None,
                        ctypes.byref(h))
     assert st == _lib.MM_ERR_OUT_OF_MEMORY and not h.value
+
+
+@pytest.mark.parametrize("name", ["default", "u8_cas_eager", "relabel_u32_cas", "relabel_u8_cas",
+                                  "u32_two_eager"])
+@pytest.mark.parametrize("shift", [1, 2, 3])
+def test_unaligned_output(name, shift):
+    # an output view at any 4-byte offset: fills and sweep write exactly its n entries
+    g = graphgen.rmat(13, seed=8)
+    off, nbr = to_dev(g)
+    h = mm.Graph(off, nbr, symmetric=True, tuning=TUNINGS[name])
+    buf = torch.full((g.n + 8,), 12345, dtype=torch.int32, device="cuda")
+    out = buf[shift:shift + g.n]
+    h.run(out)
+    h.sync()
+    b = buf.cpu().numpy()
+    assert (b[:shift] == 12345).all() and (b[shift + g.n:] == 12345).all()
+    assert_parity(g, b[shift:shift + g.n])
