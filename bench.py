@@ -109,6 +109,70 @@ def cpu_baseline(csr, budget_s: float = 30.0):
     return res, t, len(times)
 
 
+# Design-choice variants (--variants): overrides of the tuned tuning, one
+# choice at a time, each timed and counted on the same resident graph.
+VARIANTS = {
+    "tuned": {},
+    "natural_order": {"relabel": 0},
+    "u8_byte_cas": {"layout": 0, "protocol": 0, "lazy_init": 0},
+    "u8_byte_cas_lazy": {"layout": 0, "protocol": 0, "lazy_init": 1},
+    "u2_two_phase": {"layout": 2, "protocol": 1, "lazy_init": 0},
+    "u32_two_phase": {"layout": 1, "protocol": 1, "lazy_init": 0},
+    "hint_bits": {"hint": 1},
+    "hint_bytes": {"hint": 2},
+    "no_hint": {"hint": 0},
+    "assist_16": {"assist_after": 16},
+    "assist_256": {"assist_after": 256},
+    "no_assist": {"assist_after": 0},
+    "contiguous_lanes": {"disperse": 0},
+    "dispersed_lanes": {"disperse": 1},
+}
+
+
+def bench_variants(args, csr, off, nbr, base, t_seq):
+    """Times each named variant (sweep mean over `steps` passes after one
+    warm-up) and counts its work in a separate instrumented pass."""
+    import paper_2507_04420_amd as mm
+    rows = []
+    w = csr.off.dtype.itemsize
+    for name in args.variants.split(","):
+        t = mm.Tuning(**dict(base.as_dict(), **VARIANTS[name]))
+        g = mm.Graph(off, nbr, symmetric=True, timing=True, tuning=t)
+        out = g.run()
+        g.sync()
+        g.timing()
+        for _ in range(args.steps):
+            g.run(out)
+        g.sync()
+        tm = g.timing()
+        chk = g.check(out)
+        g.close()
+        gs = mm.Graph(off, nbr, symmetric=True, stats=True, tuning=t)
+        o2 = gs.run()
+        gs.sync()
+        st = gs.stats()
+        gs.close()
+        del o2
+        sweep_s = tm["mean_ms"] / 1e3
+        b_sweep = w * (csr.n + 1) + 5 * t_seq + csr.n + 4 * csr.n
+        row = {"variant": name, "tuning": t.as_dict(), "sweep_ms": round(tm["mean_ms"], 4),
+               "gedges_per_s": round(csr.m / sweep_s / 1e9, 1),
+               "alg_gbs": round(b_sweep / sweep_s / 1e9, 1),
+               "violations": sum(chk[k] for k in ("out_of_range", "self_mate", "asymmetric",
+                                                  "not_edge", "uncovered")),
+               "size": chk["matched"] // 2,
+               "t_gpu_over_m": round((st["touched"] + st["assist_reads"]) / csr.m, 5),
+               "atomics": st["reserve_attempts"] + st["match_attempts"],
+               "conflicts": st["reserve_conflicts"] + st["match_conflicts"],
+               "word_retries": st["word_retries"], "pairs": st["pairs"],
+               "launches": 1 + args.steps}
+        rows.append(row)
+        log("variant %-18s sweep %.4f ms  %.1f GEdges/s  T/m %.4f  atomics %d  conflicts %d  viol %d" % (
+            name, row["sweep_ms"], row["gedges_per_s"], row["t_gpu_over_m"], row["atomics"],
+            row["conflicts"], row["violations"]))
+    return rows
+
+
 def bench_serve(args, dev):
     """Serving: Poisson streams of requests over a pool of resident graphs
     whose entry counts are log-uniform in [1e4, 5e7] (ER, grid and R-MAT
@@ -175,7 +239,6 @@ def bench_batch(args, tun, dev):
     (same kernels, same tuning, caches warm)."""
     import torch
     import graphgen
-    import oracle
     import paper_2507_04420_amd as mm
 
     t0 = time.perf_counter()
@@ -201,7 +264,6 @@ def bench_batch(args, tun, dev):
     torch.cuda.synchronize()
     b.sync()
     ms_batched = ev0.elapsed_time(ev1) / reps
-    mate_b = out.cpu().numpy()
 
     # per-graph launches: one handle per member graph, outputs are views of one
     # tensor. Each launch spreads its graph over many wavefronts (no whole-graph
@@ -229,14 +291,12 @@ def bench_batch(args, tun, dev):
     ev1.record(stream)
     torch.cuda.synchronize()
     ms_per_graph_total = ev0.elapsed_time(ev1) / rounds
-    mate_p = out2.cpu().numpy()
 
-    bad_b = bad_p = 0
-    for g in range(G):
-        sub = mix.member(g)
-        v0, v1 = int(vtx[g]), int(vtx[g + 1])
-        bad_b += oracle.check(sub, mate_b[v0:v1]).violations
-        bad_p += oracle.check(sub, mate_p[v0:v1]).violations
+    # untimed: the library's device check of both outputs (every member graph)
+    def violations(r):
+        return sum(r[k] for k in ("out_of_range", "self_mate", "asymmetric", "not_edge", "uncovered"))
+    bad_b = violations(b.check(out))
+    bad_p = violations(b.check(out2))
     items = b.items
     for h in handles:
         h.close()
@@ -281,6 +341,10 @@ def main():
     ap.add_argument("--serve-rates", type=float, nargs="+", default=[200.0, 500.0, 1000.0, 2000.0])
     ap.add_argument("--serve-seconds", type=float, default=1.5)
     ap.add_argument("--serve-pool", type=int, default=96)
+    ap.add_argument("--variants", default=None,
+                    help="comma-separated design-choice variants (%s): time and count each on the "
+                         "workload and print one JSON line of rows instead of the benchmark line"
+                         % ",".join(VARIANTS))
     ap.add_argument("--untuned", action="store_true",
                     help="library default tunings instead of the autotuned table")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -336,6 +400,13 @@ def main():
         del src, dst
         log("copy calibration: 3 x (1 GiB read + 1 GiB write) with torch.add(src, 0, out=dst)")
 
+    if args.variants:
+        rows = bench_variants(args, csr, off, nbr, tun, t_seq)
+        print(json.dumps({"mode": "variants", "config": config, "n": csr.n, "m": csr.m,
+                          "t_seq": t_seq, "size_sgmm": ref.pairs, "steps": args.steps,
+                          "rows": rows}), flush=True)
+        return
+
     g = mm.Graph(off, nbr, symmetric=True, validate=True, timing=True, tuning=tun)
     out = torch.empty(csr.n, dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream()
@@ -359,11 +430,13 @@ def main():
     log("timed %d steps: %.4f ms/step; sweep kernel mean %.4f ms (min %.4f, max %.4f, n=%d)" % (
         args.steps, ms_per_step, sweep["mean_ms"], sweep["min_ms"], sweep["max_ms"], sweep["count"]))
 
-    # Untimed: exact check of the last output.
-    import oracle
-    mate = out.cpu().numpy()
-    chk = oracle.check(csr, mate)
-    log("checker: violations=%d size=%d (SGMM %d)" % (chk.violations, chk.size, ref.pairs))
+    # Untimed: the library's device check of the last output (the exact
+    # checker of Section II-B, counted on the GPU; the test suite pins it
+    # against the oracle's).
+    chk = g.check(out)
+    chk_viol = sum(chk[k] for k in ("out_of_range", "self_mate", "asymmetric", "not_edge", "uncovered"))
+    chk_size = chk["matched"] // 2
+    log("check: violations=%d size=%d (SGMM %d)" % (chk_viol, chk_size, ref.pairs))
 
     counters = conflicts = None
     if not args.no_stats:
@@ -371,8 +444,9 @@ def main():
         o2 = gs.run()
         gs.sync()
         counters = gs.stats()
-        c2 = oracle.check(csr, o2.cpu().numpy())
-        counters["checker_violations"] = c2.violations
+        c2 = gs.check(o2)
+        counters["checker_violations"] = sum(
+            c2[k] for k in ("out_of_range", "self_mate", "asymmetric", "not_edge", "uncovered"))
         gs.close()
         log("counters: %s" % counters)
         # Table II on this graph: worst (most conflicting edges) of five passes
@@ -439,8 +513,8 @@ def main():
             "sample": "full graph, SGMM single thread, median of %d run(s), %.3f s each" % (reps, t_sgmm),
             "host": host_cpu(),
         },
-        "checker": {"violations": chk.violations, "size": chk.size, "size_sgmm": ref.pairs,
-                    "t_seq": t_seq},
+        "checker": {"kind": "device check (mm_check)", "violations": int(chk_viol),
+                    "size": int(chk_size), "size_sgmm": ref.pairs, "t_seq": t_seq},
         "counters": counters,
         "conflicts": conflicts,
         "batch": batch,

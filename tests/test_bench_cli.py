@@ -32,3 +32,13 @@ def test_traffic_lookup(tmp_path, monkeypatch):
     f.write_text(json.dumps({"kernel_sources_sha256": "0" * 64, "config": cfg,
                              "hbm_bytes_per_launch": 4.5e10}))
     assert bench.measured_traffic(cfg) is None  # kernel changed since
+
+
+def test_variants_are_valid_tunings():
+    import ctypes
+    import paper_2507_04420_amd as mm
+    from paper_2507_04420_amd import _lib
+    lib = _lib.load()
+    for name, over in bench.VARIANTS.items():
+        t = mm.Tuning(**dict(mm.Tuning().as_dict(), **over)).to_c()
+        assert lib.mm_workspace_bytes_graph(1000, 5000, ctypes.byref(t)) > 0, name
