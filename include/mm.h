@@ -131,6 +131,13 @@ typedef struct {
                             lines. Output stays in the given ids. Workspace from
                             mm_workspace_bytes_graph; create allocates temporary
                             device memory for the sort */
+  int32_t hub_degree;    /* single graphs: lists longer than this are not swept by
+                            their block's lane but cut into pieces of hub_chunk
+                            entries, each swept by its own lane in a second launch
+                            right after the first (the hub tier); 0 disables.
+                            mm_create then allocates the piece table itself
+                            (device memory, freed by mm_destroy) */
+  int32_t hub_chunk;     /* entries per piece of a long list, >= 1 */
   int64_t iter_cap;      /* loop-trip budget per wavefront; 0 = default of
                             65536 + 8 x (neighbour entries of its block);
                             exceeding it raises MM_ERR_NO_PROGRESS */

@@ -44,6 +44,8 @@ class Tuning:
     stream_loads: int = 0
     whole_graph_vertices: int = 16384
     relabel: int = 0
+    hub_degree: int = 4096
+    hub_chunk: int = 256
     iter_cap: int = 0
 
     @classmethod

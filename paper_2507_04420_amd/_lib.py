@@ -47,6 +47,8 @@ class mm_tuning(ctypes.Structure):
         ("stream_loads", ctypes.c_int32),
         ("whole_graph_vertices", ctypes.c_int32),
         ("relabel", ctypes.c_int32),
+        ("hub_degree", ctypes.c_int32),
+        ("hub_chunk", ctypes.c_int32),
         ("iter_cap", ctypes.c_int64),
     ]
 

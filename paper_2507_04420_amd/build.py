@@ -11,7 +11,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libmm_hip.so")
-SOURCES = [os.path.join(CSRC, f) for f in ("mm.hip", "batch.hip", "check.hip", "pairs.hip", "ems.hip", "relabel.hip")]
+SOURCES = [os.path.join(CSRC, f) for f in ("mm.hip", "batch.hip", "check.hip", "pairs.hip", "ems.hip", "relabel.hip", "hubs.hip")]
 HEADERS = [os.path.join(CSRC, f) for f in ("protocol.h", "sweep.h", "batch.h", "internal.h")] + [
     os.path.join(ROOT, "include", "mm.h")]
 

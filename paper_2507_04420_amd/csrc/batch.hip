@@ -443,6 +443,9 @@ mm_status finish_create(std::vector<mmb::GraphDesc>& descs, const std::vector<in
   p.params.scan_width = t.scan_width;
   p.params.stream_loads = t.stream_loads;
   p.params.iter_cap = t.iter_cap;
+  p.params.hub_degree = 0;  // the hub tier is for single graphs
+  p.params.hub_chunk = 0;
+  p.params.chunks = nullptr;
   p.params.err = f;
   p.descs = descs_dev;
   p.items = items_dev;

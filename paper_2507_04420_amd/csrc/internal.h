@@ -42,6 +42,16 @@ size_t relabel_bytes(int64_t n, int64_t m);
 hipError_t build_relabel(const void* off, int off64, const int32_t* nbr, int64_t n, int64_t m,
                          uint8_t* region, RelabelView* view, hipStream_t s);
 
+// The hub tier's table (see hubs.hip); allocated here, freed with hipFree by
+// the handle's owner. *count = 0 and *table = null when no list is long enough.
+}  // namespace mmi
+namespace mmk {
+struct HubChunk;
+}
+namespace mmi {
+hipError_t build_hub_chunks(const void* off, int off64, int64_t n, int64_t hub_degree,
+                            int64_t chunk, mmk::HubChunk** table, int64_t* count, hipStream_t s);
+
 // Copies the raw device counters (sweep.h order) into the ABI struct.
 void stats_from_counters(const unsigned long long* c, mm_stats* out);
 

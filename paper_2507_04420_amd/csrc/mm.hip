@@ -62,6 +62,9 @@ mm_status check_tuning(const mm_tuning& t) {
     return fail(MM_ERR_INVALID_ARG, "tuning.whole_graph_vertices must be >= 0");
   if (t.relabel != 0 && t.relabel != 1)
     return fail(MM_ERR_INVALID_ARG, "tuning.relabel must be 0 or 1");
+  if (t.hub_degree < 0) return fail(MM_ERR_INVALID_ARG, "tuning.hub_degree must be >= 0");
+  if (t.hub_degree > 0 && t.hub_chunk < 1)
+    return fail(MM_ERR_INVALID_ARG, "tuning.hub_chunk must be >= 1 when hub_degree > 0");
   if (t.iter_cap < 0) return fail(MM_ERR_INVALID_ARG, "tuning.iter_cap must be >= 0");
   return MM_OK;
 }
@@ -245,6 +248,8 @@ struct mm_graph {
   bool lazy;  // effective lazy output
   int device;
   TimingRing* timing;
+  mmk::HubChunk* chunks = nullptr;  // hub tier table (device, owned), or null
+  int64_t n_chunks = 0;
   bool relabel;         // sweep the graph relabelled by degree (relabel.hip)
   mmi::RelabelView rl;  // its arrays, in the workspace
   int32_t* rl_state;    // word-layout states in the new ids (relabel only)
@@ -280,6 +285,9 @@ SweepParams make_params(const mm_graph* g) {
   p.stream_loads = g->tun.stream_loads;
   p.iter_cap = g->tun.iter_cap;
   p.err = reinterpret_cast<uint32_t*>(g->ws);
+  p.hub_degree = g->n_chunks > 0 ? g->tun.hub_degree : 0;
+  p.hub_chunk = g->tun.hub_chunk;
+  p.chunks = nullptr;
   const int64_t ns = g->n - sweep_begin(g);
   if (ns <= g->tun.whole_graph_vertices) {  // one wavefront takes the whole graph
     p.wave_vertices = std::max<int64_t>(64, (ns + 63) / 64 * 64);
@@ -313,6 +321,20 @@ hipError_t launch_sweep(const mm_graph* g, const Layout& L, hipStream_t s) {
                      dim3(g->tun.wg_size), 0, s, p, off, nbr, g->n, v_begin, L, stats);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if (g->n_chunks > 0) {
+    // the hub tier's chunk pass: 64 pieces of long lists per wavefront
+    SweepParams pc = p;
+    pc.wave_vertices = 64;
+    pc.disperse = 0;
+    pc.hub_degree = 0;
+    pc.chunks = g->chunks;
+    const int64_t cblocks = ((g->n_chunks + 63) / 64 + wpb - 1) / wpb;
+    hipLaunchKernelGGL((sweep_kernel<OffT, Layout, HINT, false, STATS>), dim3((unsigned)cblocks),
+                       dim3(g->tun.wg_size), 0, s, pc, off, nbr, g->n_chunks, (int64_t)0, L,
+                       stats);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   if (g->timing) {
     e = hipEventRecord(g->timing->after(), s);
     ++g->timing->recorded;
@@ -446,6 +468,8 @@ void mm_default_tuning(mm_tuning* t) {
   t->lazy_init = 0;
   t->scan_width = 4;
   t->whole_graph_vertices = 16384;
+  t->hub_degree = 4096;
+  t->hub_chunk = 256;
   t->iter_cap = 0;
 }
 
@@ -547,11 +571,24 @@ mm_status mm_create(const void* offsets, mm_offset_type off_type, const int32_t*
   // Lazy output is only sound when every edge is in both endpoints' lists.
   g->lazy = t.lazy_init && (flags & MM_SYMMETRIC) && !t.relabel &&
             !(t.layout == MM_LAYOUT_U32 && t.protocol == MM_PROTOCOL_CAS);
+  if (t.hub_degree > 0 && m > t.hub_degree) {
+    // the table is built on the lists the sweep reads (relabelled or given)
+    hipError_t e = g->relabel
+        ? mmi::build_hub_chunks(g->rl.off, 1, n, t.hub_degree, t.hub_chunk, &g->chunks, &g->n_chunks, s)
+        : mmi::build_hub_chunks(offsets, off_type == MM_OFF_I64, n, t.hub_degree, t.hub_chunk,
+                                &g->chunks, &g->n_chunks, s);
+    if (e != hipSuccess) {
+      delete g;
+      return fail(MM_ERR_HIP, "building the hub table failed: %s", hipGetErrorString(e));
+    }
+    if (g->n_chunks > 0) g->lazy = false;  // a piece of a list cannot finalise its source
+  }
   g->device = dev;
   g->timing = nullptr;
   if (flags & MM_TIMING) {
     g->timing = new (std::nothrow) TimingRing();
     if (!g->timing) {
+      if (g->chunks) hipFree(g->chunks);
       delete g;
       return fail(MM_ERR_OUT_OF_MEMORY, "host allocation of the timing ring failed");
     }
@@ -559,6 +596,7 @@ mm_status mm_create(const void* offsets, mm_offset_type off_type, const int32_t*
     if (e != hipSuccess) {
       g->timing->destroy();
       delete g->timing;
+      if (g->chunks) hipFree(g->chunks);
       delete g;
       return fail(MM_ERR_HIP, "hipEventCreate failed: %s", hipGetErrorString(e));
     }
@@ -643,6 +681,7 @@ mm_status mm_get_timing(mm_handle g, int64_t* count, double* total_ms, double* m
 
 void mm_destroy(mm_handle g) {
   if (!g) return;
+  if (g->chunks) hipFree(g->chunks);
   if (g->timing) {
     g->timing->destroy();
     delete g->timing;

@@ -63,6 +63,13 @@ enum : int {
 // Launch parameters shared by every block of a sweep. Vertex ids inside a
 // block are local to its graph; the layout object and the offsets pointer
 // are already based at the graph's first vertex.
+// A piece of a long list (the hub tier): entries b .. e-1 of source x.
+struct HubChunk {
+  int64_t b, e;
+  int32_t x;
+  int32_t pad;
+};
+
 struct SweepParams {
   int64_t wave_vertices;   // multiple of 64
   int32_t disperse;
@@ -71,6 +78,13 @@ struct SweepParams {
   int32_t stream_loads;    // 1: offsets and ids through non-temporal loads
   int64_t iter_cap;        // 0: per-block default budget
   uint32_t* err;           // bit 0: loop-trip budget exceeded
+  // Hub tier. Main pass: sources with more than hub_degree entries are left
+  // to the chunk pass (0: none are). Chunk pass (chunks != null): the block
+  // indexes this table instead of the vertices, each entry one piece of at
+  // most hub_chunk entries of one long list.
+  int64_t hub_degree;
+  int64_t hub_chunk;
+  const HubChunk* chunks;
 };
 
 // Counters of the instrumented build. S_H0 .. S_H0+9: edges by the number of
@@ -170,7 +184,8 @@ __device__ __forceinline__ void sweep_block(const SweepParams& a, const OffT* __
   // of the block (a pass needs at most about one trip per entry plus short
   // waits), so even an unforeseen livelock ends with an error flag.
   const int64_t cap = a.iter_cap > 0 ? a.iter_cap
-                                     : 65536 + 8 * ((int64_t)off[vb + nv] - (int64_t)off[vb]);
+                     : a.chunks ? 65536 + 8 * nv * a.hub_chunk
+                                : 65536 + 8 * ((int64_t)off[vb + nv] - (int64_t)off[vb]);
 
   // Filter reads: the hint bit, or the vertex's own state word.
   auto filter_word = [&](int64_t y) -> uint32_t {
@@ -191,6 +206,7 @@ __device__ __forceinline__ void sweep_block(const SweepParams& a, const OffT* __
   bool chunk_pending = false;
   uint32_t q_head = 0, q_tail = 0;
   int64_t cb_b = 0, cb_e = 0;  // this lane's source of the pending chunk
+  int32_t cb_x = 0;
   uint32_t cb_w = 0, cb_o = 0;  // its filter word and (relabelled graphs) given id
   int64_t trips = 0;
   int phase = P_IDLE;
@@ -391,10 +407,12 @@ __device__ __forceinline__ void sweep_block(const SweepParams& a, const OffT* __
       bool need = false;
       int64_t xs = 0;
       if (kk < nv) {
-        xs = source_of(kk);
-        if (STATS) cnt.add(S_SOURCES, 1);
+        xs = cb_x;
+        if (STATS && !a.chunks) cnt.add(S_SOURCES, 1);
         if (cb_b == cb_e) {
           if (LAZY) L.write_unmatched(xs);  // no incident entry: never matched (symmetric input)
+        } else if (a.hub_degree > 0 && cb_e - cb_b > a.hub_degree) {
+          // a long list: the chunk pass sweeps it, spread over many lanes
         } else if (filter_matched(cb_w, xs)) {
           if (STATS) cnt.add(S_SKIPPED, 1);
         } else {
@@ -449,9 +467,18 @@ __device__ __forceinline__ void sweep_block(const SweepParams& a, const OffT* __
       chunk_next += 64;
       const int64_t kk = chunk_base + lane;
       if (kk < nv) {
-        const int64_t xs = source_of(kk);
-        cb_b = (int64_t)ld_stream(off + xs, nt);
-        cb_e = (int64_t)ld_stream(off + xs + 1, nt);
+        int64_t xs;
+        if (a.chunks) {
+          const HubChunk c = a.chunks[vb + kk];
+          xs = c.x;
+          cb_b = c.b;
+          cb_e = c.e;
+        } else {
+          xs = source_of(kk);
+          cb_b = (int64_t)ld_stream(off + xs, nt);
+          cb_e = (int64_t)ld_stream(off + xs + 1, nt);
+        }
+        cb_x = (int32_t)xs;
         cb_w = filter_word(xs);
         if constexpr (Layout::kRelabelled) cb_o = (uint32_t)L.orig[xs];
       }

@@ -57,6 +57,10 @@ TUNINGS = {
     "relabel_u32_bytehint": mm.Tuning(relabel=1, hint=2),
     "u8_two_bytehint": mm.Tuning(layout=U8, protocol=TWO, hint=2, lazy_init=1),
     "u32_cas_bytehint_w2": mm.Tuning(hint=2, scan_width=2, wave_vertices=128),
+    "hub_every_entry": mm.Tuning(hub_degree=1, hub_chunk=1),
+    "hub_small_u8_lazy": mm.Tuning(layout=U8, lazy_init=1, hub_degree=8, hub_chunk=3),
+    "hub_relabel_two": mm.Tuning(relabel=1, protocol=TWO, hub_degree=5, hub_chunk=2, hint=2),
+    "no_hub_tier": mm.Tuning(hub_degree=0),
 }
 
 
@@ -434,3 +438,41 @@ def test_unaligned_output(name, shift):
     b = buf.cpu().numpy()
     assert (b[:shift] == 12345).all() and (b[shift + g.n:] == 12345).all()
     assert_parity(g, b[shift:shift + g.n])
+
+
+# ---------------------------------------------------------------- hub tier
+
+def hub_trap(k):
+    # k disjoint edges (2i, 2i+1) and one last vertex adjacent to all of them:
+    # in id order every pair matches first, and the hub's whole list is dead
+    pairs = np.stack([np.arange(0, 2 * k, 2), np.arange(1, 2 * k, 2)], 1)
+    hub = np.stack([np.full(2 * k, 2 * k), np.arange(2 * k)], 1)
+    return graphgen.from_edges(2 * k + 1, np.concatenate([pairs, hub]))
+
+
+@pytest.mark.parametrize("name", ["default", "hub_every_entry", "hub_relabel_two", "no_hub_tier"])
+def test_hub_trap(name):
+    g = hub_trap(50_000)
+    mate, _ = gpu_match(g, TUNINGS[name])
+    assert_parity(g, mate)
+    assert mate[2 * 50_000] == -1 or mate[mate[2 * 50_000]] == 2 * 50_000
+
+
+def test_hub_tier_spreads_a_long_dead_list():
+    # with the tier, the hub's dead list is swept by many lanes at once
+    import time
+    g = hub_trap(1_000_000)
+    off, nbr = to_dev(g)
+    times = {}
+    for name, t in (("tier", mm.Tuning()), ("no_tier", mm.Tuning(hub_degree=0))):
+        h = mm.Graph(off, nbr, symmetric=True, tuning=t, timing=True)
+        out = h.run()
+        h.sync()
+        h.timing()
+        h.run(out)
+        h.sync()
+        times[name] = h.timing()["mean_ms"]
+        assert_parity(g, out.cpu().numpy())
+        h.close()
+    print("hub trap sweep ms:", times)
+    assert times["tier"] * 5 < times["no_tier"]
