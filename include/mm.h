@@ -20,7 +20,9 @@
  *    non-OK status, mm_last_error() returns a thread-local message.
  *  - The graph arrays are borrowed: the library neither copies nor frees
  *    them, and they must outlive the handle. Workspaces and outputs are
- *    caller-owned device memory.
+ *    caller-owned device memory. mm_run and mm_batch_run allocate nothing;
+ *    mm_create may (tuning.relabel: temporary buffers; tuning.hub_degree:
+ *    the hub piece table, kept until mm_destroy).
  *
  * Graph format (Section II-A): CSR with `offsets` of n+1 entries (int32 or
  * int64, non-decreasing, offsets[0] = 0, offsets[n] = m) and `neighbors` of m
