@@ -22,10 +22,12 @@ struct GraphDesc {
   uint32_t* st;    // packed states, or null for the word layout
   uint32_t* hint;  // matched hint words, or null
   uint32_t hint_lg;  // log2 of vertices per hint word
-  uint32_t pad_;
+  uint32_t flags;    // kWholeGraph: swept by one wavefront, no hub pieces
 };
+constexpr uint32_t kWholeGraph = 1u;
 
-// One wavefront block: sources vb .. vb+nv-1 of graph `desc`.
+// One wavefront block: sources vb .. vb+nv-1 of graph `desc`; or, with
+// nv < 0, the hub pieces vb .. vb-nv-1 of the piece table (all of graph desc).
 struct WorkItem {
   int32_t desc;
   int32_t nv;
@@ -34,7 +36,7 @@ struct WorkItem {
 
 // Everything one pass of the batched sweep needs on the device.
 struct BatchPlan {
-  mmk::SweepParams params;
+  mmk::SweepParams params;  // hub_degree / hub_chunk / chunks: the hub tier
   const GraphDesc* descs;
   const WorkItem* items;
   int64_t n_items;
@@ -76,5 +78,13 @@ struct BatchInfo {
   uint8_t* ws;
 };
 BatchInfo batch_info(const mm_batch* b);
+
+// Hub pieces of a batch (see hubs.hip): lists longer than hub_degree in
+// graphs without kWholeGraph, cut into pieces of `chunk` entries. On return
+// *table (device, hipMalloc'd, or null) holds *count pieces, those of graph g
+// at first[g] .. first[g+1]-1 (first: host, G+1 entries).
+hipError_t build_batch_hubs(const GraphDesc* descs_dev, const int64_t* vtx_dev, int32_t G, int64_t N,
+                            int64_t hub_degree, int64_t chunk, mmk::HubChunk** table,
+                            int64_t* count, int64_t* first, hipStream_t s);
 
 }  // namespace mmb

@@ -158,7 +158,18 @@ __global__ __launch_bounds__(256) void batch_sweep_kernel(SweepParams p,
     const WorkItem w = items[it];
     const GraphDesc d = descs[w.desc];
     const Layout L = layout_of<Layout>(d, mate);
-    sweep_block<int64_t, Layout, HINT, LAZY, STATS>(p, d.off, d.nbr, L, w.vb, (int64_t)w.nv,
+    SweepParams pp = p;
+    int64_t nv = w.nv;
+    if (nv < 0) {  // hub pieces (never with lazy output: the plan turns it off)
+      nv = -nv;
+      pp.wave_vertices = 64;
+      pp.disperse = 0;
+      pp.hub_degree = 0;
+    } else {
+      pp.chunks = nullptr;
+      if (d.flags & kWholeGraph) pp.hub_degree = 0;
+    }
+    sweep_block<int64_t, Layout, HINT, LAZY, STATS>(pp, d.off, d.nbr, L, w.vb, nv,
                                                     queues[threadIdx.x >> 6], cnt);
   }
   if (STATS) cnt.flush(stats);
@@ -324,6 +335,8 @@ struct mm_batch {
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  mmk::HubChunk* chunks = nullptr;      // hub piece table (device, owned)
+  mmb::WorkItem* own_items = nullptr;   // item table when hub pieces exist (owned)
 };
 
 namespace {
@@ -374,6 +387,7 @@ mm_status finish_create(std::vector<mmb::GraphDesc>& descs, const std::vector<in
     d.st = t.layout == MM_LAYOUT_U32 ? nullptr : st_base + st_w;
     d.hint = t.hint ? hint_base + hint_w : nullptr;
     d.hint_lg = mmk::hint_lg(t.hint);
+    d.flags = d.n <= t.whole_graph_vertices ? mmb::kWholeGraph : 0u;
     st_w += mmb::state_words_for(d.n, t.layout);
     hint_w += mmk::hint_words(d.n, t.hint);
     // a small graph is one item (one wavefront), a larger one an item per block
@@ -395,9 +409,6 @@ mm_status finish_create(std::vector<mmb::GraphDesc>& descs, const std::vector<in
     HIP_TRY(hipMemcpyAsync(descs_dev, descs.data(), sizeof(mmb::GraphDesc) * G,
                            hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(vtx_dev, vtx.data(), sizeof(int64_t) * (G + 1), hipMemcpyHostToDevice, s));
-  if (!items.empty())
-    HIP_TRY(hipMemcpyAsync(items_dev, items.data(), sizeof(mmb::WorkItem) * items.size(),
-                           hipMemcpyHostToDevice, s));
   if (flags & MM_VALIDATE) {
     if (concat_off)
       HIP_TRY(mmb::validate_batch(concat_off, concat_nbr, vtx_dev, G, N, M, f, s));
@@ -417,15 +428,58 @@ mm_status finish_create(std::vector<mmb::GraphDesc>& descs, const std::vector<in
                 (hf & 2u) ? " offsets decrease;" : "",
                 (hf & 4u) ? " neighbour id outside its graph;" : "");
   }
+  // hub tier: pieces of long lists become work items of their own, after the
+  // blocks; the item table then lives in memory the handle owns
+  mmk::HubChunk* chunks = nullptr;
+  int64_t n_chunks = 0;
+  mmb::WorkItem* own_items = nullptr;
+  if (t.hub_degree > 0 && N > 0) {
+    std::vector<int64_t> first((size_t)G + 1, 0);
+    hipError_t e = mmb::build_batch_hubs(descs_dev, vtx_dev, G, N, t.hub_degree, t.hub_chunk,
+                                         &chunks, &n_chunks, first.data(), s);
+    if (e != hipSuccess) return fail(MM_ERR_HIP, "building the hub table failed: %s", hipGetErrorString(e));
+    for (int32_t g = 0; g < G; ++g)
+      for (int64_t c = first[g]; c < first[g + 1]; c += 64) {
+        mmb::WorkItem w;
+        w.desc = g;
+        w.vb = c;
+        w.nv = -(int32_t)std::min<int64_t>(64, first[g + 1] - c);
+        items.push_back(w);
+      }
+    if (n_chunks > 0) {
+      e = hipMalloc(&own_items, sizeof(mmb::WorkItem) * items.size());
+      if (e != hipSuccess) {
+        hipFree(chunks);
+        return fail(MM_ERR_OUT_OF_MEMORY, "hub item table: %s", hipGetErrorString(e));
+      }
+      items_dev = own_items;
+    }
+  }
+  if (!items.empty()) {
+    hipError_t e = hipMemcpyAsync(items_dev, items.data(), sizeof(mmb::WorkItem) * items.size(),
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);  // the host vector is released after this
+    if (e != hipSuccess) {
+      if (chunks) hipFree(chunks);
+      if (own_items) hipFree(own_items);
+      return fail(MM_ERR_HIP, "uploading the work items failed: %s", hipGetErrorString(e));
+    }
+  }
   int cus = 0, dev = 0;
   HIP_TRY(hipGetDevice(&dev));
   HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   mm_batch* b = new (std::nothrow) mm_batch();
-  if (!b) return fail(MM_ERR_OUT_OF_MEMORY, "host allocation of the batch handle failed");
+  if (!b) {
+    if (chunks) hipFree(chunks);
+    if (own_items) hipFree(own_items);
+    return fail(MM_ERR_OUT_OF_MEMORY, "host allocation of the batch handle failed");
+  }
+  b->chunks = chunks;
+  b->own_items = own_items;
   if (flags & MM_CAPTURE) {
     hipError_t e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
-      delete b;
+      mm_batch_destroy(b);
       return fail(MM_ERR_HIP, "capture stream: %s", hipGetErrorString(e));
     }
   }
@@ -443,19 +497,19 @@ mm_status finish_create(std::vector<mmb::GraphDesc>& descs, const std::vector<in
   p.params.scan_width = t.scan_width;
   p.params.stream_loads = t.stream_loads;
   p.params.iter_cap = t.iter_cap;
-  p.params.hub_degree = 0;  // the hub tier is for single graphs
-  p.params.hub_chunk = 0;
-  p.params.chunks = nullptr;
+  p.params.hub_degree = n_chunks > 0 ? t.hub_degree : 0;
+  p.params.hub_chunk = t.hub_chunk;
+  p.params.chunks = chunks;
   p.params.err = f;
   p.descs = descs_dev;
   p.items = items_dev;
-  p.n_items = lay.n_items;
+  p.n_items = (int64_t)items.size();
   p.queue = reinterpret_cast<uint32_t*>(ws + kQueueOffset);
   p.stats = reinterpret_cast<unsigned long long*>(ws + kStatsOffset);
   p.layout = t.layout;
   p.protocol = t.protocol;
   p.hint = t.hint != 0;
-  p.lazy = t.lazy_init && (flags & MM_SYMMETRIC) &&
+  p.lazy = t.lazy_init && (flags & MM_SYMMETRIC) && n_chunks == 0 &&
            !(t.layout == MM_LAYOUT_U32 && t.protocol == MM_PROTOCOL_CAS);
   p.stats_on = (flags & MM_STATS) != 0;
   p.wg_size = t.wg_size;
@@ -610,6 +664,8 @@ int64_t mm_batch_items(mm_batch_handle b) { return b ? b->plan.n_items : -1; }
 void mm_batch_destroy(mm_batch_handle b) {
   if (!b) return;
   drop_graph(b);
+  if (b->chunks) hipFree(b->chunks);
+  if (b->own_items) hipFree(b->own_items);
   if (b->cap_stream) hipStreamDestroy(b->cap_stream);
   delete b;
 }

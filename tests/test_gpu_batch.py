@@ -214,3 +214,55 @@ def test_batch_rejects_relabel():
         mm.Batch(torch.from_numpy(mix.off).cuda(), torch.from_numpy(mix.nbr).cuda(), mix.vtx_off,
                  tuning=mm.Tuning(relabel=1))
     assert ei.value.status in (_lib.MM_ERR_UNSUPPORTED, _lib.MM_ERR_INVALID_ARG)
+
+
+def hub_trap(k):
+    pairs = np.stack([np.arange(0, 2 * k, 2), np.arange(1, 2 * k, 2)], 1)
+    hub = np.stack([np.full(2 * k, 2 * k), np.arange(2 * k)], 1)
+    return graphgen.from_edges(2 * k + 1, np.concatenate([pairs, hub]))
+
+
+@pytest.mark.parametrize("tuning", [mm.Tuning(whole_graph_vertices=0),
+                                    mm.Tuning(hub_degree=3, hub_chunk=2, whole_graph_vertices=0),
+                                    mm.Tuning(hub_degree=3, hub_chunk=2, layout=_lib.MM_LAYOUT_U8,
+                                              lazy_init=1),
+                                    mm.Tuning(hub_degree=0)])
+def test_batch_hub_pieces(tuning):
+    # hub traps and mixture members in one batch, captured and replayed
+    parts = [hub_trap(20_000), mixture_small(G=1, seed=31).member(0), hub_trap(300),
+             graphgen.rmat(13, seed=2)]
+    b = mm.Batch.from_list(list_of(parts), symmetric=True, capture=True, tuning=tuning)
+    out = torch.empty(b.N, dtype=torch.int32, device="cuda")
+    for rep in range(2):
+        out.fill_(-9)
+        b.run(out)
+        b.sync()
+        torch.cuda.synchronize()
+        mate = out.cpu().numpy()
+        v = b.vtx_off
+        for g, p in enumerate(parts):
+            assert oracle.check(p, mate[v[g]:v[g + 1]]).ok, (rep, g)
+    st_b = mm.Batch.from_list(list_of(parts), symmetric=True, stats=True, tuning=tuning)
+    st_b.run()
+    st_b.sync()
+    assert st_b.stats()["sources"] == b.N
+
+
+def test_batch_hub_pieces_are_fast():
+    import time
+    parts = [hub_trap(100_000)]
+    for name, t in (("tier", mm.Tuning(whole_graph_vertices=0)),
+                    ("no_tier", mm.Tuning(whole_graph_vertices=0, hub_degree=0))):
+        b = mm.Batch.from_list(list_of(parts), symmetric=True, tuning=t)
+        out = b.run()
+        b.sync()
+        t0 = time.perf_counter()
+        b.run(out)
+        b.sync()
+        dt = time.perf_counter() - t0
+        assert oracle.check(parts[0], out.cpu().numpy()).ok
+        print("batch hub trap", name, "%.3f ms" % (dt * 1e3))
+        if name == "tier":
+            tier = dt
+        else:
+            assert tier * 3 < dt
