@@ -21,8 +21,8 @@
  *  - The graph arrays are borrowed: the library neither copies nor frees
  *    them, and they must outlive the handle. Workspaces and outputs are
  *    caller-owned device memory. mm_run and mm_batch_run allocate nothing;
- *    mm_create may (tuning.relabel: temporary buffers; tuning.hub_degree:
- *    the hub piece table, kept until mm_destroy).
+ *    the create calls may (tuning.relabel: temporary buffers;
+ *    tuning.hub_degree: the hub piece table, kept until destroy).
  *
  * Graph format (Section II-A): CSR with `offsets` of n+1 entries (int32 or
  * int64, non-decreasing, offsets[0] = 0, offsets[n] = m) and `neighbors` of m
@@ -133,12 +133,14 @@ typedef struct {
                             lines. Output stays in the given ids. Workspace from
                             mm_workspace_bytes_graph; create allocates temporary
                             device memory for the sort */
-  int32_t hub_degree;    /* single graphs: lists longer than this are not swept by
-                            their block's lane but cut into pieces of hub_chunk
-                            entries, each swept by its own lane in a second launch
-                            right after the first (the hub tier); 0 disables.
-                            mm_create then allocates the piece table itself
-                            (device memory, freed by mm_destroy) */
+  int32_t hub_degree;    /* lists longer than this are not swept by their block's
+                            lane but cut into pieces of hub_chunk entries, each swept
+                            by its own lane: in a second launch right after the
+                            first (single graphs), or as work items queued after the
+                            blocks (batches; not for graphs swept whole by one
+                            wavefront). 0 disables. The create call then allocates
+                            the piece table itself (device memory, freed by the
+                            destroy call) */
   int32_t hub_chunk;     /* entries per piece of a long list, >= 1 */
   int64_t iter_cap;      /* loop-trip budget per wavefront; 0 = default of
                             65536 + 8 x (neighbour entries of its block);
