@@ -23,6 +23,7 @@ struct GraphDesc {
   uint32_t* hint;  // matched hint words, or null
   uint32_t hint_lg;  // log2 of vertices per hint word
   uint32_t flags;    // kWholeGraph: swept by one wavefront, no hub pieces
+  int64_t pieces;    // hub table build only: piece count, then fill cursor
 };
 constexpr uint32_t kWholeGraph = 1u;
 
@@ -80,11 +81,13 @@ struct BatchInfo {
 BatchInfo batch_info(const mm_batch* b);
 
 // Hub pieces of a batch (see hubs.hip): lists longer than hub_degree in
-// graphs without kWholeGraph, cut into pieces of `chunk` entries. On return
-// *table (device, hipMalloc'd, or null) holds *count pieces, those of graph g
-// at first[g] .. first[g+1]-1 (first: host, G+1 entries).
-hipError_t build_batch_hubs(const GraphDesc* descs_dev, const int64_t* vtx_dev, int32_t G, int64_t N,
-                            int64_t hub_degree, int64_t chunk, mmk::HubChunk** table,
-                            int64_t* count, int64_t* first, hipStream_t s);
+// graphs without kWholeGraph, cut into pieces of `chunk` entries. Counting
+// adds each graph's pieces to descs[g].pieces (zero on entry) and all of them
+// to the control block word at kHubOffset. Filling takes descs[g].pieces as
+// the first table slot of graph g and writes every piece (stream-ordered).
+hipError_t count_batch_hubs(GraphDesc* descs_dev, const int64_t* vtx_dev, int32_t G, int64_t N,
+                            int64_t hub_degree, int64_t chunk, uint8_t* ctrl, hipStream_t s);
+hipError_t fill_batch_hubs(GraphDesc* descs_dev, const int64_t* vtx_dev, int32_t G, int64_t N,
+                           int64_t hub_degree, int64_t chunk, mmk::HubChunk* table, hipStream_t s);
 
 }  // namespace mmb

@@ -24,6 +24,7 @@
 using namespace mmk;
 using mmi::fail;
 using mmi::kCtrlBytes;
+using mmi::kHubOffset;
 using mmi::kQueueOffset;
 using mmi::kStatsOffset;
 using mmi::round_up;
@@ -335,8 +336,8 @@ struct mm_batch {
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  mmk::HubChunk* chunks = nullptr;      // hub piece table (device, owned)
-  mmb::WorkItem* own_items = nullptr;   // item table when hub pieces exist (owned)
+  mmk::HubChunk* chunks = nullptr;  // hub piece table, inside `own`
+  void* own = nullptr;  // item and piece tables when hub pieces exist (device, owned)
 };
 
 namespace {
@@ -415,8 +416,20 @@ mm_status finish_create(std::vector<mmb::GraphDesc>& descs, const std::vector<in
     else
       HIP_TRY(mmb::validate_list(descs_dev, vtx_dev, G, N, f, s));
   }
+  // hub tier, first pass: pieces per graph, counted beside the validation so
+  // that a batch without long lists pays no further wait or allocation
+  bool hubs_possible = false;
+  if (t.hub_degree > 0)
+    for (int32_t g = 0; g < G && !hubs_possible; ++g)
+      hubs_possible = !(descs[g].flags & mmb::kWholeGraph) && descs[g].n > 0 &&
+                      (descs[g].m < 0 || descs[g].m > t.hub_degree);
+  if (hubs_possible)
+    HIP_TRY(mmb::count_batch_hubs(descs_dev, vtx_dev, G, N, t.hub_degree, t.hub_chunk, ws, s));
   uint32_t hf = 0;
+  unsigned long long n_pieces = 0;
   HIP_TRY(hipMemcpyAsync(&hf, f, sizeof(hf), hipMemcpyDeviceToHost, s));
+  if (hubs_possible)
+    HIP_TRY(hipMemcpyAsync(&n_pieces, ws + kHubOffset, sizeof(n_pieces), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));  // the host vectors are released after this
   if (hf) {
     HIP_TRY(hipMemsetAsync(ws, 0, kCtrlBytes, s));
@@ -428,31 +441,41 @@ mm_status finish_create(std::vector<mmb::GraphDesc>& descs, const std::vector<in
                 (hf & 2u) ? " offsets decrease;" : "",
                 (hf & 4u) ? " neighbour id outside its graph;" : "");
   }
-  // hub tier: pieces of long lists become work items of their own, after the
-  // blocks; the item table then lives in memory the handle owns
+  // second pass, only when pieces exist: they become work items of their own
+  // after the blocks, in one allocation the handle owns (item table, then
+  // piece table)
   mmk::HubChunk* chunks = nullptr;
-  int64_t n_chunks = 0;
-  mmb::WorkItem* own_items = nullptr;
-  if (t.hub_degree > 0 && N > 0) {
-    std::vector<int64_t> first((size_t)G + 1, 0);
-    hipError_t e = mmb::build_batch_hubs(descs_dev, vtx_dev, G, N, t.hub_degree, t.hub_chunk,
-                                         &chunks, &n_chunks, first.data(), s);
-    if (e != hipSuccess) return fail(MM_ERR_HIP, "building the hub table failed: %s", hipGetErrorString(e));
-    for (int32_t g = 0; g < G; ++g)
-      for (int64_t c = first[g]; c < first[g + 1]; c += 64) {
+  const int64_t n_chunks = (int64_t)n_pieces;
+  void* own = nullptr;
+  if (n_chunks > 0) {
+    HIP_TRY(hipMemcpyAsync(descs.data(), descs_dev, sizeof(mmb::GraphDesc) * G,
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    int64_t first = 0;
+    for (int32_t g = 0; g < G; ++g) {
+      const int64_t k = descs[g].pieces;
+      for (int64_t c = 0; c < k; c += 64) {
         mmb::WorkItem w;
         w.desc = g;
-        w.vb = c;
-        w.nv = -(int32_t)std::min<int64_t>(64, first[g + 1] - c);
+        w.vb = first + c;
+        w.nv = -(int32_t)std::min<int64_t>(64, k - c);
         items.push_back(w);
       }
-    if (n_chunks > 0) {
-      e = hipMalloc(&own_items, sizeof(mmb::WorkItem) * items.size());
-      if (e != hipSuccess) {
-        hipFree(chunks);
-        return fail(MM_ERR_OUT_OF_MEMORY, "hub item table: %s", hipGetErrorString(e));
-      }
-      items_dev = own_items;
+      descs[g].pieces = first;
+      first += k;
+    }
+    const size_t items_bytes = round_up(sizeof(mmb::WorkItem) * items.size(), 256);
+    hipError_t e = hipMallocAsync(&own, items_bytes + sizeof(mmk::HubChunk) * (size_t)n_chunks, s);
+    if (e != hipSuccess)
+      return fail(MM_ERR_OUT_OF_MEMORY, "hub item and piece tables: %s", hipGetErrorString(e));
+    items_dev = static_cast<mmb::WorkItem*>(own);
+    chunks = reinterpret_cast<mmk::HubChunk*>(static_cast<uint8_t*>(own) + items_bytes);
+    e = hipMemcpyAsync(descs_dev, descs.data(), sizeof(mmb::GraphDesc) * G, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = mmb::fill_batch_hubs(descs_dev, vtx_dev, G, N, t.hub_degree, t.hub_chunk, chunks, s);
+    if (e != hipSuccess) {
+      mmi::free_owned(own);
+      return fail(MM_ERR_HIP, "building the hub table failed: %s", hipGetErrorString(e));
     }
   }
   if (!items.empty()) {
@@ -460,8 +483,7 @@ mm_status finish_create(std::vector<mmb::GraphDesc>& descs, const std::vector<in
                                   hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);  // the host vector is released after this
     if (e != hipSuccess) {
-      if (chunks) hipFree(chunks);
-      if (own_items) hipFree(own_items);
+      mmi::free_owned(own);
       return fail(MM_ERR_HIP, "uploading the work items failed: %s", hipGetErrorString(e));
     }
   }
@@ -470,12 +492,11 @@ mm_status finish_create(std::vector<mmb::GraphDesc>& descs, const std::vector<in
   HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   mm_batch* b = new (std::nothrow) mm_batch();
   if (!b) {
-    if (chunks) hipFree(chunks);
-    if (own_items) hipFree(own_items);
+    mmi::free_owned(own);
     return fail(MM_ERR_OUT_OF_MEMORY, "host allocation of the batch handle failed");
   }
   b->chunks = chunks;
-  b->own_items = own_items;
+  b->own = own;
   if (flags & MM_CAPTURE) {
     hipError_t e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
@@ -664,8 +685,7 @@ int64_t mm_batch_items(mm_batch_handle b) { return b ? b->plan.n_items : -1; }
 void mm_batch_destroy(mm_batch_handle b) {
   if (!b) return;
   drop_graph(b);
-  if (b->chunks) hipFree(b->chunks);
-  if (b->own_items) hipFree(b->own_items);
+  mmi::free_owned(b->own);
   if (b->cap_stream) hipStreamDestroy(b->cap_stream);
   delete b;
 }

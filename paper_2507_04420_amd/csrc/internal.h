@@ -42,24 +42,30 @@ size_t relabel_bytes(int64_t n, int64_t m);
 hipError_t build_relabel(const void* off, int off64, const int32_t* nbr, int64_t n, int64_t m,
                          uint8_t* region, RelabelView* view, hipStream_t s);
 
-// The hub tier's table (see hubs.hip); allocated here, freed with hipFree by
-// the handle's owner. *count = 0 and *table = null when no list is long enough.
+// The hub tier's table (see hubs.hip), allocated stream-ordered on s and
+// released with free_owned by the handle's owner; *count = 0 and *table = null
+// when no list is long enough. Uses two words of the control block at ctrl.
 }  // namespace mmi
 namespace mmk {
 struct HubChunk;
 }
 namespace mmi {
 hipError_t build_hub_chunks(const void* off, int off64, int64_t n, int64_t hub_degree,
-                            int64_t chunk, mmk::HubChunk** table, int64_t* count, hipStream_t s);
+                            int64_t chunk, uint8_t* ctrl, mmk::HubChunk** table, int64_t* count,
+                            hipStream_t s);
+// Stream-ordered release of memory a handle owns (no wait for the device).
+void free_owned(void* p);
 
 // Copies the raw device counters (sweep.h order) into the ABI struct.
 void stats_from_counters(const unsigned long long* c, mm_stats* out);
 
 // Control block at the start of every workspace: error word at 0, counters
-// at kStatsOffset, a work-queue counter at kQueueOffset, the six counters of
-// the device check at kCheckOffset.
+// at kStatsOffset, the hub table build's piece count and cursor at
+// kHubOffset, a work-queue counter at kQueueOffset, the six counters of the
+// device check at kCheckOffset.
 constexpr size_t kCtrlBytes = 4096;
 constexpr size_t kStatsOffset = 256;
+constexpr size_t kHubOffset = 512;
 constexpr size_t kQueueOffset = 1024;
 constexpr size_t kCheckOffset = 2048;
 constexpr int kStatWords = 32;  // 64-bit counters at kStatsOffset

@@ -574,8 +574,9 @@ mm_status mm_create(const void* offsets, mm_offset_type off_type, const int32_t*
   if (t.hub_degree > 0 && m > t.hub_degree) {
     // the table is built on the lists the sweep reads (relabelled or given)
     hipError_t e = g->relabel
-        ? mmi::build_hub_chunks(g->rl.off, 1, n, t.hub_degree, t.hub_chunk, &g->chunks, &g->n_chunks, s)
-        : mmi::build_hub_chunks(offsets, off_type == MM_OFF_I64, n, t.hub_degree, t.hub_chunk,
+        ? mmi::build_hub_chunks(g->rl.off, 1, n, t.hub_degree, t.hub_chunk, ws, &g->chunks,
+                                &g->n_chunks, s)
+        : mmi::build_hub_chunks(offsets, off_type == MM_OFF_I64, n, t.hub_degree, t.hub_chunk, ws,
                                 &g->chunks, &g->n_chunks, s);
     if (e != hipSuccess) {
       delete g;
@@ -588,7 +589,7 @@ mm_status mm_create(const void* offsets, mm_offset_type off_type, const int32_t*
   if (flags & MM_TIMING) {
     g->timing = new (std::nothrow) TimingRing();
     if (!g->timing) {
-      if (g->chunks) hipFree(g->chunks);
+      mmi::free_owned(g->chunks);
       delete g;
       return fail(MM_ERR_OUT_OF_MEMORY, "host allocation of the timing ring failed");
     }
@@ -596,7 +597,7 @@ mm_status mm_create(const void* offsets, mm_offset_type off_type, const int32_t*
     if (e != hipSuccess) {
       g->timing->destroy();
       delete g->timing;
-      if (g->chunks) hipFree(g->chunks);
+      mmi::free_owned(g->chunks);
       delete g;
       return fail(MM_ERR_HIP, "hipEventCreate failed: %s", hipGetErrorString(e));
     }
@@ -681,7 +682,7 @@ mm_status mm_get_timing(mm_handle g, int64_t* count, double* total_ms, double* m
 
 void mm_destroy(mm_handle g) {
   if (!g) return;
-  if (g->chunks) hipFree(g->chunks);
+  mmi::free_owned(g->chunks);
   if (g->timing) {
     g->timing->destroy();
     delete g->timing;

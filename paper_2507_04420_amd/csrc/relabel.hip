@@ -133,12 +133,18 @@ hipError_t build_typed(const OffT* off, const int32_t* nbr, int64_t n, int64_t* 
     e = rocprim::exclusive_scan(nullptr, scan_bytes, rdeg, roff, (int64_t)0, (size_t)(n + 1),
                                 rocprim::plus<int64_t>(), s);
   tmp_bytes = sort_bytes > scan_bytes ? sort_bytes : scan_bytes;
-  if (e == hipSuccess) e = hipMalloc(&keys, sizeof(uint32_t) * (size_t)n);
-  if (e == hipSuccess) e = hipMalloc(&keys_sorted, sizeof(uint32_t) * (size_t)n);
-  if (e == hipSuccess) e = hipMalloc(&inv, sizeof(int32_t) * (size_t)n);
-  if (e == hipSuccess) e = hipMalloc(&rdeg, sizeof(int64_t) * (size_t)(n + 1));
-  if (e == hipSuccess) e = hipMalloc(&tmp, tmp_bytes > 0 ? tmp_bytes : 1);
-  if (e == hipSuccess) e = hipMalloc(&iso, sizeof(unsigned long long));
+  if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&keys),
+                                          sizeof(uint32_t) * (size_t)n, s);
+  if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&keys_sorted),
+                                          sizeof(uint32_t) * (size_t)n, s);
+  if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&inv),
+                                          sizeof(int32_t) * (size_t)n, s);
+  if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&rdeg),
+                                          sizeof(int64_t) * (size_t)(n + 1), s);
+  if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&tmp),
+                                          tmp_bytes > 0 ? tmp_bytes : 1, s);
+  if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&iso),
+                                          sizeof(unsigned long long), s);
   if (e == hipSuccess) e = hipMemsetAsync(iso, 0, sizeof(unsigned long long), s);
   if (e == hipSuccess) {
     hipLaunchKernelGGL((degree_keys_kernel<OffT>), dim3(blocks_for(n)), dim3(256), 0, s, off, n, keys);
@@ -168,12 +174,12 @@ hipError_t build_typed(const OffT* off, const int32_t* nbr, int64_t n, int64_t* 
   if (e == hipSuccess) e = hipMemcpyAsync(&h_iso, iso, sizeof(h_iso), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   *n_isolated = (int64_t)h_iso;
-  hipFree(keys);
-  hipFree(keys_sorted);
-  hipFree(inv);
-  hipFree(rdeg);
-  hipFree(tmp);
-  hipFree(iso);
+  if (keys) hipFreeAsync(keys, s);
+  if (keys_sorted) hipFreeAsync(keys_sorted, s);
+  if (inv) hipFreeAsync(inv, s);
+  if (rdeg) hipFreeAsync(rdeg, s);
+  if (tmp) hipFreeAsync(tmp, s);
+  if (iso) hipFreeAsync(iso, s);
   return e;
 }
 
