@@ -22,7 +22,10 @@
  *    them, and they must outlive the handle. Workspaces and outputs are
  *    caller-owned device memory. mm_run and mm_batch_run allocate nothing;
  *    the create calls may (tuning.relabel: temporary buffers;
- *    tuning.hub_degree: the hub piece table, kept until destroy).
+ *    tuning.hub_degree: the hub piece table, kept until destroy). Those
+ *    allocations are stream-ordered (hipMallocAsync on the create call's
+ *    stream, hipFreeAsync at destroy), so create and destroy never wait for
+ *    the whole device; destroy only after the handle's runs have finished.
  *
  * Graph format (Section II-A): CSR with `offsets` of n+1 entries (int32 or
  * int64, non-decreasing, offsets[0] = 0, offsets[n] = m) and `neighbors` of m
@@ -135,12 +138,13 @@ typedef struct {
                             device memory for the sort */
   int32_t hub_degree;    /* lists longer than this are not swept by their block's
                             lane but cut into pieces of hub_chunk entries, each swept
-                            by its own lane: in a second launch right after the
-                            first (single graphs), or as work items queued after the
-                            blocks (batches; not for graphs swept whole by one
-                            wavefront). 0 disables. The create call then allocates
-                            the piece table itself (device memory, freed by the
-                            destroy call) */
+                            by its own lane: by wavefronts launched after the
+                            blocks' (single graphs, same launch), or as work items
+                            queued after the blocks (batches; not for graphs swept
+                            whole by one wavefront). 0 disables. The create call
+                            counts the pieces (one kernel and one wait) and, if
+                            any exist, allocates the piece table itself (device
+                            memory, freed by the destroy call) */
   int32_t hub_chunk;     /* entries per piece of a long list, >= 1 */
   int64_t iter_cap;      /* loop-trip budget per wavefront; 0 = default of
                             65536 + 8 x (neighbour entries of its block);

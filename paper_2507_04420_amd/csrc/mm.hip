@@ -188,16 +188,30 @@ __global__ void validate_kernel(const OffT* __restrict__ off, const int32_t* __r
   if (f) atomicOr(flags, f);
 }
 
-// One graph: wavefront w sweeps sources [v_begin + w * wave_vertices, ...).
+// One graph: wavefront w < main_waves sweeps sources [v_begin + w *
+// wave_vertices, ...); the wavefronts after them (dispatched last) take the
+// hub tier's pieces, 64 to a wavefront, as one launch with the main pass.
 template <typename OffT, class Layout, bool HINT, bool LAZY, bool STATS>
 __global__ __launch_bounds__(256) void sweep_kernel(SweepParams p, const OffT* __restrict__ off,
                                                    const int32_t* __restrict__ nbr, int64_t n,
-                                                   int64_t v_begin, Layout L,
+                                                   int64_t v_begin, int64_t main_waves,
+                                                   int64_t n_chunks, Layout L,
                                                    unsigned long long* stats) {
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const int64_t vb = v_begin + wave * p.wave_vertices;
-  if (vb >= n) return;
-  const int64_t nv = (n - vb < p.wave_vertices) ? (n - vb) : p.wave_vertices;
+  int64_t vb, nv;
+  if (wave < main_waves) {
+    vb = v_begin + wave * p.wave_vertices;
+    if (vb >= n) return;
+    nv = (n - vb < p.wave_vertices) ? (n - vb) : p.wave_vertices;
+    p.chunks = nullptr;
+  } else {
+    vb = (wave - main_waves) * 64;
+    if (vb >= n_chunks) return;
+    nv = (n_chunks - vb < 64) ? (n_chunks - vb) : 64;
+    p.wave_vertices = 64;
+    p.disperse = 0;
+    p.hub_degree = 0;
+  }
   __shared__ QSlot queues[4][kQueue];  // one ring per wavefront (wg_size <= 256)
   Counters<STATS> cnt;
   sweep_block<OffT, Layout, HINT, LAZY, STATS>(p, off, nbr, L, vb, nv, queues[threadIdx.x >> 6],
@@ -310,31 +324,22 @@ hipError_t launch_sweep(const mm_graph* g, const Layout& L, hipStream_t s) {
                                : static_cast<const OffT*>(g->off);
   const int32_t* nbr = g->relabel ? g->rl.nbr : g->nbr;
   const int64_t waves = (g->n - v_begin + p.wave_vertices - 1) / p.wave_vertices;
+  // the hub tier's pieces: 64 to a wavefront, after the main pass's waves
+  const int64_t chunk_waves = (g->n_chunks + 63) / 64;
+  SweepParams pl = p;
+  pl.chunks = g->chunks;
   const int wpb = g->tun.wg_size / 64;
-  const int64_t blocks = (waves + wpb - 1) / wpb;
+  const int64_t blocks = (waves + chunk_waves + wpb - 1) / wpb;
   if (blocks == 0) return hipSuccess;
   if (g->timing) {
     hipError_t e = hipEventRecord(g->timing->before(), s);
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL((sweep_kernel<OffT, Layout, HINT, LAZY, STATS>), dim3((unsigned)blocks),
-                     dim3(g->tun.wg_size), 0, s, p, off, nbr, g->n, v_begin, L, stats);
+                     dim3(g->tun.wg_size), 0, s, pl, off, nbr, g->n, v_begin, waves, g->n_chunks,
+                     L, stats);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (g->n_chunks > 0) {
-    // the hub tier's chunk pass: 64 pieces of long lists per wavefront
-    SweepParams pc = p;
-    pc.wave_vertices = 64;
-    pc.disperse = 0;
-    pc.hub_degree = 0;
-    pc.chunks = g->chunks;
-    const int64_t cblocks = ((g->n_chunks + 63) / 64 + wpb - 1) / wpb;
-    hipLaunchKernelGGL((sweep_kernel<OffT, Layout, HINT, false, STATS>), dim3((unsigned)cblocks),
-                       dim3(g->tun.wg_size), 0, s, pc, off, nbr, g->n_chunks, (int64_t)0, L,
-                       stats);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
   if (g->timing) {
     e = hipEventRecord(g->timing->after(), s);
     ++g->timing->recorded;
