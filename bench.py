@@ -36,7 +36,7 @@ METRIC = "GEdges/s single-pass MM + % HBM roofline; batched vs per-graph graphs/
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_kernel_traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2507_04420_amd", "csrc", f)
-                  for f in ("protocol.h", "sweep.h", "mm.hip", "relabel.hip")]
+                  for f in ("protocol.h", "sweep.h", "mm.hip", "relabel.hip", "hubs.hip")]
 
 
 def kernel_sources_sha256() -> str:
@@ -469,6 +469,7 @@ def main():
     # initialisation n.
     b_sweep = w * (n + 1) + 5 * t_seq + n + 4 * n
     b_pass = b_sweep + n
+    csr_bytes = w * (n + 1) + 4 * m
     sweep_s = sweep["mean_ms"] / 1e3
     achieved = b_sweep / sweep_s / 1e9 if sweep_s > 0 else 0.0
     value = m / (ms_per_step / 1e3) / 1e9
@@ -504,6 +505,11 @@ def main():
             "sweep_ms": round(sweep["mean_ms"], 5),
             "pass_alg_bytes": int(b_pass),
             "pass_frac": round(b_pass / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 5),
+            # the edge rate a pass that streams the whole CSR once (offsets and
+            # ids, w(n+1) + 4m bytes) would reach at the peak, and the value as
+            # a fraction of it: the roofline of a method without early exit
+            "csr_stream_gedges_per_s": round(m / (csr_bytes / (HBM_PEAK_GBS * 1e9)) / 1e9, 1),
+            "csr_stream_frac": round(value / (m / (csr_bytes / (HBM_PEAK_GBS * 1e9)) / 1e9), 5),
         },
         "cpu_baseline": {
             "value": round(m / t_sgmm / 1e9, 4),
