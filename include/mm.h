@@ -98,6 +98,9 @@ typedef enum {
   MM_PROTOCOL_TWO_PHASE = 1
 } mm_protocol;
 
+/* Largest graph whose states a wavefront keeps in LDS (tuning.whole_graph_lds). */
+#define MM_LDS_WHOLE_MAX 16384
+
 /* Launch and layout parameters. None of them changes what a correct result
    is; they change only speed. Fill with mm_default_tuning() first. */
 typedef struct {
@@ -146,6 +149,15 @@ typedef struct {
                             any exist, allocates the piece table itself (device
                             memory, freed by the destroy call) */
   int32_t hub_chunk;     /* entries per piece of a long list, >= 1 */
+  int32_t whole_graph_lds; /* 1: a graph swept whole by one wavefront (see
+                            whole_graph_vertices) with at most MM_LDS_WHOLE_MAX
+                            vertices keeps its states in that wavefront's LDS,
+                            since no other wavefront reads them: 2 bits per
+                            vertex, with the two-phase protocol whatever the
+                            layout and protocol fields say; the mates are
+                            written to the output as pairs are committed. Not
+                            with relabel. 0: states in device memory, as for
+                            every other graph */
   int64_t iter_cap;      /* loop-trip budget per wavefront; 0 = default of
                             65536 + 8 x (neighbour entries of its block);
                             exceeding it raises MM_ERR_NO_PROGRESS */
@@ -287,7 +299,8 @@ mm_status mm_batch_sync(mm_batch_handle h, void* stream);
 /* As mm_get_stats, for a batch created with MM_STATS. */
 mm_status mm_batch_get_stats(mm_batch_handle h, void* stream, mm_stats* out);
 
-/* Number of work items (wavefront blocks) of the batch; -1 for a null handle. */
+/* Number of work items of the batch (wavefront blocks, hub pieces in runs of
+   64, and one per graph swept whole); -1 for a null handle. */
 int64_t mm_batch_items(mm_batch_handle h);
 
 /* Frees the host-side handle and any captured graph. */

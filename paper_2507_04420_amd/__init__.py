@@ -46,6 +46,7 @@ class Tuning:
     relabel: int = 0
     hub_degree: int = 4096
     hub_chunk: int = 256
+    whole_graph_lds: int = 1
     iter_cap: int = 0
 
     @classmethod

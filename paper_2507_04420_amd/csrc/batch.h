@@ -26,6 +26,7 @@ struct GraphDesc {
   int64_t pieces;    // hub table build only: piece count, then fill cursor
 };
 constexpr uint32_t kWholeGraph = 1u;
+constexpr uint32_t kWholeLds = 2u;  // with kWholeGraph: states in the wavefront's LDS (whole.h)
 
 // One wavefront block: sources vb .. vb+nv-1 of graph `desc`; or, with
 // nv < 0, the hub pieces vb .. vb-nv-1 of the piece table (all of graph desc).
@@ -52,6 +53,12 @@ struct BatchPlan {
   int64_t st_words;
   uint32_t* hint_base;
   int64_t hint_words;
+  // graphs kept in LDS (kWholeLds): one item each, swept by a kernel of
+  // their own before the persistent sweep
+  const WorkItem* lds_items;
+  int64_t n_lds;
+  int32_t lds_words;  // LDS words per wavefront (0: no such graph)
+  int lds_wg;         // threads per workgroup of that kernel
 };
 
 // Enqueues one pass: fills, queue reset, persistent sweep, output fix-up.

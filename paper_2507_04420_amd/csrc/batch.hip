@@ -20,6 +20,7 @@
 #include "internal.h"
 #include "mm.h"
 #include "sweep.h"
+#include "whole.h"
 
 using namespace mmk;
 using mmi::fail;
@@ -176,6 +177,28 @@ __global__ __launch_bounds__(256) void batch_sweep_kernel(SweepParams p,
   if (STATS) cnt.flush(stats);
 }
 
+// Graphs flagged kWholeLds, one wavefront each, their states in LDS
+// (whole.h): lds_words words of the dynamic LDS per wavefront. A kernel of its
+// own, so that the persistent sweep keeps its register budget.
+template <bool STATS>
+__global__ __launch_bounds__(256) void batch_whole_lds_kernel(SweepParams p,
+                                                             const GraphDesc* __restrict__ descs,
+                                                             const WorkItem* __restrict__ items,
+                                                             int64_t n_items, int32_t* mate,
+                                                             unsigned long long* stats,
+                                                             int32_t lds_words) {
+  __shared__ QSlot queues[4][kQueue];
+  extern __shared__ uint32_t whole_st[];
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (wave >= n_items) return;
+  Counters<STATS> cnt;
+  const GraphDesc d = descs[items[wave].desc];
+  sweep_whole_lds<int64_t, STATS>(p, d.off, d.nbr, d.n, mate + d.v0,
+                                  whole_st + (int64_t)(threadIdx.x >> 6) * lds_words,
+                                  queues[threadIdx.x >> 6], cnt);
+  if (STATS) cnt.flush(stats);
+}
+
 int grid_for(int64_t words) {
   int64_t blocks = (words + 1023) / 1024;
   if (blocks < 1) blocks = 1;
@@ -219,15 +242,35 @@ void fill(uint32_t* p, int64_t words, uint32_t v, hipStream_t s) {
 }
 
 template <bool STATS>
+hipError_t launch_whole_lds(const BatchPlan& bp, hipStream_t s) {
+  if (bp.n_lds == 0) return hipSuccess;
+  const int wpb = bp.lds_wg / 64;
+  const size_t shmem = (size_t)wpb * (size_t)bp.lds_words * 4;
+  const int64_t blocks = (bp.n_lds + wpb - 1) / wpb;
+  hipLaunchKernelGGL((batch_whole_lds_kernel<STATS>), dim3((unsigned)blocks), dim3(bp.lds_wg),
+                     shmem, s, bp.params, bp.descs, bp.lds_items, bp.n_lds, bp.mate, bp.stats,
+                     bp.lds_words);
+  return hipGetLastError();
+}
+
+template <bool STATS>
 hipError_t enqueue_typed(const BatchPlan& bp, hipStream_t s) {
   uint32_t* mate_w = reinterpret_cast<uint32_t*>(bp.mate);
   if (bp.hint) fill(bp.hint_base, bp.hint_words, 0u, s);
   hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(64), 0, s, bp.queue);
   const bool two = bp.protocol == MM_PROTOCOL_TWO_PHASE;
-  hipError_t e;
+  // init (Algorithm 1, L1-4) for every graph; the graphs kept in LDS then
+  // overwrite their own mates, ahead of the persistent sweep of the rest
+  if (bp.layout == MM_LAYOUT_U32) {
+    fill(mate_w, bp.N, two ? LayoutU32<true>::kAcc : LayoutU32<false>::kAcc, s);
+  } else {
+    fill(bp.st_base, bp.st_words, 0u, s);
+    if (!bp.lazy) fill(mate_w, bp.N, 0xffffffffu, s);
+  }
+  hipError_t e = launch_whole_lds<STATS>(bp, s);
+  if (e != hipSuccess) return e;
   if (bp.layout == MM_LAYOUT_U32) {
     if (two) {
-      fill(mate_w, bp.N, LayoutU32<true>::kAcc, s);
       e = launch_flags<LayoutU32<true>, STATS>(bp, s);
       if (e == hipSuccess && !bp.lazy) {
         hipLaunchKernelGGL(replace_words_kernel, dim3(grid_for(bp.N)), dim3(256), 0, s, mate_w,
@@ -236,11 +279,8 @@ hipError_t enqueue_typed(const BatchPlan& bp, hipStream_t s) {
       }
       return e;
     }
-    fill(mate_w, bp.N, LayoutU32<false>::kAcc, s);
     return launch_flags<LayoutU32<false>, STATS>(bp, s);
   }
-  fill(bp.st_base, bp.st_words, 0u, s);
-  if (!bp.lazy) fill(mate_w, bp.N, 0xffffffffu, s);
   if (bp.layout == MM_LAYOUT_U2)
     return two ? launch_flags<LayoutPacked<2, true>, STATS>(bp, s)
                : launch_flags<LayoutPacked<2, false>, STATS>(bp, s);
@@ -383,12 +423,21 @@ mm_status finish_create(std::vector<mmb::GraphDesc>& descs, const std::vector<in
   int64_t st_w = 0, hint_w = 0;
   std::vector<mmb::WorkItem> items;
   items.reserve((size_t)lay.n_items);
+  // graphs swept whole keep their states in LDS when they fit (whole.h); the
+  // choice depends on the graph and the tuning only, never on the rest of
+  // the batch
+  int64_t lds_words = 0;
+  std::vector<mmb::WorkItem> lds_items;  // placed after all other items
   for (int32_t g = 0; g < G; ++g) {
     mmb::GraphDesc& d = descs[g];
     d.st = t.layout == MM_LAYOUT_U32 ? nullptr : st_base + st_w;
     d.hint = t.hint ? hint_base + hint_w : nullptr;
     d.hint_lg = mmk::hint_lg(t.hint);
     d.flags = d.n <= t.whole_graph_vertices ? mmb::kWholeGraph : 0u;
+    if ((d.flags & mmb::kWholeGraph) && t.whole_graph_lds && d.n > 0 && d.n <= MM_LDS_WHOLE_MAX) {
+      d.flags |= mmb::kWholeLds;
+      lds_words = std::max(lds_words, mmk::whole_lds_words(d.n));
+    }
     st_w += mmb::state_words_for(d.n, t.layout);
     hint_w += mmk::hint_words(d.n, t.hint);
     // a small graph is one item (one wavefront), a larger one an item per block
@@ -398,7 +447,7 @@ mm_status finish_create(std::vector<mmb::GraphDesc>& descs, const std::vector<in
       w.desc = g;
       w.vb = vb;
       w.nv = (int32_t)std::min<int64_t>(step, d.n - vb);
-      items.push_back(w);
+      (d.flags & mmb::kWholeLds ? lds_items : items).push_back(w);
     }
   }
   auto* descs_dev = reinterpret_cast<mmb::GraphDesc*>(ws + lay.descs);
@@ -464,7 +513,8 @@ mm_status finish_create(std::vector<mmb::GraphDesc>& descs, const std::vector<in
       descs[g].pieces = first;
       first += k;
     }
-    const size_t items_bytes = round_up(sizeof(mmb::WorkItem) * items.size(), 256);
+    const size_t items_bytes =
+        round_up(sizeof(mmb::WorkItem) * (items.size() + lds_items.size()), 256);
     hipError_t e = hipMallocAsync(&own, items_bytes + sizeof(mmk::HubChunk) * (size_t)n_chunks, s);
     if (e != hipSuccess)
       return fail(MM_ERR_OUT_OF_MEMORY, "hub item and piece tables: %s", hipGetErrorString(e));
@@ -478,6 +528,8 @@ mm_status finish_create(std::vector<mmb::GraphDesc>& descs, const std::vector<in
       return fail(MM_ERR_HIP, "building the hub table failed: %s", hipGetErrorString(e));
     }
   }
+  const int64_t n_main = (int64_t)items.size();
+  items.insert(items.end(), lds_items.begin(), lds_items.end());
   if (!items.empty()) {
     hipError_t e = hipMemcpyAsync(items_dev, items.data(), sizeof(mmb::WorkItem) * items.size(),
                                   hipMemcpyHostToDevice, s);
@@ -524,7 +576,9 @@ mm_status finish_create(std::vector<mmb::GraphDesc>& descs, const std::vector<in
   p.params.err = f;
   p.descs = descs_dev;
   p.items = items_dev;
-  p.n_items = (int64_t)items.size();
+  p.n_items = n_main;
+  p.lds_items = items_dev + n_main;
+  p.n_lds = (int64_t)lds_items.size();
   p.queue = reinterpret_cast<uint32_t*>(ws + kQueueOffset);
   p.stats = reinterpret_cast<unsigned long long*>(ws + kStatsOffset);
   p.layout = t.layout;
@@ -540,6 +594,23 @@ mm_status finish_create(std::vector<mmb::GraphDesc>& descs, const std::vector<in
   p.st_base = st_base;
   p.st_words = lay.st_words;
   p.hint_base = hint_base;
+  p.lds_words = (int32_t)((lds_words + 3) / 4 * 4);  // 16-byte aligned regions
+  p.lds_wg = t.wg_size;
+  if (p.lds_words > 0) {
+    // fewer wavefronts per workgroup if their LDS regions and the queues do
+    // not fit one workgroup's LDS (results do not depend on the group size)
+    int max_lds = 0;
+    HIP_TRY(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    const int64_t fixed = (int64_t)sizeof(mmk::QSlot) * mmk::kQueue * 4;
+    p.lds_wg = t.wg_size;
+    while (p.lds_wg > 64 && fixed + (int64_t)(p.lds_wg / 64) * p.lds_words * 4 > max_lds)
+      p.lds_wg -= 64;
+    if (fixed + (int64_t)p.lds_words * 4 > max_lds) {
+      mm_batch_destroy(b);
+      return fail(MM_ERR_UNSUPPORTED, "LDS per workgroup (%d bytes) too small for whole-graph "
+                  "states; set tuning.whole_graph_lds = 0", max_lds);
+    }
+  }
   p.hint_words = lay.hint_words;
   *out = b;
   return MM_OK;
@@ -626,7 +697,7 @@ mm_status mm_batch_create_list(const int64_t* const* offsets, const int32_t* con
 mm_status mm_batch_run(mm_batch_handle b, void* stream, int32_t* match_out) {
   if (!b) return fail(MM_ERR_INVALID_ARG, "batch handle is null");
   if (!match_out && b->N > 0) return fail(MM_ERR_INVALID_ARG, "match_out is null");
-  if (b->plan.n_items == 0) return MM_OK;
+  if (b->plan.n_items + b->plan.n_lds == 0) return MM_OK;
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (match_out != b->bound_mate) {  // a captured pass is tied to its output
     b->plan.mate = match_out;
@@ -680,7 +751,7 @@ mm_status mm_batch_get_stats(mm_batch_handle b, void* stream, mm_stats* out) {
   return MM_OK;
 }
 
-int64_t mm_batch_items(mm_batch_handle b) { return b ? b->plan.n_items : -1; }
+int64_t mm_batch_items(mm_batch_handle b) { return b ? b->plan.n_items + b->plan.n_lds : -1; }
 
 void mm_batch_destroy(mm_batch_handle b) {
   if (!b) return;

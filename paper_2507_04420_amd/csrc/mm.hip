@@ -14,6 +14,7 @@
 #include "internal.h"
 #include "mm.h"
 #include "sweep.h"
+#include "whole.h"
 
 using namespace mmk;
 using mmi::fail;
@@ -66,6 +67,8 @@ mm_status check_tuning(const mm_tuning& t) {
   if (t.hub_degree > 0 && t.hub_chunk < 1)
     return fail(MM_ERR_INVALID_ARG, "tuning.hub_chunk must be >= 1 when hub_degree > 0");
   if (t.iter_cap < 0) return fail(MM_ERR_INVALID_ARG, "tuning.iter_cap must be >= 0");
+  if (t.whole_graph_lds != 0 && t.whole_graph_lds != 1)
+    return fail(MM_ERR_INVALID_ARG, "tuning.whole_graph_lds must be 0 or 1");
   return MM_OK;
 }
 
@@ -219,6 +222,19 @@ __global__ __launch_bounds__(256) void sweep_kernel(SweepParams p, const OffT* _
   if (STATS) cnt.flush(stats);
 }
 
+// A graph swept whole by one wavefront, its states in that wavefront's LDS
+// (dynamic, whole_lds_words(n) words).
+template <typename OffT, bool STATS>
+__global__ __launch_bounds__(64) void whole_lds_kernel(SweepParams p, const OffT* __restrict__ off,
+                                                       const int32_t* __restrict__ nbr, int64_t n,
+                                                       int32_t* mate, unsigned long long* stats) {
+  __shared__ QSlot q[kQueue];
+  extern __shared__ uint32_t st[];
+  Counters<STATS> cnt;
+  sweep_whole_lds<OffT, STATS>(p, off, nbr, n, mate, st, q, cnt);
+  if (STATS) cnt.flush(stats);
+}
+
 // ---------------------------------------------------------------- helpers
 
 int grid_for(int64_t words) {
@@ -315,10 +331,40 @@ SweepParams make_params(const mm_graph* g) {
   return p;
 }
 
+// Whether the sweep keeps the states in LDS (whole.h): a graph swept whole,
+// small enough, not relabelled. The same rule as for batch members.
+bool whole_in_lds(const mm_graph* g) {
+  return g->tun.whole_graph_lds && !g->relabel && g->n > 0 && g->n <= g->tun.whole_graph_vertices &&
+         g->n <= MM_LDS_WHOLE_MAX;
+}
+
+template <typename OffT, bool STATS>
+hipError_t launch_whole_lds(const mm_graph* g, const SweepParams& p, int32_t* mate,
+                            unsigned long long* stats, hipStream_t s) {
+  const size_t shmem = sizeof(uint32_t) * (size_t)whole_lds_words(g->n);
+  hipLaunchKernelGGL((whole_lds_kernel<OffT, STATS>), dim3(1), dim3(64), shmem, s, p,
+                     static_cast<const OffT*>(g->off), g->nbr, g->n, mate, stats);
+  return hipGetLastError();
+}
+
 template <typename OffT, class Layout, bool HINT, bool LAZY, bool STATS>
 hipError_t launch_sweep(const mm_graph* g, const Layout& L, hipStream_t s) {
   const SweepParams p = make_params(g);
   unsigned long long* stats = reinterpret_cast<unsigned long long*>(g->ws + kStatsOffset);
+  if constexpr (!Layout::kRelabelled) {
+    if (whole_in_lds(g)) {
+      if (g->timing) {
+        hipError_t e = hipEventRecord(g->timing->before(), s);
+        if (e != hipSuccess) return e;
+      }
+      hipError_t e = launch_whole_lds<OffT, STATS>(g, p, L.mate, stats, s);
+      if (e == hipSuccess && g->timing) {
+        e = hipEventRecord(g->timing->after(), s);
+        ++g->timing->recorded;
+      }
+      return e;
+    }
+  }
   const int64_t v_begin = sweep_begin(g);
   const OffT* off = g->relabel ? reinterpret_cast<const OffT*>(g->rl.off)
                                : static_cast<const OffT*>(g->off);
@@ -475,6 +521,7 @@ void mm_default_tuning(mm_tuning* t) {
   t->whole_graph_vertices = 16384;
   t->hub_degree = 4096;
   t->hub_chunk = 256;
+  t->whole_graph_lds = 1;
   t->iter_cap = 0;
 }
 
@@ -576,7 +623,8 @@ mm_status mm_create(const void* offsets, mm_offset_type off_type, const int32_t*
   // Lazy output is only sound when every edge is in both endpoints' lists.
   g->lazy = t.lazy_init && (flags & MM_SYMMETRIC) && !t.relabel &&
             !(t.layout == MM_LAYOUT_U32 && t.protocol == MM_PROTOCOL_CAS);
-  if (t.hub_degree > 0 && m > t.hub_degree) {
+  // a graph swept whole by one wavefront gets no hub pieces (as in batches)
+  if (t.hub_degree > 0 && m > t.hub_degree && n > t.whole_graph_vertices) {
     // the table is built on the lists the sweep reads (relabelled or given)
     hipError_t e = g->relabel
         ? mmi::build_hub_chunks(g->rl.off, 1, n, t.hub_degree, t.hub_chunk, ws, &g->chunks,

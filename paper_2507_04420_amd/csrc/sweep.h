@@ -41,6 +41,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "protocol.h"
 
 namespace mmk {
@@ -154,8 +156,10 @@ constexpr int kQueue = 128;  // ring entries per wavefront (power of two)
 
 // Loads of offsets and neighbour ids: non-temporal when streaming, so that
 // these once-read lines leave L2 before the state lines that are read again.
-template <typename T>
-__device__ __forceinline__ T ld_stream(const T* p, bool nt) {
+// P: a pointer, generic or to global memory (address space 1).
+template <typename P>
+__device__ __forceinline__ auto ld_stream(P p, bool nt) ->
+    typename std::remove_cv<typename std::remove_reference<decltype(p[0] + 0)>::type>::type {
   return nt ? __builtin_nontemporal_load(p) : *p;
 }
 
@@ -170,9 +174,12 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
 // HINT: skip matched neighbours by the matched hint (a bit or byte per vertex) instead of the
 // state word.
 // q: this wavefront's LDS ring of kQueue slots.
-template <typename OffT, class Layout, bool HINT, bool LAZY, bool STATS>
-__device__ __forceinline__ void sweep_block(const SweepParams& a, const OffT* __restrict__ off,
-                                            const int32_t* __restrict__ nbr, const Layout& L,
+// OffP / NbrP: the pointer types of off and nbr (generic by default; a caller
+// that knows the graph is in device memory may pass global pointers).
+template <typename OffT, class Layout, bool HINT, bool LAZY, bool STATS,
+          class OffP = const OffT*, class NbrP = const int32_t*>
+__device__ __forceinline__ void sweep_block(const SweepParams& a, OffP __restrict__ off,
+                                            NbrP __restrict__ nbr, const Layout& L,
                                             int64_t vb, int64_t nv, QSlot* q,
                                             Counters<STATS>& cnt) {
   const int lane = (int)(threadIdx.x & 63);
@@ -269,13 +276,8 @@ __device__ __forceinline__ void sweep_block(const SweepParams& a, const OffT* __
     if (w == x) phase = P_IDLE; else advance();
   };
 
-#pragma unroll 1
-  while (true) {
-    // ---------------- consume the results of last trip's operations
-    // One wait for everything issued on the previous trip (s_waitcnt vmcnt(0);
-    // expcnt and lgkmcnt left at their maxima), so that no issue branch below
-    // waits for a register written on an earlier trip.
-    __builtin_amdgcn_s_waitcnt(0x0f70);
+  // Consumes the result of the operation this lane issued last.
+  auto consume = [&]() {
     switch (phase) {
       case P_IDS: {
         const int64_t rem = e - i;
@@ -382,6 +384,51 @@ __device__ __forceinline__ void sweep_block(const SweepParams& a, const OffT* __
       default:
         break;
     }
+  };
+  // Issues this lane's next operation: one per lane and phase.
+  auto issue = [&]() {
+    switch (phase) {
+      case P_IDS:
+#pragma unroll
+        for (int j = 0; j < kMaxW; ++j)
+          if (j < W) ids[j] = (i + j < e) ? ld_stream(nbr + i + j, nt) : (int32_t)x;
+        break;
+      case P_STS:
+#pragma unroll
+        for (int j = 0; j < kMaxW; ++j)
+          if (j < nids && (int64_t)ids[j] != x) rw[j] = filter_word(ids[j]);
+        break;
+      case P_RES:
+        if (STATS) cnt.add(S_RES_ATT, 1);
+        res_w = L.reserve(u);
+        break;
+      case P_CHK:
+        chk_u = L.word_coherent(u);
+        chk_v = L.word_coherent(v);
+        break;
+      case P_MAT:
+        if (STATS) cnt.add(S_MAT_ATT, 1);
+        mat_w = Layout::kTwoPhase ? L.reserve(v) : L.match(v, u, vguess);
+        break;
+      case P_MATW:
+        matw_w = L.word_coherent(v);
+        break;
+      case P_FIN:
+        fin_w = L.fin_probe(x);
+        break;
+      default:
+        break;
+    }
+  };
+
+#pragma unroll 1
+  while (true) {
+    // ---------------- consume the results of last trip's operations
+    // One wait for everything issued on the previous trip (s_waitcnt vmcnt(0);
+    // expcnt and lgkmcnt left at their maxima), so that no issue branch below
+    // waits for a register written on an earlier trip.
+    __builtin_amdgcn_s_waitcnt(0x0f70);
+    consume();
 
     // ---------------- wavefront assist: consume
     if (asst == 2) {
@@ -506,38 +553,7 @@ __device__ __forceinline__ void sweep_block(const SweepParams& a, const OffT* __
     }
 
     // ---------------- issue one operation per lane
-    switch (phase) {
-      case P_IDS:
-#pragma unroll
-        for (int j = 0; j < kMaxW; ++j)
-          if (j < W) ids[j] = (i + j < e) ? ld_stream(nbr + i + j, nt) : (int32_t)x;
-        break;
-      case P_STS:
-#pragma unroll
-        for (int j = 0; j < kMaxW; ++j)
-          if (j < nids && (int64_t)ids[j] != x) rw[j] = filter_word(ids[j]);
-        break;
-      case P_RES:
-        if (STATS) cnt.add(S_RES_ATT, 1);
-        res_w = L.reserve(u);
-        break;
-      case P_CHK:
-        chk_u = L.word_coherent(u);
-        chk_v = L.word_coherent(v);
-        break;
-      case P_MAT:
-        if (STATS) cnt.add(S_MAT_ATT, 1);
-        mat_w = Layout::kTwoPhase ? L.reserve(v) : L.match(v, u, vguess);
-        break;
-      case P_MATW:
-        matw_w = L.word_coherent(v);
-        break;
-      case P_FIN:
-        fin_w = L.fin_probe(x);
-        break;
-      default:
-        break;
-    }
+    issue();
   }
   if (STATS) cnt.add(S_TRIPS, lane == 0 ? (uint32_t)trips : 0u);
 }

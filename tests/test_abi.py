@@ -40,8 +40,8 @@ def test_version_and_defaults():
     assert t.layout in (_lib.MM_LAYOUT_U8, _lib.MM_LAYOUT_U32, _lib.MM_LAYOUT_U2)
     assert t.wg_size % 64 == 0 and t.wave_vertices % 64 == 0
     # the ctypes mirror has the C layout: the last fields read back as written
-    assert t.whole_graph_vertices == 16384 and t.iter_cap == 0
-    assert ctypes.sizeof(_lib.mm_tuning) == 64
+    assert t.whole_graph_vertices == 16384 and t.iter_cap == 0 and t.whole_graph_lds == 1
+    assert ctypes.sizeof(_lib.mm_tuning) == 72
     from paper_2507_04420_amd import Tuning
     assert Tuning.default() == Tuning()  # the Python defaults mirror the library's
 
@@ -107,7 +107,7 @@ def test_create_bad_tuning():
     assert b"wave_vertices" in lib.mm_last_error()
     for field, bad in (("protocol", 2), ("hint", 3), ("hint", -1), ("scan_width", 0), ("scan_width", 9),
                        ("layout", 5), ("stream_loads", 2), ("whole_graph_vertices", -1), ("relabel", 2),
-                       ("hub_degree", -1),
+                       ("hub_degree", -1), ("whole_graph_lds", 2),
                        ("iter_cap", -1)):
         lib.mm_default_tuning(ctypes.byref(t))
         setattr(t, field, bad)

@@ -27,6 +27,9 @@ TUNINGS = {
     "u8_small": mm.Tuning(layout=_lib.MM_LAYOUT_U8, wave_vertices=64, wg_size=64, assist_after=2,
                           lazy_init=1),
     "u32_bytehint": mm.Tuning(hint=2, whole_graph_vertices=0),
+    "u32_whole_in_device_memory": mm.Tuning(whole_graph_lds=0),
+    "u2_two_whole_lds_wg64": mm.Tuning(layout=_lib.MM_LAYOUT_U2, protocol=_lib.MM_PROTOCOL_TWO_PHASE,
+                                       wg_size=64),
 }
 
 
@@ -266,3 +269,62 @@ def test_batch_hub_pieces_are_fast():
             tier = dt
         else:
             assert tier * 3 < dt
+
+
+LDS_CASES = [
+    mm.Tuning(),
+    mm.Tuning(layout=_lib.MM_LAYOUT_U8, lazy_init=1),
+    mm.Tuning(layout=_lib.MM_LAYOUT_U2, protocol=_lib.MM_PROTOCOL_TWO_PHASE),
+    mm.Tuning(protocol=_lib.MM_PROTOCOL_TWO_PHASE, lazy_init=1, hint=1),
+]
+
+
+@pytest.mark.parametrize("case", range(len(LDS_CASES)))
+def test_whole_graph_lds_same_alone_as_in_batch(case):
+    # graphs swept whole keep their states in LDS, in a batch and alone; the
+    # result depends on the graph and the tuning only: a batch member's slice
+    # equals the graph matched alone (mm_run), element by element
+    t = LDS_CASES[case]
+    mix = graphgen.mixture(24, seed=11 + case, nmin=60, nmax=9000)
+    assert int(np.diff(mix.vtx_off).max()) <= t.whole_graph_vertices
+    off = torch.from_numpy(mix.off).cuda()
+    nbr = torch.from_numpy(mix.nbr).cuda()
+    b = mm.Batch(off, nbr, mix.vtx_off, symmetric=True, validate=True, tuning=t)
+    assert b.items == mix.num_graphs
+    out = b.run()
+    b.sync()
+    mate = out.cpu().numpy()
+    check_members(mix, mate)
+    for g in range(mix.num_graphs):
+        sub = mix.member(g)
+        gg = mm.Graph(torch.from_numpy(sub.off).cuda(), torch.from_numpy(sub.nbr).cuda(),
+                      symmetric=True, tuning=t)
+        alone = gg.run()
+        gg.sync()
+        gg.close()
+        v0, v1 = int(mix.vtx_off[g]), int(mix.vtx_off[g + 1])
+        np.testing.assert_array_equal(mate[v0:v1], alone.cpu().numpy(), err_msg=sub.name)
+
+
+def test_whole_graph_lds_largest_and_beyond():
+    # a member at the LDS limit (16384 vertices) and one just above it (swept
+    # whole from device memory), beside small ones; alone and in the batch
+    t = mm.Tuning(whole_graph_vertices=20000)
+    parts = [graphgen.grid(128, 128), graphgen.grid(128, 129), graphgen.er(3000, 6, seed=2),
+             graphgen.from_edges(3, [(0, 1), (1, 2)])]
+    assert parts[0].n == 16384 and parts[1].n == 16512
+    dev = [(torch.from_numpy(p.off.astype(np.int64)).cuda(), torch.from_numpy(p.nbr).cuda())
+           for p in parts]
+    b = mm.Batch.from_list(dev, symmetric=True, validate=True, tuning=t)
+    out = b.run()
+    b.sync()
+    mate = out.cpu().numpy()
+    for k, p in enumerate(parts):
+        v0, v1 = int(b.vtx_off[k]), int(b.vtx_off[k + 1])
+        c = oracle.check(p, mate[v0:v1])
+        assert c.violations == 0, (k, c)
+        g = mm.Graph(dev[k][0], dev[k][1], symmetric=True, tuning=t)
+        alone = g.run()
+        g.sync()
+        g.close()
+        np.testing.assert_array_equal(mate[v0:v1], alone.cpu().numpy(), err_msg=str(k))

@@ -61,6 +61,15 @@ TUNINGS = {
     "hub_small_u8_lazy": mm.Tuning(layout=U8, lazy_init=1, hub_degree=8, hub_chunk=3),
     "hub_relabel_two": mm.Tuning(relabel=1, protocol=TWO, hub_degree=5, hub_chunk=2, hint=2),
     "no_hub_tier": mm.Tuning(hub_degree=0),
+    # small graphs are swept whole with their states in LDS by default; these
+    # keep the states of a whole-graph sweep in device memory, or spread a
+    # small graph over many wavefronts
+    "whole_in_device_memory": mm.Tuning(whole_graph_lds=0),
+    "whole_in_device_memory_u2_two": mm.Tuning(whole_graph_lds=0, layout=U2, protocol=TWO),
+    "multi_wave_u8_lazy": mm.Tuning(layout=U8, lazy_init=1, whole_graph_vertices=0,
+                                    wave_vertices=64, wg_size=64),
+    "multi_wave_u32_two_bytehint": mm.Tuning(protocol=TWO, whole_graph_vertices=0,
+                                             wave_vertices=64, hint=2),
 }
 
 
