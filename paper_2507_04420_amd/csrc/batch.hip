@@ -169,7 +169,10 @@ __global__ __launch_bounds__(256) void batch_sweep_kernel(SweepParams p,
       pp.hub_degree = 0;
     } else {
       pp.chunks = nullptr;
-      if (d.flags & kWholeGraph) pp.hub_degree = 0;
+      if (d.flags & kWholeGraph) {  // as mm_run sweeps a graph whole
+        pp.hub_degree = 0;
+        pp.disperse = 1;
+      }
     }
     sweep_block<int64_t, Layout, HINT, LAZY, STATS>(pp, d.off, d.nbr, L, w.vb, nv,
                                                     queues[threadIdx.x >> 6], cnt);

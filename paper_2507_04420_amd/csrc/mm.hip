@@ -321,7 +321,10 @@ SweepParams make_params(const mm_graph* g) {
   const int64_t ns = g->n - sweep_begin(g);
   if (ns <= g->tun.whole_graph_vertices) {  // one wavefront takes the whole graph
     p.wave_vertices = std::max<int64_t>(64, (ns + 63) / 64 * 64);
-    p.disperse = 0;
+    // lanes stride apart: one wavefront alone is bound by its loop trips, and
+    // lanes on adjacent vertices (neighbours in a mesh) would wait on each
+    // other's reservations
+    p.disperse = 1;
   } else if (ns < kMinWaves * p.wave_vertices) {
     // a small graph alone on the GPU: shorter blocks, so that at least
     // kMinWaves wavefronts (8 per CU) share the sweep and its latency

@@ -185,8 +185,12 @@ __device__ __forceinline__ void sweep_block(const SweepParams& a, OffP __restric
   const int lane = (int)(threadIdx.x & 63);
   const int W = a.scan_width;
   const bool nt = a.stream_loads != 0;
-  const bool disperse = a.disperse && nv == a.wave_vertices;
-  const int64_t stride = a.wave_vertices >> 6;
+  // Dispersed lanes: hand-out index kk goes to source (kk & 63) * stride +
+  // (kk >> 6), so that the lanes of a wavefront work stride sources apart;
+  // indices whose source lies past the block are skipped.
+  const bool disperse = a.disperse != 0 && !a.chunks;
+  const int64_t stride = (nv + 63) >> 6;
+  const int64_t span = disperse ? stride << 6 : nv;  // hand-out indices
   // Loop-trip budget: explicit, or by default 65536 plus 8 per neighbour entry
   // of the block (a pass needs at most about one trip per entry plus short
   // waits), so even an unforeseen livelock ends with an error flag.
@@ -206,6 +210,9 @@ __device__ __forceinline__ void sweep_block(const SweepParams& a, OffP __restric
 
   auto source_of = [&](int64_t kk) -> int64_t {
     return vb + (disperse ? (kk & 63) * stride + (kk >> 6) : kk);
+  };
+  auto in_block = [&](int64_t kk) -> bool {
+    return disperse ? kk < span && (kk & 63) * stride + (kk >> 6) < nv : kk < nv;
   };
   // front end (wavefront-uniform): next hand-out index to read, the chunk
   // whose offsets and states are in flight, and the LDS ring's cursors
@@ -453,7 +460,7 @@ __device__ __forceinline__ void sweep_block(const SweepParams& a, OffP __restric
       const int64_t kk = chunk_base + lane;
       bool need = false;
       int64_t xs = 0;
-      if (kk < nv) {
+      if (in_block(kk)) {
         xs = cb_x;
         if (STATS && !a.chunks) cnt.add(S_SOURCES, 1);
         if (cb_b == cb_e) {
@@ -500,7 +507,7 @@ __device__ __forceinline__ void sweep_block(const SweepParams& a, OffP __restric
       const uint32_t ni = (uint32_t)__popcll(idle);
       q_head += ni < avail ? ni : avail;
     }
-    const bool front_done = chunk_next >= nv && !chunk_pending && q_head == q_tail;
+    const bool front_done = chunk_next >= span && !chunk_pending && q_head == q_tail;
     if (front_done && !__ballot(phase != P_IDLE) && asst == 0) break;
     if (++trips > cap) {
       if (phase == P_MAT || phase == P_MATW) L.release(u);  // holding u
@@ -509,11 +516,11 @@ __device__ __forceinline__ void sweep_block(const SweepParams& a, OffP __restric
     }
 
     // ---------------- front end: read the next 64 sources when the queue runs low
-    if (!chunk_pending && chunk_next < nv && q_tail - q_head < 64) {
+    if (!chunk_pending && chunk_next < span && q_tail - q_head < 64) {
       chunk_base = chunk_next;
       chunk_next += 64;
       const int64_t kk = chunk_base + lane;
-      if (kk < nv) {
+      if (in_block(kk)) {
         int64_t xs;
         if (a.chunks) {
           const HubChunk c = a.chunks[vb + kk];

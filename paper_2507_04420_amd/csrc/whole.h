@@ -60,7 +60,7 @@ __device__ __forceinline__ void sweep_whole_lds(SweepParams p, const OffT* __res
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
   p.wave_vertices = (n + 63) / 64 * 64;
-  p.disperse = 0;
+  p.disperse = 1;  // lanes stride apart (see the whole-graph case of mm_run)
   p.hub_degree = 0;
   p.chunks = nullptr;
   LayoutLds lay;
