@@ -9,7 +9,8 @@ by dimension, keeps the fastest value; every candidate's output must pass the
 device check (zero violations) or the candidate is discarded.
 
 Results are stored as JSON keyed by GPU architecture and compute-unit count,
-then by graph class ("rmat", "grid", "er" for single graphs; "batch" for
+then by graph class ("rmat", "grid", "er", and "rmat_mid", "grid_mid" for
+grid and R-MAT graphs below MID_VERTICES, for single graphs; "batch" for
 many-graph batches), and read back with :func:`tuned`.
 
     python -m paper_2507_04420_amd.autotune --classes batch,rmat --out tuned.json
@@ -36,7 +37,7 @@ SPACE = {
     "relabel": [0, 1],
     "hint": [0, 1, 2],
     "disperse": [0, 1],
-    "wave_vertices": [256, 512, 1024, 2048, 4096],
+    "wave_vertices": [64, 128, 256, 512, 1024, 2048, 4096],
     "wg_size": [64, 128, 256],
     "assist_after": [16, 32, 64, 128, 256],
     "scan_width": [2, 3, 4],
@@ -66,12 +67,16 @@ def _value(t: Tuning, dim: str):
 
 
 class SingleTarget:
-    """One resident graph; objective = GEdges/s of a whole pass."""
+    """One resident graph; objective = GEdges/s of a whole pass. With
+    relabel=False the tuning keeps the given order (relabelling pays off only
+    for a handle that runs many passes; a serving request runs one)."""
 
     unit = "GEdges/s"
-    dims = [d for d in SPACE if d != "whole_graph_vertices"]  # single graphs here are large
 
-    def __init__(self, csr, reps: int = 5):
+    def __init__(self, csr, reps: int = 5, relabel: bool = True):
+        # single graphs here are large: no whole-graph sweeps
+        self.dims = [d for d in SPACE if d != "whole_graph_vertices" and (relabel or d != "relabel")]
+        self.fixed = {} if relabel else {"relabel": 0}  # held for the whole search
         import torch
         self.off = torch.from_numpy(csr.off).cuda()
         self.nbr = torch.from_numpy(csr.nbr).cuda()
@@ -148,6 +153,7 @@ def search(target, start: Tuning | None = None, passes: int = 2, dims=None, log=
     """Coordinate search; returns the best tuning, its objective and the
     number of candidates measured and rejected (failed check or error)."""
     best = start if start is not None else Tuning.default()
+    best = Tuning(**dict(best.as_dict(), **getattr(target, "fixed", {})))
     cache = {}
 
     def score(t):
@@ -184,14 +190,23 @@ def search(target, start: Tuning | None = None, passes: int = 2, dims=None, log=
             "rejected": rejected}
 
 
+# Below this many vertices a grid or R-MAT graph is of the "_mid" class (the
+# serving workload's large jobs): the best launch shape differs there.
+MID_VERTICES = 1 << 25
+
+
 def _targets(classes, seed, rmat_scale=27, grid_side=16384):
     import graphgen
     out = {}
     for c in classes:
         if c == "rmat":
             out[c] = lambda: SingleTarget(graphgen.rmat(rmat_scale, seed=seed))
+        elif c == "rmat_mid":
+            out[c] = lambda: SingleTarget(graphgen.rmat(21, 8, seed=seed), relabel=False)
         elif c == "grid":
             out[c] = lambda: SingleTarget(graphgen.grid(grid_side, grid_side))
+        elif c == "grid_mid":
+            out[c] = lambda: SingleTarget(graphgen.grid(3168, 3168), relabel=False)
         elif c == "er":
             out[c] = lambda: SingleTarget(graphgen.er(1 << 22, 16, seed=seed))
         elif c == "batch":
@@ -206,11 +221,15 @@ def tuned_path(key: str | None = None) -> str:
 
 
 def tuned(graph_class: str, key: str | None = None) -> Tuning:
-    """The stored tuning for this device and graph class, else the defaults."""
+    """The stored tuning for this device and graph class (a "_mid" class
+    without an entry of its own takes its kind's), else the defaults."""
     path = tuned_path(key)
     if os.path.exists(path):
         with open(path) as f:
-            entry = json.load(f).get("classes", {}).get(graph_class)
+            classes = json.load(f).get("classes", {})
+        entry = classes.get(graph_class)
+        if not entry and graph_class.endswith("_mid"):
+            entry = classes.get(graph_class[:-len("_mid")])
         if entry:
             return Tuning(**entry["tuning"])
     return Tuning.default()
@@ -219,16 +238,19 @@ def tuned(graph_class: str, key: str | None = None) -> Tuning:
 def classify(off: np.ndarray) -> str:
     """Graph class of a CSR from its degree sequence: 'grid' when no vertex has
     more than 4 entries, 'rmat' when the degrees are heavily skewed (largest
-    over 32 times the mean), else 'er'."""
+    over 32 times the mean), else 'er'; a grid or R-MAT graph of fewer than
+    MID_VERTICES vertices is 'grid_mid' / 'rmat_mid'."""
     deg = np.diff(off)
     if deg.size == 0 or deg.max() <= 4:
-        return "grid"
-    return "rmat" if deg.max() > 32 * max(deg.mean(), 1e-9) else "er"
+        kind = "grid"
+    else:
+        kind = "rmat" if deg.max() > 32 * max(deg.mean(), 1e-9) else "er"
+    return kind + "_mid" if kind != "er" and deg.size < MID_VERTICES else kind
 
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
-    ap.add_argument("--classes", default="batch,rmat,grid,er")
+    ap.add_argument("--classes", default="batch,rmat,grid,er,rmat_mid,grid_mid")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--passes", type=int, default=2)
     ap.add_argument("--rmat-scale", type=int, default=27)

@@ -329,7 +329,6 @@ SweepParams make_params(const mm_graph* g) {
     // a small graph alone on the GPU: shorter blocks, so that at least
     // kMinWaves wavefronts (8 per CU) share the sweep and its latency
     p.wave_vertices = std::max<int64_t>(64, (ns / kMinWaves + 63) / 64 * 64);
-    p.disperse = 0;
   }
   return p;
 }

@@ -56,10 +56,26 @@ def test_tuned_lookup(tmp_path, monkeypatch):
     assert autotune.tuned("grid", key="dev_1cu") == Tuning.default()
 
 
-def test_classify():
-    assert autotune.classify(graphgen.grid(50, 60).off) == "grid"
+def test_classify(monkeypatch):
+    assert autotune.classify(graphgen.grid(50, 60).off) == "grid_mid"
     assert autotune.classify(graphgen.er(20000, 16, seed=1).off) == "er"
+    assert autotune.classify(graphgen.rmat(16, seed=1).off) == "rmat_mid"
+    # the vertex count alone decides mid against large
+    monkeypatch.setattr(autotune, "MID_VERTICES", 3000)
+    assert autotune.classify(graphgen.grid(50, 60).off) == "grid"
+    assert autotune.classify(graphgen.grid(50, 59).off) == "grid_mid"
     assert autotune.classify(graphgen.rmat(16, seed=1).off) == "rmat"
+    assert autotune.classify(graphgen.er(20000, 16, seed=1).off) == "er"
+
+
+def test_mid_class_falls_back_to_its_kind(tmp_path, monkeypatch):
+    monkeypatch.setattr(autotune, "TUNED_DIR", str(tmp_path))
+    doc = {"device": "dev_2cu", "classes": {"grid": {"tuning": dict(Tuning().as_dict(), wave_vertices=128)},
+                                            "rmat_mid": {"tuning": dict(Tuning().as_dict(), disperse=1)}}}
+    (tmp_path / "dev_2cu.json").write_text(json.dumps(doc))
+    assert autotune.tuned("grid_mid", key="dev_2cu").wave_vertices == 128
+    assert autotune.tuned("rmat_mid", key="dev_2cu").disperse == 1
+    assert autotune.tuned("rmat", key="dev_2cu") == Tuning.default()
 
 
 def test_stored_tunings_are_valid():
@@ -73,3 +89,11 @@ def test_stored_tunings_are_valid():
         for cls, entry in doc["classes"].items():
             ct = Tuning(**entry["tuning"]).to_c()
             assert lib.mm_workspace_bytes_graph(1000, 5000, ctypes.byref(ct)) > 0, (path, cls)
+
+
+def test_search_holds_fixed_fields():
+    class Fixed(FakeTarget):
+        fixed = {"relabel": 0}
+        dims = ["wave_vertices", "scan_width"]
+    r = autotune.search(Fixed(), start=Tuning(relabel=1), passes=1, log=lambda s: None)
+    assert r["tuning"]["relabel"] == 0
