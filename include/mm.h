@@ -158,6 +158,15 @@ typedef struct {
                             written to the output as pairs are committed. Not
                             with relabel. 0: states in device memory, as for
                             every other graph */
+  int32_t mesh_wave_vertices; /* batches: a member graph none of whose lists holds
+                            more than 4 entries (a mesh) and that is not swept
+                            whole is cut into blocks of this many sources (a
+                            multiple of 64), its lanes taking sources
+                            block/64 apart, so that lanes do not hold
+                            neighbouring vertices; create measures the degrees
+                            on the device. 0: such graphs are cut like the
+                            others. Single graphs take their launch shape from
+                            the tuning alone */
   int64_t iter_cap;      /* loop-trip budget per wavefront; 0 = default of
                             65536 + 8 x (neighbour entries of its block);
                             exceeding it raises MM_ERR_NO_PROGRESS */

@@ -47,6 +47,7 @@ class Tuning:
     hub_degree: int = 4096
     hub_chunk: int = 256
     whole_graph_lds: int = 1
+    mesh_wave_vertices: int = 0
     iter_cap: int = 0
 
     @classmethod

@@ -50,6 +50,7 @@ class mm_tuning(ctypes.Structure):
         ("hub_degree", ctypes.c_int32),
         ("hub_chunk", ctypes.c_int32),
         ("whole_graph_lds", ctypes.c_int32),
+        ("mesh_wave_vertices", ctypes.c_int32),
         ("iter_cap", ctypes.c_int64),
     ]
 

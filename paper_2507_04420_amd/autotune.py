@@ -3,8 +3,9 @@
 The matching itself has no parameters; what is tuned is how the sweep maps to
 the device: the status layout and reservation protocol, degree relabelling
 (single graphs), the matched hint (none, bits, bytes), vertices per wavefront
-item, workgroup size, the list length after which a wavefront scans one
-source together, the per-lane scan width and lazy output. A coordinate search starts from the library defaults and, dimension
+item (and, in batches, per mesh-like member), workgroup size, the list
+length after which a wavefront scans one source together, the per-lane scan
+width and lazy output. A coordinate search starts from the library defaults and, dimension
 by dimension, keeps the fastest value; every candidate's output must pass the
 device check (zero violations) or the candidate is discarded.
 
@@ -43,6 +44,7 @@ SPACE = {
     "scan_width": [2, 3, 4],
     "lazy_init": [0, 1],
     "whole_graph_vertices": [0, 4096, 16384],
+    "mesh_wave_vertices": [0, 128, 256, 512],
 }
 
 
@@ -75,7 +77,8 @@ class SingleTarget:
 
     def __init__(self, csr, reps: int = 5, relabel: bool = True):
         # single graphs here are large: no whole-graph sweeps
-        self.dims = [d for d in SPACE if d != "whole_graph_vertices" and (relabel or d != "relabel")]
+        self.dims = [d for d in SPACE if d not in ("whole_graph_vertices", "mesh_wave_vertices") and
+                     (relabel or d != "relabel")]
         self.fixed = {} if relabel else {"relabel": 0}  # held for the whole search
         import torch
         self.off = torch.from_numpy(csr.off).cuda()

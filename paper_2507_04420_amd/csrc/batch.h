@@ -24,9 +24,12 @@ struct GraphDesc {
   uint32_t hint_lg;  // log2 of vertices per hint word
   uint32_t flags;    // kWholeGraph: swept by one wavefront, no hub pieces
   int64_t pieces;    // hub table build only: piece count, then fill cursor
+  int64_t not_mesh;  // create only (mesh_wave_vertices): 1 if a list exceeds kMeshDegree
 };
 constexpr uint32_t kWholeGraph = 1u;
 constexpr uint32_t kWholeLds = 2u;  // with kWholeGraph: states in the wavefront's LDS (whole.h)
+constexpr uint32_t kMesh = 4u;      // lists of at most kMeshDegree entries: dispersed lanes
+constexpr int64_t kMeshDegree = 4;
 
 // One wavefront block: sources vb .. vb+nv-1 of graph `desc`; or, with
 // nv < 0, the hub pieces vb .. vb-nv-1 of the piece table (all of graph desc).
@@ -94,6 +97,10 @@ BatchInfo batch_info(const mm_batch* b);
 // the first table slot of graph g and writes every piece (stream-ordered).
 hipError_t count_batch_hubs(GraphDesc* descs_dev, const int64_t* vtx_dev, int32_t G, int64_t N,
                             int64_t hub_degree, int64_t chunk, uint8_t* ctrl, hipStream_t s);
+// Sets descs[g].not_mesh (zero on entry) for every graph with a list of more
+// than kMeshDegree entries.
+hipError_t batch_find_meshes(GraphDesc* descs_dev, const int64_t* vtx_dev, int32_t G, int64_t N,
+                             hipStream_t s);
 hipError_t fill_batch_hubs(GraphDesc* descs_dev, const int64_t* vtx_dev, int32_t G, int64_t N,
                            int64_t hub_degree, int64_t chunk, mmk::HubChunk* table, hipStream_t s);
 

@@ -172,6 +172,8 @@ __global__ __launch_bounds__(256) void batch_sweep_kernel(SweepParams p,
       if (d.flags & kWholeGraph) {  // as mm_run sweeps a graph whole
         pp.hub_degree = 0;
         pp.disperse = 1;
+      } else if (d.flags & kMesh) {
+        pp.disperse = 1;
       }
     }
     sweep_block<int64_t, Layout, HINT, LAZY, STATS>(pp, d.off, d.nbr, L, w.vb, nv,
@@ -339,7 +341,10 @@ bool plan_layout(int32_t G, const int64_t* vtx_off, const mm_tuning& t, BatchLay
   for (int32_t g = 0; g < G; ++g) {
     const int64_t n = vtx_off[g + 1] - vtx_off[g];
     if (n < 0 || n > INT32_MAX) return false;
-    n_items += n <= t.whole_graph_vertices ? (n > 0) : (n + t.wave_vertices - 1) / t.wave_vertices;
+    // mesh graphs may take shorter blocks: room for the shorter of the two
+    const int64_t wv = t.mesh_wave_vertices > 0 ? std::min(t.wave_vertices, t.mesh_wave_vertices)
+                                                 : t.wave_vertices;
+    n_items += n <= t.whole_graph_vertices ? (n > 0) : (n + wv - 1) / wv;
     st_words += mmb::state_words_for(n, t.layout);
     hint_words += mmk::hint_words(n, t.hint);
   }
@@ -443,15 +448,6 @@ mm_status finish_create(std::vector<mmb::GraphDesc>& descs, const std::vector<in
     }
     st_w += mmb::state_words_for(d.n, t.layout);
     hint_w += mmk::hint_words(d.n, t.hint);
-    // a small graph is one item (one wavefront), a larger one an item per block
-    const int64_t step = d.n <= t.whole_graph_vertices ? d.n : t.wave_vertices;
-    for (int64_t vb = 0; vb < d.n; vb += step) {
-      mmb::WorkItem w;
-      w.desc = g;
-      w.vb = vb;
-      w.nv = (int32_t)std::min<int64_t>(step, d.n - vb);
-      (d.flags & mmb::kWholeLds ? lds_items : items).push_back(w);
-    }
   }
   auto* descs_dev = reinterpret_cast<mmb::GraphDesc*>(ws + lay.descs);
   auto* items_dev = reinterpret_cast<mmb::WorkItem*>(ws + lay.items);
@@ -477,6 +473,9 @@ mm_status finish_create(std::vector<mmb::GraphDesc>& descs, const std::vector<in
                       (descs[g].m < 0 || descs[g].m > t.hub_degree);
   if (hubs_possible)
     HIP_TRY(mmb::count_batch_hubs(descs_dev, vtx_dev, G, N, t.hub_degree, t.hub_chunk, ws, s));
+  // meshes (no list longer than kMeshDegree) get their own block length
+  const bool find_meshes = t.mesh_wave_vertices > 0;
+  if (find_meshes) HIP_TRY(mmb::batch_find_meshes(descs_dev, vtx_dev, G, N, s));
   uint32_t hf = 0;
   unsigned long long n_pieces = 0;
   HIP_TRY(hipMemcpyAsync(&hf, f, sizeof(hf), hipMemcpyDeviceToHost, s));
@@ -493,16 +492,42 @@ mm_status finish_create(std::vector<mmb::GraphDesc>& descs, const std::vector<in
                 (hf & 2u) ? " offsets decrease;" : "",
                 (hf & 4u) ? " neighbour id outside its graph;" : "");
   }
+  const int64_t n_chunks = (int64_t)n_pieces;
+  if (G > 0 && (n_chunks > 0 || find_meshes)) {  // per-graph results of the counting kernels
+    HIP_TRY(hipMemcpyAsync(descs.data(), descs_dev, sizeof(mmb::GraphDesc) * G,
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  // work items: a small graph is one item (one wavefront), a larger one an
+  // item per block; a mesh's blocks are shorter, and its lanes dispersed
+  bool descs_changed = false;
+  for (int32_t g = 0; g < G; ++g) {
+    mmb::GraphDesc& d = descs[g];
+    int64_t step = t.wave_vertices;
+    if (d.flags & mmb::kWholeGraph) {
+      step = d.n;
+    } else if (find_meshes && !d.not_mesh) {
+      d.flags |= mmb::kMesh;
+      step = t.mesh_wave_vertices;
+      descs_changed = true;
+    }
+    for (int64_t vb = 0; vb < d.n; vb += step) {
+      mmb::WorkItem w;
+      w.desc = g;
+      w.vb = vb;
+      w.nv = (int32_t)std::min<int64_t>(step, d.n - vb);
+      (d.flags & mmb::kWholeLds ? lds_items : items).push_back(w);
+    }
+  }
+  if (descs_changed && n_chunks == 0)
+    HIP_TRY(hipMemcpyAsync(descs_dev, descs.data(), sizeof(mmb::GraphDesc) * G,
+                           hipMemcpyHostToDevice, s));
   // second pass, only when pieces exist: they become work items of their own
   // after the blocks, in one allocation the handle owns (item table, then
   // piece table)
   mmk::HubChunk* chunks = nullptr;
-  const int64_t n_chunks = (int64_t)n_pieces;
   void* own = nullptr;
   if (n_chunks > 0) {
-    HIP_TRY(hipMemcpyAsync(descs.data(), descs_dev, sizeof(mmb::GraphDesc) * G,
-                           hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
     int64_t first = 0;
     for (int32_t g = 0; g < G; ++g) {
       const int64_t k = descs[g].pieces;

@@ -129,6 +129,21 @@ __global__ void batch_fill_kernel(mmb::GraphDesc* descs, const int64_t* __restri
   }
 }
 
+// Marks the graphs that are not meshes. Once a graph is marked, its other
+// vertices see the mark with a plain load and write nothing.
+__global__ void find_meshes_kernel(mmb::GraphDesc* descs, const int64_t* __restrict__ vtx_off,
+                                   int32_t G, int64_t N) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < N; v += stride) {
+    const int g = graph_of(vtx_off, G, v);
+    mmb::GraphDesc& d = descs[g];
+    const int64_t x = v - d.v0;
+    if (d.off[x + 1] - d.off[x] > mmb::kMeshDegree &&
+        __hip_atomic_load(&d.not_mesh, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+      __hip_atomic_store(&d.not_mesh, (int64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
 template <typename OffT>
 hipError_t build_typed(const OffT* off, int64_t n, int64_t hub_degree, int64_t chunk, uint8_t* ctrl,
                        mmk::HubChunk** table, int64_t* count, hipStream_t s) {
@@ -192,6 +207,14 @@ hipError_t count_batch_hubs(GraphDesc* descs_dev, const int64_t* vtx_dev, int32_
   if (e != hipSuccess || N == 0 || G == 0 || hub_degree <= 0) return e;
   hipLaunchKernelGGL(batch_count_kernel, dim3(blocks_for(N)), dim3(256), 0, s, descs_dev, vtx_dev,
                      G, N, hub_degree, chunk, total);
+  return hipGetLastError();
+}
+
+hipError_t batch_find_meshes(GraphDesc* descs_dev, const int64_t* vtx_dev, int32_t G, int64_t N,
+                             hipStream_t s) {
+  if (N == 0 || G == 0) return hipSuccess;
+  hipLaunchKernelGGL(find_meshes_kernel, dim3(blocks_for(N)), dim3(256), 0, s, descs_dev, vtx_dev,
+                     G, N);
   return hipGetLastError();
 }
 

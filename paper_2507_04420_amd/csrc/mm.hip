@@ -69,6 +69,8 @@ mm_status check_tuning(const mm_tuning& t) {
   if (t.iter_cap < 0) return fail(MM_ERR_INVALID_ARG, "tuning.iter_cap must be >= 0");
   if (t.whole_graph_lds != 0 && t.whole_graph_lds != 1)
     return fail(MM_ERR_INVALID_ARG, "tuning.whole_graph_lds must be 0 or 1");
+  if (t.mesh_wave_vertices < 0 || t.mesh_wave_vertices % 64)
+    return fail(MM_ERR_INVALID_ARG, "tuning.mesh_wave_vertices must be 0 or a positive multiple of 64");
   return MM_OK;
 }
 

@@ -28,6 +28,9 @@ TUNINGS = {
                           lazy_init=1),
     "u32_bytehint": mm.Tuning(hint=2, whole_graph_vertices=0),
     "u32_whole_in_device_memory": mm.Tuning(whole_graph_lds=0),
+    "u32_mesh128": mm.Tuning(whole_graph_vertices=0, mesh_wave_vertices=128),
+    "u8_mesh64_hubs": mm.Tuning(layout=_lib.MM_LAYOUT_U8, whole_graph_vertices=0, mesh_wave_vertices=64,
+                                hub_degree=8, hub_chunk=4, lazy_init=1),
     "u2_two_whole_lds_wg64": mm.Tuning(layout=_lib.MM_LAYOUT_U2, protocol=_lib.MM_PROTOCOL_TWO_PHASE,
                                        wg_size=64),
 }
@@ -328,3 +331,26 @@ def test_whole_graph_lds_largest_and_beyond():
         g.sync()
         g.close()
         np.testing.assert_array_equal(mate[v0:v1], alone.cpu().numpy(), err_msg=str(k))
+
+
+def test_mesh_members_get_short_blocks():
+    # a grid member (no list longer than 4) is cut into mesh_wave_vertices
+    # blocks, the others into wave_vertices blocks
+    parts = [graphgen.grid(40, 50), graphgen.er(2000, 8, seed=4)]
+    dev = [(torch.from_numpy(p.off.astype(np.int64)).cuda(), torch.from_numpy(p.nbr).cuda())
+           for p in parts]
+    base = dict(whole_graph_vertices=0, wave_vertices=1024)
+    counts = {}
+    for mesh in (0, 64):
+        b = mm.Batch.from_list(dev, symmetric=True, validate=True,
+                               tuning=mm.Tuning(**base, mesh_wave_vertices=mesh))
+        out = b.run()
+        b.sync()
+        mate = out.cpu().numpy()
+        for k, p in enumerate(parts):
+            c = oracle.check(p, mate[int(b.vtx_off[k]):int(b.vtx_off[k + 1])])
+            assert c.violations == 0, (mesh, k, c)
+        counts[mesh] = b.items
+        b.close()
+    assert counts[0] == 2 + 2  # ceil(2000 / 1024) blocks each
+    assert counts[64] == (2000 + 63) // 64 + 2
