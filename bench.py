@@ -267,8 +267,9 @@ def bench_batch(args, tun, dev):
 
     # per-graph launches: one handle per member graph, outputs are views of one
     # tensor. Each launch spreads its graph over many wavefronts (no whole-graph
-    # items, and mm_run's short blocks for small graphs): its fastest form alone.
-    tun_pg = mm.Tuning(**dict(tun.as_dict(), whole_graph_vertices=0))
+    # items, and mm_run's short blocks for small graphs) and runs no hint (its
+    # fill would be one more launch per graph): its fastest form alone.
+    tun_pg = mm.Tuning(**dict(tun.as_dict(), whole_graph_vertices=0, hint=0))
     vtx = mix.vtx_off
     offs, handles = [], []
     out2 = torch.empty(mix.n, dtype=torch.int32, device=dev)
