@@ -334,21 +334,33 @@ namespace {
 struct BatchLayout {  // byte offsets of the workspace pieces after the control block
   size_t descs, items, vtx, st, hint, total;
   int64_t n_items, st_words, hint_words;
+  int64_t wave_vertices, mesh_wave_vertices;  // block lengths (shortened for a small batch)
 };
 
 bool plan_layout(int32_t G, const int64_t* vtx_off, const mm_tuning& t, BatchLayout* out) {
   int64_t n_items = 0, st_words = 0, hint_words = 0;
+  // sources swept in blocks (graphs not swept whole): too few of them for
+  // kMinWaves wavefronts, and the blocks get shorter, as for a single graph
+  int64_t blocked = 0;
   for (int32_t g = 0; g < G; ++g) {
     const int64_t n = vtx_off[g + 1] - vtx_off[g];
     if (n < 0 || n > INT32_MAX) return false;
+    if (n > t.whole_graph_vertices) blocked += n;
+  }
+  const int64_t wv_main = mmi::short_blocks(blocked, t.wave_vertices);
+  const int64_t wv_mesh =
+      t.mesh_wave_vertices > 0 ? mmi::short_blocks(blocked, t.mesh_wave_vertices) : 0;
+  for (int32_t g = 0; g < G; ++g) {
+    const int64_t n = vtx_off[g + 1] - vtx_off[g];
     // mesh graphs may take shorter blocks: room for the shorter of the two
-    const int64_t wv = t.mesh_wave_vertices > 0 ? std::min(t.wave_vertices, t.mesh_wave_vertices)
-                                                 : t.wave_vertices;
+    const int64_t wv = wv_mesh > 0 ? std::min(wv_main, wv_mesh) : wv_main;
     n_items += n <= t.whole_graph_vertices ? (n > 0) : (n + wv - 1) / wv;
     st_words += mmb::state_words_for(n, t.layout);
     hint_words += mmk::hint_words(n, t.hint);
   }
   BatchLayout L;
+  L.wave_vertices = wv_main;
+  L.mesh_wave_vertices = wv_mesh;
   L.n_items = n_items;
   L.st_words = st_words;
   L.hint_words = hint_words;
@@ -503,12 +515,12 @@ mm_status finish_create(std::vector<mmb::GraphDesc>& descs, const std::vector<in
   bool descs_changed = false;
   for (int32_t g = 0; g < G; ++g) {
     mmb::GraphDesc& d = descs[g];
-    int64_t step = t.wave_vertices;
+    int64_t step = lay.wave_vertices;
     if (d.flags & mmb::kWholeGraph) {
       step = d.n;
     } else if (find_meshes && !d.not_mesh) {
       d.flags |= mmb::kMesh;
-      step = t.mesh_wave_vertices;
+      step = lay.mesh_wave_vertices;
       descs_changed = true;
     }
     for (int64_t vb = 0; vb < d.n; vb += step) {
@@ -592,7 +604,7 @@ mm_status finish_create(std::vector<mmb::GraphDesc>& descs, const std::vector<in
   b->lay = lay;
   b->vtx_off = vtx;
   mmb::BatchPlan& p = b->plan;
-  p.params.wave_vertices = t.wave_vertices;
+  p.params.wave_vertices = lay.wave_vertices;
   p.params.disperse = t.disperse;
   p.params.assist_after = t.assist_after;
   p.params.scan_width = t.scan_width;

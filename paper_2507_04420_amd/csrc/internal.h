@@ -56,6 +56,16 @@ hipError_t build_hub_chunks(const void* off, int off64, int64_t n, int64_t hub_d
 // Stream-ordered release of memory a handle owns (no wait for the device).
 void free_owned(void* p);
 
+// A sweep too small to give this many wavefronts of wave_vertices sources
+// gets shorter blocks (single graphs and batches alike), so that at least
+// this many wavefronts (8 per CU) share it and its latency.
+constexpr int64_t kMinWaves = 2048;
+inline int64_t short_blocks(int64_t sources, int64_t wave_vertices) {
+  if (sources >= kMinWaves * wave_vertices) return wave_vertices;
+  const int64_t w = (sources / kMinWaves + 63) / 64 * 64;
+  return w < 64 ? 64 : w;
+}
+
 // Copies the raw device counters (sweep.h order) into the ABI struct.
 void stats_from_counters(const unsigned long long* c, mm_stats* out);
 

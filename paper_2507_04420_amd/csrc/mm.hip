@@ -303,7 +303,6 @@ uint32_t handle_flags(const mm_graph* h) { return h->flags; }
 
 namespace {
 
-constexpr int64_t kMinWaves = 2048;
 
 // Sources the sweep visits: all vertices, or, relabelled, those with entries.
 int64_t sweep_begin(const mm_graph* g) { return g->relabel ? g->rl.n_isolated : 0; }
@@ -327,10 +326,9 @@ SweepParams make_params(const mm_graph* g) {
     // lanes on adjacent vertices (neighbours in a mesh) would wait on each
     // other's reservations
     p.disperse = 1;
-  } else if (ns < kMinWaves * p.wave_vertices) {
-    // a small graph alone on the GPU: shorter blocks, so that at least
-    // kMinWaves wavefronts (8 per CU) share the sweep and its latency
-    p.wave_vertices = std::max<int64_t>(64, (ns / kMinWaves + 63) / 64 * 64);
+  } else {
+    // a small graph alone on the GPU: shorter blocks
+    p.wave_vertices = mmi::short_blocks(ns, p.wave_vertices);
   }
   return p;
 }

@@ -335,13 +335,14 @@ def test_whole_graph_lds_largest_and_beyond():
 
 def test_mesh_members_get_short_blocks():
     # a grid member (no list longer than 4) is cut into mesh_wave_vertices
-    # blocks, the others into wave_vertices blocks
-    parts = [graphgen.grid(40, 50), graphgen.er(2000, 8, seed=4)]
+    # blocks, the others into wave_vertices blocks (the batch is large enough
+    # that neither is shortened for size)
+    parts = [graphgen.grid(512, 512), graphgen.er(20000, 8, seed=4)]
     dev = [(torch.from_numpy(p.off.astype(np.int64)).cuda(), torch.from_numpy(p.nbr).cuda())
            for p in parts]
-    base = dict(whole_graph_vertices=0, wave_vertices=1024)
+    base = dict(whole_graph_vertices=0, wave_vertices=64)
     counts = {}
-    for mesh in (0, 64):
+    for mesh in (0, 128):
         b = mm.Batch.from_list(dev, symmetric=True, validate=True,
                                tuning=mm.Tuning(**base, mesh_wave_vertices=mesh))
         out = b.run()
@@ -352,5 +353,23 @@ def test_mesh_members_get_short_blocks():
             assert c.violations == 0, (mesh, k, c)
         counts[mesh] = b.items
         b.close()
-    assert counts[0] == 2 + 2  # ceil(2000 / 1024) blocks each
-    assert counts[64] == (2000 + 63) // 64 + 2
+    er_blocks = (20000 + 63) // 64
+    assert counts[0] == 512 * 512 // 64 + er_blocks
+    assert counts[128] == 512 * 512 // 128 + er_blocks
+
+
+def test_small_batch_gets_short_blocks():
+    # too few sources for 2048 wavefronts of wave_vertices: blocks of 64
+    parts = [graphgen.er(20000, 8, seed=5), graphgen.rmat(14, 8, seed=5)]
+    dev = [(torch.from_numpy(p.off.astype(np.int64)).cuda(), torch.from_numpy(p.nbr).cuda())
+           for p in parts]
+    b = mm.Batch.from_list(dev, symmetric=True, validate=True,
+                           tuning=mm.Tuning(whole_graph_vertices=0, wave_vertices=2048))
+    assert b.items == sum((p.n + 63) // 64 for p in parts)
+    out = b.run()
+    b.sync()
+    mate = out.cpu().numpy()
+    for k, p in enumerate(parts):
+        c = oracle.check(p, mate[int(b.vtx_off[k]):int(b.vtx_off[k + 1])])
+        assert c.violations == 0, (k, c)
+    b.close()
