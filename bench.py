@@ -126,6 +126,7 @@ VARIANTS = {
     "no_assist": {"assist_after": 0},
     "contiguous_lanes": {"disperse": 0},
     "dispersed_lanes": {"disperse": 1},
+    "wait_release": {"wait_release": 1},
 }
 
 

@@ -167,6 +167,13 @@ typedef struct {
                             on the device. 0: such graphs are cut like the
                             others. Single graphs take their launch shape from
                             the tuning alone */
+  int32_t wait_release;  /* 1: a lane that finds v reserved by another lane
+                            releases u while it waits, and takes u again once
+                            v is accessible (Algorithm 1 holds u, L13-14). No
+                            lane then waits on a lane that is itself waiting,
+                            so no chain of reservations forms, which on meshes
+                            swept by many lanes at once can grow as long as a
+                            column. 0: as printed */
   int64_t iter_cap;      /* loop-trip budget per wavefront; 0 = default of
                             65536 + 8 x (neighbour entries of its block);
                             exceeding it raises MM_ERR_NO_PROGRESS */

@@ -48,6 +48,7 @@ class Tuning:
     hub_chunk: int = 256
     whole_graph_lds: int = 1
     mesh_wave_vertices: int = 0
+    wait_release: int = 0
     iter_cap: int = 0
 
     @classmethod

@@ -51,6 +51,7 @@ class mm_tuning(ctypes.Structure):
         ("hub_chunk", ctypes.c_int32),
         ("whole_graph_lds", ctypes.c_int32),
         ("mesh_wave_vertices", ctypes.c_int32),
+        ("wait_release", ctypes.c_int32),
         ("iter_cap", ctypes.c_int64),
     ]
 

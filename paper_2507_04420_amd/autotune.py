@@ -5,7 +5,7 @@ the device: the status layout and reservation protocol, degree relabelling
 (single graphs), the matched hint (none, bits, bytes), vertices per wavefront
 item (and, in batches, per mesh-like member), workgroup size, the list
 length after which a wavefront scans one source together, the per-lane scan
-width and lazy output. A coordinate search starts from the library defaults and, dimension
+width, lazy output, and whether a lane releases u while it waits for v. A coordinate search starts from the library defaults and, dimension
 by dimension, keeps the fastest value; every candidate's output must pass the
 device check (zero violations) or the candidate is discarded.
 
@@ -45,6 +45,7 @@ SPACE = {
     "lazy_init": [0, 1],
     "whole_graph_vertices": [0, 4096, 16384],
     "mesh_wave_vertices": [0, 128, 256, 512],
+    "wait_release": [0, 1],
 }
 
 

@@ -609,6 +609,7 @@ mm_status finish_create(std::vector<mmb::GraphDesc>& descs, const std::vector<in
   p.params.assist_after = t.assist_after;
   p.params.scan_width = t.scan_width;
   p.params.stream_loads = t.stream_loads;
+  p.params.wait_release = t.wait_release;
   p.params.iter_cap = t.iter_cap;
   p.params.hub_degree = n_chunks > 0 ? t.hub_degree : 0;
   p.params.hub_chunk = t.hub_chunk;

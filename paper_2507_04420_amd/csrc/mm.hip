@@ -69,6 +69,8 @@ mm_status check_tuning(const mm_tuning& t) {
   if (t.iter_cap < 0) return fail(MM_ERR_INVALID_ARG, "tuning.iter_cap must be >= 0");
   if (t.whole_graph_lds != 0 && t.whole_graph_lds != 1)
     return fail(MM_ERR_INVALID_ARG, "tuning.whole_graph_lds must be 0 or 1");
+  if (t.wait_release != 0 && t.wait_release != 1)
+    return fail(MM_ERR_INVALID_ARG, "tuning.wait_release must be 0 or 1");
   if (t.mesh_wave_vertices < 0 || t.mesh_wave_vertices % 64)
     return fail(MM_ERR_INVALID_ARG, "tuning.mesh_wave_vertices must be 0 or a positive multiple of 64");
   return MM_OK;
@@ -314,6 +316,7 @@ SweepParams make_params(const mm_graph* g) {
   p.assist_after = g->tun.assist_after;
   p.scan_width = g->tun.scan_width;
   p.stream_loads = g->tun.stream_loads;
+  p.wait_release = g->tun.wait_release;
   p.iter_cap = g->tun.iter_cap;
   p.err = reinterpret_cast<uint32_t*>(g->ws);
   p.hub_degree = g->n_chunks > 0 ? g->tun.hub_degree : 0;

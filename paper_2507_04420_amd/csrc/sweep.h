@@ -57,6 +57,7 @@ enum : int {
   P_CHK,       // u was reserved by another lane: coherent re-read of u and v (L10)
   P_MAT,       // v requested: CAS ACC -> MCHD (L14), or reserve(v) (two-phase)
   P_MATW,      // v was reserved by another lane: coherent re-read of v (L13)
+  P_VW,        // the same wait with u released first (wait_release): then u again
   P_FIN,       // list exhausted: final check of the source's own state
   P_ASST,      // paused while the wavefront scans ahead for this lane
   P_DONE
@@ -78,6 +79,7 @@ struct SweepParams {
   int32_t assist_after;
   int32_t scan_width;      // 1..kMaxW
   int32_t stream_loads;    // 1: offsets and ids through non-temporal loads
+  int32_t wait_release;    // 1: release u while waiting for a reserved v
   int64_t iter_cap;        // 0: per-block default budget
   uint32_t* err;           // bit 0: loop-trip budget exceeded
   // Hub tier. Main pass: sources with more than hub_degree entries are left
@@ -355,7 +357,14 @@ __device__ __forceinline__ void sweep_block(const SweepParams& a, OffP __restric
             cnt.add(S_MAT_CONF, 1);
             ++econf;
           }
-          phase = P_MATW;
+          if (a.wait_release) {
+            // hold nothing while waiting: a lane waiting on u then need not
+            // wait for this lane's wait too, so no chain of holders forms
+            L.release(u);
+            phase = P_VW;
+          } else {
+            phase = P_MATW;
+          }
         } else {
           if (STATS) cnt.add(S_MAT_MCHD, 1);
           L.release(u);
@@ -370,6 +379,16 @@ __device__ __forceinline__ void sweep_block(const SweepParams& a, OffP __restric
           phase = P_MAT;
         } else if (s == R_MCHD) {
           L.release(u);
+          edge_dead(v);
+        }
+        break;
+      }
+      case P_VW: {
+        const int s = Layout::decode(matw_w, v);
+        if (s == R_ACC) {
+          vguess = matw_w;
+          phase = P_RES;  // take u again, then v
+        } else if (s == R_MCHD) {
           edge_dead(v);
         }
         break;
@@ -418,6 +437,7 @@ __device__ __forceinline__ void sweep_block(const SweepParams& a, OffP __restric
         mat_w = Layout::kTwoPhase ? L.reserve(v) : L.match(v, u, vguess);
         break;
       case P_MATW:
+      case P_VW:
         matw_w = L.word_coherent(v);
         break;
       case P_FIN:

@@ -41,7 +41,7 @@ def test_version_and_defaults():
     assert t.wg_size % 64 == 0 and t.wave_vertices % 64 == 0
     # the ctypes mirror has the C layout: the last fields read back as written
     assert t.whole_graph_vertices == 16384 and t.iter_cap == 0 and t.whole_graph_lds == 1
-    assert ctypes.sizeof(_lib.mm_tuning) == 72
+    assert ctypes.sizeof(_lib.mm_tuning) == 80
     from paper_2507_04420_amd import Tuning
     assert Tuning.default() == Tuning()  # the Python defaults mirror the library's
 
@@ -107,7 +107,8 @@ def test_create_bad_tuning():
     assert b"wave_vertices" in lib.mm_last_error()
     for field, bad in (("protocol", 2), ("hint", 3), ("hint", -1), ("scan_width", 0), ("scan_width", 9),
                        ("layout", 5), ("stream_loads", 2), ("whole_graph_vertices", -1), ("relabel", 2),
-                       ("hub_degree", -1), ("whole_graph_lds", 2),
+                       ("hub_degree", -1), ("whole_graph_lds", 2), ("wait_release", 2),
+                       ("mesh_wave_vertices", 100),
                        ("iter_cap", -1)):
         lib.mm_default_tuning(ctypes.byref(t))
         setattr(t, field, bad)

@@ -31,6 +31,8 @@ TUNINGS = {
     "u32_mesh128": mm.Tuning(whole_graph_vertices=0, mesh_wave_vertices=128),
     "u8_mesh64_hubs": mm.Tuning(layout=_lib.MM_LAYOUT_U8, whole_graph_vertices=0, mesh_wave_vertices=64,
                                 hub_degree=8, hub_chunk=4, lazy_init=1),
+    "u32_mesh128_wait_release": mm.Tuning(whole_graph_vertices=0, mesh_wave_vertices=128,
+                                          wait_release=1),
     "u2_two_whole_lds_wg64": mm.Tuning(layout=_lib.MM_LAYOUT_U2, protocol=_lib.MM_PROTOCOL_TWO_PHASE,
                                        wg_size=64),
 }

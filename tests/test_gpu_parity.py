@@ -70,6 +70,10 @@ TUNINGS = {
                                     wave_vertices=64, wg_size=64),
     "multi_wave_u32_two_bytehint": mm.Tuning(protocol=TWO, whole_graph_vertices=0,
                                              wave_vertices=64, hint=2),
+    "wait_release_multi_wave": mm.Tuning(wait_release=1, whole_graph_vertices=0, wave_vertices=64),
+    "wait_release_u8_two_lazy": mm.Tuning(layout=U8, protocol=TWO, wait_release=1, lazy_init=1,
+                                          whole_graph_vertices=0, wave_vertices=64, wg_size=64),
+    "wait_release_whole_lds": mm.Tuning(wait_release=1),
 }
 
 
