@@ -5,9 +5,10 @@ the device: the status layout and reservation protocol, degree relabelling
 (single graphs), the matched hint (none, bits, bytes), vertices per wavefront
 item (and, in batches, per mesh-like member), workgroup size, the list
 length after which a wavefront scans one source together, the per-lane scan
-width, lazy output, and whether a lane releases u while it waits for v. A coordinate search starts from the library defaults and, dimension
-by dimension, keeps the fastest value; every candidate's output must pass the
-device check (zero violations) or the candidate is discarded.
+width, lazy output, and whether a lane releases u while it waits for v. A
+coordinate search starts from the stored entry (or the library defaults) and,
+dimension by dimension, keeps the fastest value; every candidate's output must
+pass the device check (zero violations) or the candidate is discarded.
 
 Results are stored as JSON keyed by GPU architecture and compute-unit count,
 then by graph class ("rmat", "grid", "er", and "rmat_mid", "grid_mid" for
@@ -112,6 +113,30 @@ class SingleTarget:
             g.close()
 
 
+class MultiTarget:
+    """Several resident graphs of one class, each its own handle; objective =
+    their entries over the sum of their pass times, so that a tuning must
+    serve every size of the class, not one graph."""
+
+    unit = "GEdges/s"
+
+    def __init__(self, csrs, reps: int = 5, relabel: bool = False):
+        self.parts = [SingleTarget(c, reps=reps, relabel=relabel) for c in csrs]
+        self.dims = self.parts[0].dims
+        self.fixed = self.parts[0].fixed
+        self.sample = " + ".join(p.sample for p in self.parts)
+
+    def measure(self, t: Tuning):
+        seconds, m = 0.0, 0
+        for p in self.parts:
+            r = p.measure(t)
+            if r is None:
+                return None
+            seconds += p.m / (r * 1e9)
+            m += p.m
+        return m / seconds / 1e9
+
+
 class BatchTarget:
     """A many-graph batch; objective = graphs/s of a captured pass."""
 
@@ -206,11 +231,11 @@ def _targets(classes, seed, rmat_scale=27, grid_side=16384):
         if c == "rmat":
             out[c] = lambda: SingleTarget(graphgen.rmat(rmat_scale, seed=seed))
         elif c == "rmat_mid":
-            out[c] = lambda: SingleTarget(graphgen.rmat(21, 8, seed=seed), relabel=False)
+            out[c] = lambda: MultiTarget([graphgen.rmat(18, 8, seed=seed), graphgen.rmat(21, 8, seed=seed)])
         elif c == "grid":
             out[c] = lambda: SingleTarget(graphgen.grid(grid_side, grid_side))
         elif c == "grid_mid":
-            out[c] = lambda: SingleTarget(graphgen.grid(3168, 3168), relabel=False)
+            out[c] = lambda: MultiTarget([graphgen.grid(1024, 1024), graphgen.grid(3168, 3168)])
         elif c == "er":
             out[c] = lambda: SingleTarget(graphgen.er(1 << 22, 16, seed=seed))
         elif c == "batch":

@@ -97,3 +97,18 @@ def test_search_holds_fixed_fields():
         dims = ["wave_vertices", "scan_width"]
     r = autotune.search(Fixed(), start=Tuning(relabel=1), passes=1, log=lambda s: None)
     assert r["tuning"]["relabel"] == 0
+
+
+def test_multi_target_objective():
+    class Part:
+        def __init__(self, m, rate):
+            self.m, self.rate, self.sample = m, rate, "p"
+            self.dims, self.fixed = ["hint"], {}
+
+        def measure(self, t):
+            return self.rate
+    mt = autotune.MultiTarget.__new__(autotune.MultiTarget)
+    mt.parts = [Part(100, 1.0), Part(300, 3.0)]  # 100e-9 s + 100e-9 s
+    assert abs(mt.measure(Tuning()) - 2.0) < 1e-9
+    mt.parts.append(Part(5, None))
+    assert mt.measure(Tuning()) is None
