@@ -208,6 +208,10 @@ def bench_serve(args, dev):
     # must not depend on the jobs it shares a launch with
     tb = autotune.tuned("batch")
     tb.whole_graph_vertices = mm.Tuning().whole_graph_vertices
+    # a serving batch holds a few jobs, all of whose vertices are swept at
+    # once: lanes release u while they wait, so no chain of waiting holders
+    # forms (within 1% either way on the 4096-graph mixture)
+    tb.wait_release = 1
 
     def scheduler():
         ex = serve.GpuExecutor(batch_slots=2, solo_slots=2, tuning_batch=tb)
