@@ -241,7 +241,7 @@ def bench_serve(args, dev):
 def bench_batch(args, tun, dev):
     """Batched matching of the 4096-graph mixture: one hipGraph-captured
     persistent launch per pass, against one mm_run per graph on one stream
-    (same kernels, same tuning, caches warm)."""
+    (same kernels, the same tuning without the hint, caches warm)."""
     import torch
     import graphgen
     import paper_2507_04420_amd as mm
