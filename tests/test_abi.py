@@ -5,6 +5,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_2507_04420_amd import _lib
@@ -191,3 +192,37 @@ def test_workspace_bytes_graph():
     assert lib.mm_workspace_bytes_graph(1000, -1, ctypes.byref(t)) == 0
     vtx = (ctypes.c_int64 * 2)(0, 10)
     assert lib.mm_batch_workspace_bytes(1, vtx, ctypes.byref(t)) == 0
+
+
+def _batch_bytes(lib, ns, **kw):
+    t = _lib.mm_tuning()
+    lib.mm_default_tuning(ctypes.byref(t))
+    for k, v in kw.items():
+        setattr(t, k, v)
+    vtx = (ctypes.c_int64 * (len(ns) + 1))(*np.concatenate([[0], np.cumsum(ns)]).tolist())
+    return lib.mm_batch_workspace_bytes(len(ns), vtx, ctypes.byref(t))
+
+
+def test_batch_workspace_short_blocks_and_mesh_room():
+    # host-side plan: a batch too small for 2048 wavefronts of wave_vertices
+    # sources is cut into short blocks whatever wave_vertices says, so its
+    # item table (16 bytes an item) does not depend on it
+    lib = _lib.load()
+    small = [20000, 20000]
+    a = _batch_bytes(lib, small, whole_graph_vertices=0, wave_vertices=2048)
+    b = _batch_bytes(lib, small, whole_graph_vertices=0, wave_vertices=64)
+    assert a == b > 0
+    # a large batch keeps its blocks: longer blocks, fewer items, fewer bytes
+    large = [1 << 21] * 4
+    c = _batch_bytes(lib, large, whole_graph_vertices=0, wave_vertices=2048)
+    d = _batch_bytes(lib, large, whole_graph_vertices=0, wave_vertices=1024)
+    items_c, items_d = 4 * (1 << 21) // 2048, 4 * (1 << 21) // 1024
+    assert d - c >= 16 * (items_d - items_c) - 256
+    # room for mesh blocks: with mesh_wave_vertices shorter than wave_vertices
+    # the plan reserves items for the shorter blocks
+    e = _batch_bytes(lib, large, whole_graph_vertices=0, wave_vertices=2048, mesh_wave_vertices=128)
+    assert e - c >= 16 * (4 * (1 << 21) // 128 - items_c) - 256
+    # graphs swept whole are one item each, however large wave_vertices is
+    f = _batch_bytes(lib, [1000] * 8, wave_vertices=64)
+    g = _batch_bytes(lib, [1000] * 8, wave_vertices=4096)
+    assert f == g
