@@ -5,9 +5,11 @@
 // table of items (graph, first source, source count), each the size of one
 // wavefront block of the single-graph sweep. A persistent grid of wavefronts
 // pops items from a device counter and runs the same sweep_block on each, so
-// a thousand small graphs fill the GPU as well as one large graph does. The
-// per-pass work (state fill, queue reset, persistent sweep, output fix-up)
-// can be captured once into a hipGraph and replayed.
+// a thousand small graphs fill the GPU as well as one large graph does. Graphs
+// swept whole with their states in LDS run first, in a kernel of their own
+// (whole.h); mesh-like members get blocks of their own length with dispersed
+// lanes. The per-pass work (state fill, queue reset, LDS kernel, persistent
+// sweep, output fix-up) can be captured once into a hipGraph and replayed.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

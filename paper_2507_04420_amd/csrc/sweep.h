@@ -31,6 +31,8 @@
 // "continue" on a reserved u, L13's loop on a reserved v) is "stay in this
 // phase and poll again next trip". Reservation chains only wait on higher ids
 // (u < v), so the lane at the top of any chain meets ACC or MCHD and finishes.
+// With wait_release a lane releases u before it waits for v, so no lane waits
+// on a lane that is itself waiting and no chain of holders forms.
 //
 // Long scans (the wavefront tier). When a lane has read `assist_after` ids of
 // its list and more than 2W remain, the whole wavefront reads the next 64 ids
