@@ -180,8 +180,7 @@ def bench_serve(args, dev):
     kinds); small jobs are batched continuously, large ones run alone."""
     import torch
     import graphgen
-    import paper_2507_04420_amd as mm
-    from paper_2507_04420_amd import autotune, serve
+    from paper_2507_04420_amd import serve
 
     t0 = time.perf_counter()
     pool = graphgen.serve_pool(args.serve_pool, seed=args.seed)
@@ -190,12 +189,8 @@ def bench_serve(args, dev):
         sub = pool.member(g)
         off = torch.from_numpy(sub.off).to(dev)
         nbr = torch.from_numpy(sub.nbr).to(dev)
-        # the class's tuned launch parameters, without relabelling: a request
-        # creates its own handle, and relabelling pays off only when a handle
-        # runs many passes
-        t = autotune.tuned(autotune.classify(sub.off))
-        t.relabel = 0
-        graphs.append(serve.ResidentGraph.from_tensors(off, nbr, True, sub.name, tuning=t))
+        # large jobs run with their class's serving tuning (serve.solo_tuning)
+        graphs.append(serve.ResidentGraph.for_serving(off, nbr, sub.off, True, sub.name))
     torch.cuda.synchronize()
     log("serving pool: %d graphs, M=%d, generated and resident in %.1fs" % (
         pool.num_graphs, pool.m, time.perf_counter() - t0))
@@ -204,17 +199,10 @@ def bench_serve(args, dev):
     out = {"pool_graphs": pool.num_graphs, "pool_entries": int(pool.m), "small_edges": 2_000_000,
            "hbm_budget_bytes": int(free // 2), "rates": []}
 
-    # batches keep the library's whole-graph threshold: a small graph's result
-    # must not depend on the jobs it shares a launch with
-    tb = autotune.tuned("batch")
-    tb.whole_graph_vertices = mm.Tuning().whole_graph_vertices
-    # a serving batch holds a few jobs, all of whose vertices are swept at
-    # once: lanes release u while they wait, so no chain of waiting holders
-    # forms (within 1% either way on the 4096-graph mixture)
-    tb.wait_release = 1
-
+    # the executor and tunings the serving tests check (serve.batch_tuning,
+    # serve.solo_tuning)
     def scheduler():
-        ex = serve.GpuExecutor(batch_slots=2, solo_slots=2, tuning_batch=tb)
+        ex = serve.GpuExecutor.for_serving(batch_slots=2, solo_slots=2)
         return serve.Scheduler(ex, hbm_budget=free // 2, small_edges=2_000_000, max_batch=1024,
                                batch_slots=2, solo_slots=2, keep_results=False)
 
@@ -271,10 +259,11 @@ def bench_batch(args, tun, dev):
     ms_batched = ev0.elapsed_time(ev1) / reps
 
     # per-graph launches: one handle per member graph, outputs are views of one
-    # tensor. Each launch spreads its graph over many wavefronts (no whole-graph
-    # items, and mm_run's short blocks for small graphs) and runs no hint (its
-    # fill would be one more launch per graph): its fastest form alone.
-    tun_pg = mm.Tuning(**dict(tun.as_dict(), whole_graph_vertices=0, hint=0))
+    # tensor. Each launch spreads its graph over as many wavefronts as blocks of
+    # 64 sources give (no whole-graph items; min_waves = 2048 shortens every
+    # block of a small graph to 64) and runs no hint (its fill would be one more
+    # launch per graph): its fastest form alone.
+    tun_pg = mm.Tuning(**dict(tun.as_dict(), whole_graph_vertices=0, hint=0, min_waves=2048))
     vtx = mix.vtx_off
     offs, handles = [], []
     out2 = torch.empty(mix.n, dtype=torch.int32, device=dev)

@@ -22,10 +22,15 @@
  *    them, and they must outlive the handle. Workspaces and outputs are
  *    caller-owned device memory. mm_run and mm_batch_run allocate nothing;
  *    the create calls may (tuning.relabel: temporary buffers;
- *    tuning.hub_degree: the hub piece table, kept until destroy). Those
+ *    tuning.hub_degree: the hub piece table, kept until destroy), at most
+ *    mm_create_device_bytes / mm_batch_create_device_bytes bytes. Those
  *    allocations are stream-ordered (hipMallocAsync on the create call's
  *    stream, hipFreeAsync at destroy), so create and destroy never wait for
- *    the whole device; destroy only after the handle's runs have finished.
+ *    the whole device. A run on any stream waits for what its create call
+ *    enqueued, and destroy releases the tables after the handle's last run
+ *    (an event recorded on that run's stream), so a handle may be destroyed
+ *    while its last run is in flight; the caller's own memory (workspace,
+ *    output, CSR) must outlive every run.
  *
  * Graph format (Section II-A): CSR with `offsets` of n+1 entries (int32 or
  * int64, non-decreasing, offsets[0] = 0, offsets[n] = m) and `neighbors` of m
@@ -112,9 +117,8 @@ typedef struct {
                             per vertex (plain byte store) */
   int32_t wg_size;       /* threads per workgroup: 64, 128, 192 or 256 */
   int32_t wave_vertices; /* source vertices handed to one wavefront, >= 64, multiple of 64;
-                            mm_run shortens it for a graph too small to give
-                            2048 wavefronts (not for batches, whose graphs
-                            together fill the GPU) */
+                            shortened for a graph too small to give min_waves
+                            wavefronts (see min_waves) */
   int32_t disperse;      /* 0: a wavefront's lanes take consecutive sources;
                             1: concurrently active lanes of a wavefront take sources
                             wave_vertices/64 apart (for high-locality graphs) */
@@ -174,6 +178,11 @@ typedef struct {
                             so no chain of reservations forms, which on meshes
                             swept by many lanes at once can grow as long as a
                             column. 0: as printed */
+  int32_t min_waves;     /* a graph alone (mm_run) or a batch whose blocked sources
+                            are too few for this many wavefronts of wave_vertices
+                            sources gets shorter blocks, so that about this many
+                            wavefronts share it (never shorter than 64 sources);
+                            0 keeps wave_vertices whatever the size */
   int64_t iter_cap;      /* loop-trip budget per wavefront; 0 = default of
                             65536 + 8 x (neighbour entries of its block);
                             exceeding it raises MM_ERR_NO_PROGRESS */
@@ -215,6 +224,17 @@ size_t mm_workspace_bytes_graph(int64_t n, int64_t m, const mm_tuning* t);
    (NULL = defaults). Returns 0 if n or t is invalid, and for t.relabel = 1,
    whose workspace depends on m (use mm_workspace_bytes_graph). */
 size_t mm_workspace_bytes(int64_t n, const mm_tuning* t);
+
+/* Upper bound of the device memory mm_create allocates by itself for a graph
+   of n vertices and m entries under tuning t (NULL = defaults), beyond the
+   caller's workspace: the hub piece table (24 bytes a piece, kept until
+   mm_destroy; at most m / hub_chunk + m / (hub_degree + 1) pieces) and, with
+   t.relabel, the relabelling's temporaries (freed before mm_create returns;
+   their sort scratch as the device library reports it, or 16n + 64 MiB when
+   no device can be asked). 0 if nothing is allocated or the arguments are
+   invalid. A caller that budgets device memory adds this to the workspace
+   and the output. */
+size_t mm_create_device_bytes(int64_t n, int64_t m, const mm_tuning* t);
 
 /*
  * Creates a handle for one graph.
@@ -278,6 +298,13 @@ typedef struct mm_batch* mm_batch_handle;
 
 /* Workspace bytes for a batch (vtx_off: host). 0 if the arguments are invalid. */
 size_t mm_batch_workspace_bytes(int32_t num_graphs, const int64_t* vtx_off, const mm_tuning* t);
+
+/* Upper bound of the device memory a batch create call allocates by itself
+   (vtx_off: host; M: entries of all graphs together): when hub pieces exist,
+   the work-item table and the piece table, kept until mm_batch_destroy. 0 if
+   nothing is allocated or the arguments are invalid. */
+size_t mm_batch_create_device_bytes(int32_t num_graphs, const int64_t* vtx_off, int64_t M,
+                                    const mm_tuning* t);
 
 /* Creates a batch handle: builds the graph descriptors and the work-item
    table (one item per wavefront block of every graph) in the workspace and

@@ -52,6 +52,7 @@ class mm_tuning(ctypes.Structure):
         ("whole_graph_lds", ctypes.c_int32),
         ("mesh_wave_vertices", ctypes.c_int32),
         ("wait_release", ctypes.c_int32),
+        ("min_waves", ctypes.c_int32),
         ("iter_cap", ctypes.c_int64),
     ]
 
@@ -83,6 +84,7 @@ SIGNATURES = {
     "mm_default_tuning": (None, [ctypes.POINTER(mm_tuning)]),
     "mm_workspace_bytes": (_SZ, [_I64, ctypes.POINTER(mm_tuning)]),
     "mm_workspace_bytes_graph": (_SZ, [_I64, _I64, ctypes.POINTER(mm_tuning)]),
+    "mm_create_device_bytes": (_SZ, [_I64, _I64, ctypes.POINTER(mm_tuning)]),
     "mm_create": (_I32, [_P, _I32, _P, _I64, _I64, _P, _SZ, _U32, ctypes.POINTER(mm_tuning), _P,
                          ctypes.POINTER(_P)]),
     "mm_run": (_I32, [_P, _P, _P]),
@@ -93,6 +95,7 @@ SIGNATURES = {
                              ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "mm_destroy": (None, [_P]),
     "mm_batch_workspace_bytes": (_SZ, [_I32, _P, ctypes.POINTER(mm_tuning)]),
+    "mm_batch_create_device_bytes": (_SZ, [_I32, _P, _I64, ctypes.POINTER(mm_tuning)]),
     "mm_batch_create": (_I32, [_P, _P, _P, _I32, _I64, _P, _SZ, _U32, ctypes.POINTER(mm_tuning), _P,
                                ctypes.POINTER(_P)]),
     "mm_batch_create_list": (_I32, [_P, _P, _P, _P, _I32, _P, _SZ, _U32, ctypes.POINTER(mm_tuning),

@@ -342,16 +342,16 @@ struct BatchLayout {  // byte offsets of the workspace pieces after the control 
 bool plan_layout(int32_t G, const int64_t* vtx_off, const mm_tuning& t, BatchLayout* out) {
   int64_t n_items = 0, st_words = 0, hint_words = 0;
   // sources swept in blocks (graphs not swept whole): too few of them for
-  // kMinWaves wavefronts, and the blocks get shorter, as for a single graph
+  // min_waves wavefronts, and the blocks get shorter, as for a single graph
   int64_t blocked = 0;
   for (int32_t g = 0; g < G; ++g) {
     const int64_t n = vtx_off[g + 1] - vtx_off[g];
-    if (n < 0 || n > INT32_MAX) return false;
+    if (n < 0 || n > mmi::max_vertices(t)) return false;
     if (n > t.whole_graph_vertices) blocked += n;
   }
-  const int64_t wv_main = mmi::short_blocks(blocked, t.wave_vertices);
+  const int64_t wv_main = mmi::short_blocks(blocked, t.wave_vertices, t.min_waves);
   const int64_t wv_mesh =
-      t.mesh_wave_vertices > 0 ? mmi::short_blocks(blocked, t.mesh_wave_vertices) : 0;
+      t.mesh_wave_vertices > 0 ? mmi::short_blocks(blocked, t.mesh_wave_vertices, t.min_waves) : 0;
   for (int32_t g = 0; g < G; ++g) {
     const int64_t n = vtx_off[g + 1] - vtx_off[g];
     // mesh graphs may take shorter blocks: room for the shorter of the two
@@ -400,6 +400,7 @@ struct mm_batch {
   hipGraphExec_t exec = nullptr;
   mmk::HubChunk* chunks = nullptr;  // hub piece table, inside `own`
   void* own = nullptr;  // item and piece tables when hub pieces exist (device, owned)
+  hipEvent_t last_run = nullptr;  // with `own`: recorded after each run, waited for at destroy
 };
 
 namespace {
@@ -591,6 +592,13 @@ mm_status finish_create(std::vector<mmb::GraphDesc>& descs, const std::vector<in
   }
   b->chunks = chunks;
   b->own = own;
+  if (own) {
+    hipError_t e = hipEventCreateWithFlags(&b->last_run, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      mm_batch_destroy(b);
+      return fail(MM_ERR_HIP, "batch event: %s", hipGetErrorString(e));
+    }
+  }
   if (flags & MM_CAPTURE) {
     hipError_t e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
@@ -673,6 +681,27 @@ size_t mm_batch_workspace_bytes(int32_t num_graphs, const int64_t* vtx_off, cons
   return L.total;
 }
 
+size_t mm_batch_create_device_bytes(int32_t num_graphs, const int64_t* vtx_off, int64_t M,
+                                    const mm_tuning* tp) {
+  if (num_graphs < 0 || !vtx_off || M < 0) return 0;
+  mm_tuning t;
+  if (tp) t = *tp; else mm_default_tuning(&t);
+  if (mmi::check_tuning(t) != MM_OK || t.relabel) return 0;
+  BatchLayout L;
+  if (!plan_layout(num_graphs, vtx_off, t, &L)) return 0;
+  bool blocked = false;  // a graph not swept whole: the only kind with pieces
+  for (int32_t g = 0; g < num_graphs && !blocked; ++g)
+    blocked = vtx_off[g + 1] - vtx_off[g] > t.whole_graph_vertices;
+  const int64_t pieces = blocked ? mmi::hub_pieces_bound(M, t.hub_degree, t.hub_chunk) : 0;
+  if (pieces == 0) return 0;
+  // the item table moves to the handle's own allocation, with one item per
+  // run of 64 pieces of a graph (at most pieces / 64 + num_graphs of them),
+  // followed by the piece table
+  const int64_t items = L.n_items + pieces / 64 + num_graphs;
+  return round_up(sizeof(mmb::WorkItem) * (size_t)items, 256) +
+         round_up(sizeof(mmk::HubChunk) * (size_t)pieces, 256);
+}
+
 mm_status mm_batch_create(const int64_t* offsets_cat, const int32_t* neighbors_cat,
                           const int64_t* vtx_off, int32_t num_graphs, int64_t M, void* workspace,
                           size_t workspace_bytes, uint32_t flags, const mm_tuning* tuning,
@@ -690,7 +719,8 @@ mm_status mm_batch_create(const int64_t* offsets_cat, const int32_t* neighbors_c
     if (vtx_off[g + 1] < vtx_off[g] || vtx_off[g + 1] - vtx_off[g] > INT32_MAX)
       return fail(MM_ERR_INVALID_ARG, "vtx_off must be non-decreasing with graphs of < 2^31 vertices");
   BatchLayout lay;
-  plan_layout(num_graphs, vtx_off, t, &lay);
+  if (!plan_layout(num_graphs, vtx_off, t, &lay))
+    return fail(MM_ERR_INVALID_ARG, "a graph has more vertices than the layout allows");
   std::vector<int64_t> vtx(vtx_off, vtx_off + num_graphs + 1);
   std::vector<mmb::GraphDesc> descs((size_t)num_graphs);
   for (int32_t g = 0; g < num_graphs; ++g) {
@@ -732,7 +762,8 @@ mm_status mm_batch_create_list(const int64_t* const* offsets, const int32_t* con
     d.v0 = vtx[g];
   }
   BatchLayout lay;
-  plan_layout(num_graphs, vtx.data(), t, &lay);
+  if (!plan_layout(num_graphs, vtx.data(), t, &lay))
+    return fail(MM_ERR_INVALID_ARG, "a graph has more vertices than the layout allows");
   return finish_create(descs, vtx, lay, t, static_cast<uint8_t*>(workspace), workspace_bytes,
                        flags, static_cast<hipStream_t>(stream), nullptr, nullptr, 0, out);
 }
@@ -762,10 +793,12 @@ mm_status mm_batch_run(mm_batch_handle b, void* stream, int32_t* match_out) {
       HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
     }
     HIP_TRY(hipGraphLaunch(b->exec, s));
+    if (b->last_run) HIP_TRY(hipEventRecord(b->last_run, s));
     return MM_OK;
   }
   hipError_t e = mmb::enqueue_pass(b->plan, s);
   if (e != hipSuccess) return fail(MM_ERR_HIP, "batch launch failed: %s", hipGetErrorString(e));
+  if (b->last_run) HIP_TRY(hipEventRecord(b->last_run, s));
   return MM_OK;
 }
 
@@ -799,6 +832,11 @@ int64_t mm_batch_items(mm_batch_handle b) { return b ? b->plan.n_items + b->plan
 void mm_batch_destroy(mm_batch_handle b) {
   if (!b) return;
   drop_graph(b);
+  // the tables are released, stream-ordered, after the last run that reads them
+  if (b->last_run) {
+    hipStreamWaitEvent(nullptr, b->last_run, 0);
+    hipEventDestroy(b->last_run);
+  }
   mmi::free_owned(b->own);
   if (b->cap_stream) hipStreamDestroy(b->cap_stream);
   delete b;

@@ -192,7 +192,8 @@ hipError_t build_hub_chunks(const void* off, int off64, int64_t n, int64_t hub_d
 
 void free_owned(void* p) {
   // stream-ordered on the null stream: no wait for the whole device; the
-  // owner has already waited for every pass that read the memory
+  // owner first makes the null stream wait for the last pass that reads the
+  // memory (an event recorded on that pass's stream)
   if (p) hipFreeAsync(p, nullptr);
 }
 

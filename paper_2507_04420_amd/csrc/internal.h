@@ -17,6 +17,14 @@ inline size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 // Validates a tuning struct (wg_size, wave_vertices, layout, flags ranges).
 mm_status check_tuning(const mm_tuning& t);
 
+// Largest vertex count a graph may have under tuning t: the word layout with
+// the two-phase protocol keeps ACC = INT32_MAX and RSVD = INT32_MAX - 1 in the
+// same word as a mate id, so its ids must stay below INT32_MAX - 1.
+inline int64_t max_vertices(const mm_tuning& t) {
+  return (t.layout == MM_LAYOUT_U32 && t.protocol == MM_PROTOCOL_TWO_PHASE) ? (int64_t)INT32_MAX - 1
+                                                                            : (int64_t)INT32_MAX;
+}
+
 // Workspace pieces after the control block: packed states (U8 layout only),
 // then the matched hint (if enabled), each rounded to 256 bytes.
 size_t state_bytes(int64_t n, const mm_tuning& t);
@@ -39,6 +47,16 @@ struct RelabelView {
   int64_t n_isolated;  // new ids 0 .. n_isolated-1 have no entries
 };
 size_t relabel_bytes(int64_t n, int64_t m);
+// Upper bound of the device memory build_relabel allocates for its own
+// temporaries (freed before it returns).
+size_t relabel_temp_bytes(int64_t n);
+// Upper bound of the hub pieces of a graph of m entries: every list longer
+// than hub_degree gives ceil(d / chunk) <= d / chunk + 1 pieces, and there are
+// at most m / (hub_degree + 1) such lists.
+inline int64_t hub_pieces_bound(int64_t m, int64_t hub_degree, int64_t chunk) {
+  if (hub_degree <= 0 || m <= hub_degree) return 0;
+  return m / chunk + m / (hub_degree + 1);
+}
 hipError_t build_relabel(const void* off, int off64, const int32_t* nbr, int64_t n, int64_t m,
                          uint8_t* region, RelabelView* view, hipStream_t s);
 
@@ -56,13 +74,13 @@ hipError_t build_hub_chunks(const void* off, int off64, int64_t n, int64_t hub_d
 // Stream-ordered release of memory a handle owns (no wait for the device).
 void free_owned(void* p);
 
-// A sweep too small to give this many wavefronts of wave_vertices sources
-// gets shorter blocks (single graphs and batches alike), so that at least
-// this many wavefronts (8 per CU) share it and its latency.
-constexpr int64_t kMinWaves = 2048;
-inline int64_t short_blocks(int64_t sources, int64_t wave_vertices) {
-  if (sources >= kMinWaves * wave_vertices) return wave_vertices;
-  const int64_t w = (sources / kMinWaves + 63) / 64 * 64;
+// A sweep too small to give min_waves wavefronts of wave_vertices sources gets
+// shorter blocks (single graphs and batches alike), so that about min_waves
+// wavefronts share it and its latency; never shorter than 64 sources.
+// min_waves = 0 keeps wave_vertices whatever the size.
+inline int64_t short_blocks(int64_t sources, int64_t wave_vertices, int64_t min_waves) {
+  if (min_waves <= 0 || sources >= min_waves * wave_vertices) return wave_vertices;
+  const int64_t w = (sources / min_waves + 63) / 64 * 64;
   return w < 64 ? 64 : w;
 }
 

@@ -71,6 +71,7 @@ mm_status check_tuning(const mm_tuning& t) {
     return fail(MM_ERR_INVALID_ARG, "tuning.whole_graph_lds must be 0 or 1");
   if (t.wait_release != 0 && t.wait_release != 1)
     return fail(MM_ERR_INVALID_ARG, "tuning.wait_release must be 0 or 1");
+  if (t.min_waves < 0) return fail(MM_ERR_INVALID_ARG, "tuning.min_waves must be >= 0");
   if (t.mesh_wave_vertices < 0 || t.mesh_wave_vertices % 64)
     return fail(MM_ERR_INVALID_ARG, "tuning.mesh_wave_vertices must be 0 or a positive multiple of 64");
   return MM_OK;
@@ -284,6 +285,11 @@ struct mm_graph {
   TimingRing* timing;
   mmk::HubChunk* chunks = nullptr;  // hub tier table (device, owned), or null
   int64_t n_chunks = 0;
+  // with a hub table: recorded on the create stream once the table is
+  // filled (every run waits for it), and on the run stream after each run
+  // (the destroy call orders the table's release after it)
+  hipEvent_t table_ready = nullptr;
+  hipEvent_t last_run = nullptr;
   bool relabel;         // sweep the graph relabelled by degree (relabel.hip)
   mmi::RelabelView rl;  // its arrays, in the workspace
   int32_t* rl_state;    // word-layout states in the new ids (relabel only)
@@ -331,7 +337,7 @@ SweepParams make_params(const mm_graph* g) {
     p.disperse = 1;
   } else {
     // a small graph alone on the GPU: shorter blocks
-    p.wave_vertices = mmi::short_blocks(ns, p.wave_vertices);
+    p.wave_vertices = mmi::short_blocks(ns, p.wave_vertices, g->tun.min_waves);
   }
   return p;
 }
@@ -527,13 +533,16 @@ void mm_default_tuning(mm_tuning* t) {
   t->hub_degree = 4096;
   t->hub_chunk = 256;
   t->whole_graph_lds = 1;
+  // a small graph alone keeps about 32 wavefronts in flight: fewer sources
+  // racing at once, so repeated passes give matchings of nearly the same size
+  t->min_waves = 32;
   t->iter_cap = 0;
 }
 
 size_t mm_workspace_bytes_graph(int64_t n, int64_t m, const mm_tuning* tp) {
   mm_tuning t;
   if (tp) t = *tp; else mm_default_tuning(&t);
-  if (n < 0 || n > INT32_MAX || m < 0 || check_tuning(t) != MM_OK) return 0;
+  if (n < 0 || m < 0 || check_tuning(t) != MM_OK || n > mmi::max_vertices(t)) return 0;
   size_t b = kCtrlBytes + mmi::state_bytes(n, t) + mmi::hint_bytes(n, t);
   if (t.relabel) b += mmi::round_up(sizeof(int32_t) * (size_t)n, 256) + mmi::relabel_bytes(n, m);
   return b;
@@ -544,6 +553,21 @@ size_t mm_workspace_bytes(int64_t n, const mm_tuning* tp) {
   if (tp) t = *tp; else mm_default_tuning(&t);
   if (t.relabel) return 0;  // the relabelled copy depends on m
   return mm_workspace_bytes_graph(n, 0, &t);
+}
+
+size_t mm_create_device_bytes(int64_t n, int64_t m, const mm_tuning* tp) {
+  mm_tuning t;
+  if (tp) t = *tp; else mm_default_tuning(&t);
+  if (n < 0 || n > INT32_MAX || m < 0 || check_tuning(t) != MM_OK) return 0;
+  size_t b = 0;
+  // the hub table (kept until destroy); a graph swept whole gets none
+  if (n > t.whole_graph_vertices) {
+    const int64_t pieces = mmi::hub_pieces_bound(m, t.hub_degree, t.hub_chunk);
+    if (pieces > 0) b += mmi::round_up(sizeof(mmk::HubChunk) * (size_t)pieces, 256);
+  }
+  // the relabelling's temporaries (freed before create returns)
+  if (t.relabel) b += mmi::relabel_temp_bytes(n);
+  return b;
 }
 
 mm_status mm_create(const void* offsets, mm_offset_type off_type, const int32_t* neighbors,
@@ -569,6 +593,9 @@ mm_status mm_create(const void* offsets, mm_offset_type off_type, const int32_t*
   if (tuning) t = *tuning; else mm_default_tuning(&t);
   mm_status st = check_tuning(t);
   if (st != MM_OK) return st;
+  if (n > mmi::max_vertices(t))
+    return fail(MM_ERR_INVALID_ARG, "n = %lld: the word layout with the two-phase protocol "
+                "takes at most 2^31-2 vertices", (long long)n);
   const size_t need = mm_workspace_bytes_graph(n, m, &t);
   if (workspace_bytes < need)
     return fail(MM_ERR_OUT_OF_MEMORY, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
@@ -640,23 +667,31 @@ mm_status mm_create(const void* offsets, mm_offset_type off_type, const int32_t*
       delete g;
       return fail(MM_ERR_HIP, "building the hub table failed: %s", hipGetErrorString(e));
     }
-    if (g->n_chunks > 0) g->lazy = false;  // a piece of a list cannot finalise its source
+    if (g->n_chunks > 0) {
+      g->lazy = false;  // a piece of a list cannot finalise its source
+      hipError_t e1 = hipEventCreateWithFlags(&g->table_ready, hipEventDisableTiming);
+      if (e1 == hipSuccess) e1 = hipEventCreateWithFlags(&g->last_run, hipEventDisableTiming);
+      if (e1 == hipSuccess) e1 = hipEventRecord(g->table_ready, s);
+      if (e1 != hipSuccess) {
+        if (g->table_ready) hipEventDestroy(g->table_ready);
+        if (g->last_run) hipEventDestroy(g->last_run);
+        mmi::free_owned(g->chunks);
+        delete g;
+        return fail(MM_ERR_HIP, "hub table events: %s", hipGetErrorString(e1));
+      }
+    }
   }
   g->device = dev;
   g->timing = nullptr;
   if (flags & MM_TIMING) {
     g->timing = new (std::nothrow) TimingRing();
     if (!g->timing) {
-      mmi::free_owned(g->chunks);
-      delete g;
+      mm_destroy(g);
       return fail(MM_ERR_OUT_OF_MEMORY, "host allocation of the timing ring failed");
     }
     hipError_t e = g->timing->init();
     if (e != hipSuccess) {
-      g->timing->destroy();
-      delete g->timing;
-      mmi::free_owned(g->chunks);
-      delete g;
+      mm_destroy(g);
       return fail(MM_ERR_HIP, "hipEventCreate failed: %s", hipGetErrorString(e));
     }
   }
@@ -671,6 +706,8 @@ mm_status mm_run(mm_handle g, void* stream, int32_t* match_out) {
   hipStream_t s = static_cast<hipStream_t>(stream);
   const bool stats = (g->flags & MM_STATS) != 0;
   hipError_t e;
+  // the hub table was filled on the create call's stream
+  if (g->table_ready) HIP_TRY(hipStreamWaitEvent(s, g->table_ready, 0));
   if (g->relabel)
     e = stats ? run_relabelled<true>(g, match_out, s) : run_relabelled<false>(g, match_out, s);
   else if (g->off64)
@@ -678,6 +715,7 @@ mm_status mm_run(mm_handle g, void* stream, int32_t* match_out) {
   else
     e = stats ? run_typed<int32_t, true>(g, match_out, s) : run_typed<int32_t, false>(g, match_out, s);
   if (e != hipSuccess) return fail(MM_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e));
+  if (g->last_run) HIP_TRY(hipEventRecord(g->last_run, s));
   return MM_OK;
 }
 
@@ -740,7 +778,11 @@ mm_status mm_get_timing(mm_handle g, int64_t* count, double* total_ms, double* m
 
 void mm_destroy(mm_handle g) {
   if (!g) return;
+  // the table is released, stream-ordered, after the last run that reads it
+  if (g->last_run) hipStreamWaitEvent(nullptr, g->last_run, 0);
   mmi::free_owned(g->chunks);
+  if (g->table_ready) hipEventDestroy(g->table_ready);
+  if (g->last_run) hipEventDestroy(g->last_run);
   if (g->timing) {
     g->timing->destroy();
     delete g->timing;

@@ -187,6 +187,28 @@ hipError_t build_typed(const OffT* off, const int32_t* nbr, int64_t n, int64_t* 
 
 namespace mmi {
 
+size_t relabel_temp_bytes(int64_t n) {
+  if (n <= 0) return 0;
+  // the sort's and the scan's own scratch, as rocPRIM reports it for these
+  // sizes; without a device to ask, twice the sorted pairs plus 64 MiB
+  size_t sort_bytes = 0, scan_bytes = 0;
+  uint32_t* k = nullptr;
+  int32_t* o = nullptr;
+  int64_t* d = nullptr;
+  auto ids = rocprim::counting_iterator<int32_t>(0);
+  hipError_t e = rocprim::radix_sort_pairs(nullptr, sort_bytes, k, k, ids, o, (size_t)n, 0, 7,
+                                           (hipStream_t)0);
+  if (e == hipSuccess)
+    e = rocprim::exclusive_scan(nullptr, scan_bytes, d, d, (int64_t)0, (size_t)(n + 1),
+                                rocprim::plus<int64_t>(), (hipStream_t)0);
+  const size_t tmp = e == hipSuccess ? (sort_bytes > scan_bytes ? sort_bytes : scan_bytes)
+                                     : 16 * (size_t)n + ((size_t)64 << 20);
+  // keys, sorted keys, inverse map, degrees in new ids, the isolated count,
+  // and the scratch, each a separate stream-ordered allocation
+  return round_up(4 * (size_t)n, 256) * 3 + round_up(8 * (size_t)(n + 1), 256) + 256 +
+         round_up(tmp, 256);
+}
+
 size_t relabel_bytes(int64_t n, int64_t m) {
   return round_up(sizeof(int64_t) * (size_t)(n + 1), 256) + round_up(sizeof(int32_t) * (size_t)n, 256) +
          round_up(sizeof(int32_t) * (size_t)m, 256);

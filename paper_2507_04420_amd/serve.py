@@ -46,6 +46,59 @@ class ResidentGraph:
     def from_tensors(cls, off, nbr, symmetric=True, name="", tuning=None):
         return cls(off, nbr, off.numel() - 1, nbr.numel(), symmetric, name, tuning)
 
+    @classmethod
+    def for_serving(cls, off, nbr, off_host, symmetric=True, name=""):
+        """A resident graph that runs alone with its class's serving tuning
+        (see solo_tuning); off_host: the offsets as a host array."""
+        return cls.from_tensors(off, nbr, symmetric, name, solo_tuning(off_host))
+
+
+def solo_tuning(off_host):
+    """The tuning a large job runs alone with: the stored entry of its graph
+    class (autotune.classify), without relabelling. A request creates its own
+    handle and runs one pass, and relabelling pays off only for a handle that
+    runs many. The classes a request can fall in below 2^25 vertices are
+    tuned under the autotuner's spread limit, so that a job's result alone and
+    in the mix stay within the serving tolerance."""
+    from . import autotune
+    t = autotune.tuned(autotune.classify(np.asarray(off_host)))
+    t.relabel = 0
+    return t
+
+
+def batch_tuning():
+    """The tuning of the list batches small jobs are coalesced into: the
+    stored batch entry, with the library's whole-graph threshold (a small
+    graph's result must not depend on the jobs it shares a launch with) and
+    lanes that release u while they wait (a serving batch holds a few jobs,
+    all of whose vertices are swept at once, so that no chain of waiting
+    holders forms)."""
+    from . import Tuning, autotune
+    t = autotune.tuned("batch")
+    t.whole_graph_vertices = Tuning().whole_graph_vertices
+    t.wait_release = 1
+    return t
+
+
+def request_footprint(lib, n: int, m: int, tuning, route: str) -> int:
+    """Device bytes a request holds while admitted: its mate output, the
+    workspace it alone would need (with the relabelled copy when the tuning
+    asks for one) and everything the create call allocates by itself (hub
+    piece table, relabelling temporaries; batches: item and piece tables),
+    as upper bounds the library reports. The CSR is already resident."""
+    ct = tuning.to_c()
+    if route == "solo":
+        ws = lib.mm_workspace_bytes_graph(n, m, _byref(ct))
+        extra = lib.mm_create_device_bytes(n, m, _byref(ct))
+    else:
+        vtx = np.array([0, n], dtype=np.int64)
+        ws = lib.mm_batch_workspace_bytes(1, _ptr(vtx), _byref(ct))
+        extra = lib.mm_batch_create_device_bytes(1, _ptr(vtx), m, _byref(ct))
+    if ws == 0:
+        raise ValueError("the library rejects n=%d, m=%d under this tuning" % (n, m))
+    # + the 256 bytes the binding adds to align the workspace
+    return int(ws) + int(extra) + 256 + 4 * n
+
 
 @dataclass
 class Request:
@@ -203,19 +256,17 @@ class GpuExecutor:
         self.tuning_solo = tuning_solo if tuning_solo is not None else Tuning.default()
         self._lib = _lib.load()
 
+    @classmethod
+    def for_serving(cls, batch_slots=2, solo_slots=2, device="cuda") -> "GpuExecutor":
+        """The executor the serving benchmark runs: batch_tuning() for the
+        batches; large jobs run with their graph's own tuning
+        (ResidentGraph.for_serving)."""
+        return cls(batch_slots, solo_slots, tuning_batch=batch_tuning(), device=device)
+
     def footprint(self, req, route) -> int:
-        """Device bytes the request holds while admitted: its mate output plus
-        the workspace it alone would need (state words, hint bits, control
-        block, descriptors and work items)."""
-        n = req.graph.n
-        if route == "solo":
-            ct = (req.graph.tuning or self.tuning_solo).to_c()
-            ws = self._lib.mm_workspace_bytes(n, _byref(ct))
-        else:
-            ct = self.tuning_batch.to_c()
-            vtx = np.array([0, n], dtype=np.int64)
-            ws = self._lib.mm_batch_workspace_bytes(1, _ptr(vtx), _byref(ct))
-        return int(ws) + 256 + 4 * n
+        """See request_footprint."""
+        t = (req.graph.tuning or self.tuning_solo) if route == "solo" else self.tuning_batch
+        return request_footprint(self._lib, req.graph.n, req.graph.m, t, route)
 
     def launch(self, route, reqs, slot):
         from . import Batch, Graph

@@ -209,9 +209,16 @@ def test_batch_workspace_short_blocks_and_mesh_room():
     # item table (16 bytes an item) does not depend on it
     lib = _lib.load()
     small = [20000, 20000]
-    a = _batch_bytes(lib, small, whole_graph_vertices=0, wave_vertices=2048)
-    b = _batch_bytes(lib, small, whole_graph_vertices=0, wave_vertices=64)
+    a = _batch_bytes(lib, small, whole_graph_vertices=0, wave_vertices=2048, min_waves=2048)
+    b = _batch_bytes(lib, small, whole_graph_vertices=0, wave_vertices=64, min_waves=2048)
     assert a == b > 0
+    # with about 32 wavefronts (the default) the 40000 sources take blocks of
+    # 1280: 32 items instead of 626
+    a32 = _batch_bytes(lib, small, whole_graph_vertices=0, wave_vertices=2048, min_waves=32)
+    assert a32 == a - 256 * ((626 * 16 + 255) // 256 - (32 * 16 + 255) // 256)
+    # min_waves = 0 never shortens
+    z = _batch_bytes(lib, small, whole_graph_vertices=0, wave_vertices=2048, min_waves=0)
+    assert z <= a32
     # a large batch keeps its blocks: longer blocks, fewer items, fewer bytes
     large = [1 << 21] * 4
     c = _batch_bytes(lib, large, whole_graph_vertices=0, wave_vertices=2048)

@@ -57,15 +57,55 @@ def test_tuned_lookup(tmp_path, monkeypatch):
 
 
 def test_classify(monkeypatch):
-    assert autotune.classify(graphgen.grid(50, 60).off) == "grid_mid"
-    assert autotune.classify(graphgen.er(20000, 16, seed=1).off) == "er"
-    assert autotune.classify(graphgen.rmat(16, seed=1).off) == "rmat_mid"
-    # the vertex count alone decides mid against large
+    # below SMALL_VERTICES every kind is "_small"
+    assert autotune.classify(graphgen.grid(50, 60).off) == "grid_small"
+    assert autotune.classify(graphgen.er(20000, 16, seed=1).off) == "er_small"
+    assert autotune.classify(graphgen.rmat(16, seed=1).off) == "rmat_small"
+    assert autotune.classify(graphgen.rmat(18, 8, seed=1).off) == "rmat_mid"
+    assert autotune.classify(graphgen.grid(512, 512).off) == "grid_mid"
+    # the vertex count alone decides small, mid and large
+    monkeypatch.setattr(autotune, "SMALL_VERTICES", 2000)
     monkeypatch.setattr(autotune, "MID_VERTICES", 3000)
     assert autotune.classify(graphgen.grid(50, 60).off) == "grid"
     assert autotune.classify(graphgen.grid(50, 59).off) == "grid_mid"
+    assert autotune.classify(graphgen.grid(40, 49).off) == "grid_small"
     assert autotune.classify(graphgen.rmat(16, seed=1).off) == "rmat"
     assert autotune.classify(graphgen.er(20000, 16, seed=1).off) == "er"
+    assert autotune.classify(graphgen.er(1500, 8, seed=1).off) == "er_small"
+
+
+def test_small_class_without_entry_takes_the_defaults(tmp_path, monkeypatch):
+    monkeypatch.setattr(autotune, "TUNED_DIR", str(tmp_path))
+    doc = {"device": "dev_3cu", "classes": {"rmat": {"tuning": dict(Tuning().as_dict(), wave_vertices=64)}}}
+    (tmp_path / "dev_3cu.json").write_text(json.dumps(doc))
+    assert autotune.tuned("rmat_small", key="dev_3cu") == Tuning.default()
+
+
+def test_search_falls_back_to_fewer_waves_in_flight():
+    # a target that only accepts shapes with at most 16 wavefronts of a small
+    # graph in flight: the search starts from the first conservative shape
+    class Reproducible(FakeTarget):
+        def measure(self, t):
+            if t.min_waves == 0 or t.min_waves > 16:
+                return None
+            return super().measure(t)
+    r = autotune.search(Reproducible(), passes=1, log=lambda s: None)
+    assert r["tuning"]["min_waves"] <= 16 and r["default_objective"] is not None
+
+
+def test_search_restarts_from_defaults_when_the_start_is_rejected():
+    # a stored entry that fails (here: a layout the target rejects) is replaced
+    # by the library defaults as the starting point
+    r = autotune.search(FakeTarget(bad_layout=_lib.MM_LAYOUT_U2), start=Tuning(layout=_lib.MM_LAYOUT_U2),
+                        passes=1, log=lambda s: None)
+    assert r["default_objective"] is not None
+    assert r["tuning"]["layout"] != _lib.MM_LAYOUT_U2
+
+
+def test_spread_limit_is_a_tenth_of_the_serving_tolerance():
+    # one tenth of the 1% alone-vs-mix tolerance
+    assert autotune.SPREAD_LIMIT == 0.001
+    assert set(autotune.REPRODUCIBLE) >= {"rmat_small", "grid_small", "er_small", "rmat_mid", "grid_mid"}
 
 
 def test_mid_class_falls_back_to_its_kind(tmp_path, monkeypatch):

@@ -361,13 +361,36 @@ def test_mesh_members_get_short_blocks():
 
 
 def test_small_batch_gets_short_blocks():
-    # too few sources for 2048 wavefronts of wave_vertices: blocks of 64
+    # too few sources for min_waves = 2048 wavefronts of wave_vertices: blocks of 64
     parts = [graphgen.er(20000, 8, seed=5), graphgen.rmat(14, 8, seed=5)]
     dev = [(torch.from_numpy(p.off.astype(np.int64)).cuda(), torch.from_numpy(p.nbr).cuda())
            for p in parts]
     b = mm.Batch.from_list(dev, symmetric=True, validate=True,
-                           tuning=mm.Tuning(whole_graph_vertices=0, wave_vertices=2048))
+                           tuning=mm.Tuning(whole_graph_vertices=0, wave_vertices=2048,
+                                            min_waves=2048))
     assert b.items == sum((p.n + 63) // 64 for p in parts)
+    out = b.run()
+    b.sync()
+    mate = out.cpu().numpy()
+    for k, p in enumerate(parts):
+        c = oracle.check(p, mate[int(b.vtx_off[k]):int(b.vtx_off[k + 1])])
+        assert c.violations == 0, (k, c)
+    b.close()
+
+
+def test_small_batch_keeps_about_min_waves_wavefronts():
+    # the default min_waves = 32: the 36384 blocked sources take blocks of
+    # 1152 (about 32 wavefronts), not of 64
+    parts = [graphgen.er(20000, 8, seed=5), graphgen.rmat(14, 8, seed=5)]
+    dev = [(torch.from_numpy(p.off.astype(np.int64)).cuda(), torch.from_numpy(p.nbr).cuda())
+           for p in parts]
+    t = mm.Tuning(whole_graph_vertices=0, wave_vertices=2048)
+    assert t.min_waves == 32
+    b = mm.Batch.from_list(dev, symmetric=True, validate=True, tuning=t)
+    blocked = sum(p.n for p in parts)
+    w = (blocked // 32 + 63) // 64 * 64
+    assert w == 1152
+    assert b.items == sum((p.n + w - 1) // w for p in parts)
     out = b.run()
     b.sync()
     mate = out.cpu().numpy()

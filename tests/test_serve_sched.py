@@ -146,3 +146,94 @@ def test_run_trace_with_simulated_clock():
     comps, wall = run_trace(s, reqs, clock=tick)
     assert len(comps) == 20 and all(isinstance(c, Completion) for c in comps)
     assert wall > 0.019
+
+
+def _lib_or_skip():
+    from paper_2507_04420_amd import _lib
+    return _lib.load()
+
+
+def test_footprint_covers_a_relabelled_copy():
+    # a relabel-tuned request holds the relabelled CSR (int64 offsets, the
+    # id map, m ids) and its states in the workspace, plus its output
+    import ctypes
+    from paper_2507_04420_amd import Tuning
+    from paper_2507_04420_amd.serve import request_footprint
+    lib = _lib_or_skip()
+    n, m = 100_000, 1_600_000
+    t = Tuning(relabel=1)
+    fp = request_footprint(lib, n, m, t, "solo")
+    relabelled = 8 * (n + 1) + 4 * n + 4 * m + 4 * n   # offsets, map, ids, states
+    assert fp >= relabelled + 4 * n
+    # the create call's own temporaries (degree keys, sorted keys, inverse
+    # map, degrees in new ids) are counted too
+    ct = t.to_c()
+    assert lib.mm_create_device_bytes(n, m, ctypes.byref(ct)) >= 20 * n
+    assert fp >= lib.mm_workspace_bytes_graph(n, m, ctypes.byref(ct)) + 20 * n + 4 * n
+    # the n-only size cannot know the copy: it reports 0, never too little
+    assert lib.mm_workspace_bytes(n, ctypes.byref(ct)) == 0
+
+
+def test_footprint_covers_the_hub_table():
+    # every list longer than hub_degree gives ceil(d / hub_chunk) pieces of
+    # 24 bytes each, kept by the handle; the bound covers any degree sequence
+    import ctypes
+    import graphgen
+    from paper_2507_04420_amd import Tuning
+    from paper_2507_04420_amd.serve import request_footprint
+    lib = _lib_or_skip()
+    g = graphgen.rmat(16, seed=3)
+    deg = np.diff(g.off)
+    for hd, chunk in ((4096, 256), (64, 16), (8, 1)):
+        t = Tuning(hub_degree=hd, hub_chunk=chunk, whole_graph_vertices=0)
+        pieces = int(sum((d + chunk - 1) // chunk for d in deg if d > hd))
+        ct = t.to_c()
+        extra = lib.mm_create_device_bytes(g.n, g.m, ctypes.byref(ct))
+        assert extra >= 24 * pieces, (hd, chunk, extra, pieces)
+        fp = request_footprint(lib, g.n, g.m, t, "solo")
+        assert fp >= lib.mm_workspace_bytes_graph(g.n, g.m, ctypes.byref(ct)) + 24 * pieces + 4 * g.n
+    # no list can be long: nothing is allocated
+    ct = Tuning(hub_degree=4096).to_c()
+    assert lib.mm_create_device_bytes(1000, 4000, ctypes.byref(ct)) == 0
+
+
+def test_batch_footprint_covers_items_and_pieces():
+    import ctypes
+    import graphgen
+    from paper_2507_04420_amd import Tuning
+    from paper_2507_04420_amd.serve import request_footprint
+    lib = _lib_or_skip()
+    g = graphgen.rmat(15, seed=4)
+    deg = np.diff(g.off)
+    t = Tuning(hub_degree=32, hub_chunk=8, whole_graph_vertices=0)
+    pieces = int(sum((d + 7) // 8 for d in deg if d > 32))
+    vtx = np.array([0, g.n], dtype=np.int64)
+    ct = t.to_c()
+    ws = lib.mm_batch_workspace_bytes(1, ctypes.c_void_p(vtx.ctypes.data), ctypes.byref(ct))
+    extra = lib.mm_batch_create_device_bytes(1, ctypes.c_void_p(vtx.ctypes.data), g.m, ctypes.byref(ct))
+    assert extra >= 24 * pieces + 16 * (pieces // 64)
+    assert request_footprint(lib, g.n, g.m, t, "batch") == ws + extra + 256 + 4 * g.n
+    # graphs swept whole get no pieces
+    t2 = Tuning(hub_degree=32, hub_chunk=8, whole_graph_vertices=1 << 20)
+    ct2 = t2.to_c()
+    assert lib.mm_batch_create_device_bytes(1, ctypes.c_void_p(vtx.ctypes.data), g.m,
+                                            ctypes.byref(ct2)) == 0
+
+
+def test_two_phase_word_layout_rejects_the_sentinel_ids():
+    # ACC = INT32_MAX and RSVD = INT32_MAX - 1 share the word with mate ids:
+    # at most 2^31 - 2 vertices, so that no id equals RSVD
+    import ctypes
+    from paper_2507_04420_amd import Tuning, _lib
+    lib = _lib_or_skip()
+    two = Tuning(layout=_lib.MM_LAYOUT_U32, protocol=_lib.MM_PROTOCOL_TWO_PHASE).to_c()
+    cas = Tuning(layout=_lib.MM_LAYOUT_U32, protocol=_lib.MM_PROTOCOL_CAS).to_c()
+    big = (1 << 31) - 1
+    assert lib.mm_workspace_bytes_graph(big, 0, ctypes.byref(two)) == 0
+    assert lib.mm_workspace_bytes_graph(big - 1, 0, ctypes.byref(two)) > 0
+    assert lib.mm_workspace_bytes_graph(big, 0, ctypes.byref(cas)) > 0
+    h = ctypes.c_void_p()
+    st = lib.mm_create(ctypes.c_void_p(256), _lib.MM_OFF_I64, ctypes.c_void_p(256), big, 0,
+                       ctypes.c_void_p(256), 1 << 40, 0, ctypes.byref(two), None, ctypes.byref(h))
+    assert st == _lib.MM_ERR_INVALID_ARG and not h.value
+    assert b"2^31-2" in lib.mm_last_error()
