@@ -266,6 +266,40 @@ mm_status mm_run(mm_handle h, void* stream, int32_t* match_out);
    of this handle (MM_ERR_NO_PROGRESS) and clears it. */
 mm_status mm_sync(mm_handle h, void* stream);
 
+/* Bytes of the library's static device scratch (mm_run_static). */
+#define MM_STATIC_SCRATCH_BYTES ((size_t)8 << 20)
+
+/*
+ * mm_create + mm_run in one call that allocates nothing and takes no
+ * workspace, for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc). The
+ * pass is the same as mm_run's, with the same kernels; what a workspace would
+ * hold lives in a static device array of MM_STATIC_SCRATCH_BYTES that the
+ * library keeps on every device it runs on until the process ends: a 4 KiB
+ * control block, then the packed states (tuning.layout U8: n bytes, U2: n/4;
+ * the word layout keeps its states in match_out), the matched hint (n/8 or n
+ * bytes), and the hub piece table (24 bytes per piece, sized for
+ * m / hub_chunk + m / (hub_degree + 1) pieces). A graph and tuning that need
+ * more return MM_ERR_OUT_OF_MEMORY before anything is enqueued (the default
+ * tuning needs only the control block and the piece table: up to about 8.5e7
+ * entries; hub_degree = 0 needs no piece table).
+ *  offsets, off_type, neighbors, n, m   as for mm_create (borrowed, device)
+ *  flags      MM_SYMMETRIC only (no device validation, counters or timing)
+ *  tuning     host, NULL = defaults; tuning.relabel is not supported
+ *  match_out  device, n int32, caller-owned: the mate array, as mm_run's
+ *  status_out device, one uint32, caller-owned, may be NULL: set to 0 by the
+ *             pass, then to 1 if a wavefront exceeded its loop-trip budget
+ *             (the condition mm_sync reports as MM_ERR_NO_PROGRESS)
+ * Everything is enqueued on `stream` (kernels only, no copies, memsets or
+ * waits), so the call can be captured into a HIP graph. Every call on a device
+ * uses that device's one scratch array and leaves its contents behind (each
+ * call clears what must start at zero): calls that overlap on one device race,
+ * so the caller orders them (one stream, or events).
+ */
+mm_status mm_run_static(const void* offsets, mm_offset_type off_type, const int32_t* neighbors,
+                        int64_t n, int64_t m, uint32_t flags, const mm_tuning* tuning, void* stream,
+                        int32_t* match_out, uint32_t* status_out);
+
 /* Waits for `stream` and copies the counters accumulated since the last
    mm_reset_stats (MM_STATS handles only; others return MM_ERR_UNSUPPORTED). */
 mm_status mm_get_stats(mm_handle h, void* stream, mm_stats* out);

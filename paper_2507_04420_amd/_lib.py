@@ -31,6 +31,7 @@ MM_OFF_I32, MM_OFF_I64 = 0, 1
 MM_LAYOUT_U8, MM_LAYOUT_U32, MM_LAYOUT_U2 = 0, 1, 2
 MM_PROTOCOL_CAS, MM_PROTOCOL_TWO_PHASE = 0, 1
 MM_VALIDATE, MM_SYMMETRIC, MM_STATS, MM_TIMING, MM_CAPTURE = 1, 2, 4, 8, 16
+MM_STATIC_SCRATCH_BYTES = 8 << 20
 
 
 class mm_tuning(ctypes.Structure):
@@ -88,6 +89,7 @@ SIGNATURES = {
     "mm_create": (_I32, [_P, _I32, _P, _I64, _I64, _P, _SZ, _U32, ctypes.POINTER(mm_tuning), _P,
                          ctypes.POINTER(_P)]),
     "mm_run": (_I32, [_P, _P, _P]),
+    "mm_run_static": (_I32, [_P, _I32, _P, _I64, _I64, _U32, ctypes.POINTER(mm_tuning), _P, _P, _P]),
     "mm_sync": (_I32, [_P, _P]),
     "mm_get_stats": (_I32, [_P, _P, ctypes.POINTER(mm_stats)]),
     "mm_reset_stats": (_I32, [_P, _P]),

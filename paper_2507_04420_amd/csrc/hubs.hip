@@ -190,6 +190,18 @@ hipError_t build_hub_chunks(const void* off, int off64, int64_t n, int64_t hub_d
   return build_typed(static_cast<const int32_t*>(off), n, hub_degree, chunk, ctrl, table, count, s);
 }
 
+hipError_t fill_hub_chunks(const void* off, int off64, int64_t n, int64_t hub_degree, int64_t chunk,
+                           unsigned long long* cursor, mmk::HubChunk* table, hipStream_t s) {
+  if (n == 0 || hub_degree <= 0) return hipSuccess;
+  if (off64)
+    hipLaunchKernelGGL((fill_kernel<int64_t>), dim3(blocks_for(n)), dim3(256), 0, s,
+                       static_cast<const int64_t*>(off), n, hub_degree, chunk, cursor, table);
+  else
+    hipLaunchKernelGGL((fill_kernel<int32_t>), dim3(blocks_for(n)), dim3(256), 0, s,
+                       static_cast<const int32_t*>(off), n, hub_degree, chunk, cursor, table);
+  return hipGetLastError();
+}
+
 void free_owned(void* p) {
   // stream-ordered on the null stream: no wait for the whole device; the
   // owner first makes the null stream wait for the last pass that reads the

@@ -71,6 +71,12 @@ namespace mmi {
 hipError_t build_hub_chunks(const void* off, int off64, int64_t n, int64_t hub_degree,
                             int64_t chunk, uint8_t* ctrl, mmk::HubChunk** table, int64_t* count,
                             hipStream_t s);
+// Fills a hub table of known capacity without counting first and without a
+// wait: each long list takes its run of slots from *cursor (zero on entry),
+// which ends holding the number of pieces. The caller sizes the table with
+// hub_pieces_bound.
+hipError_t fill_hub_chunks(const void* off, int off64, int64_t n, int64_t hub_degree, int64_t chunk,
+                           unsigned long long* cursor, mmk::HubChunk* table, hipStream_t s);
 // Stream-ordered release of memory a handle owns (no wait for the device).
 void free_owned(void* p);
 

@@ -8,6 +8,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -199,11 +200,15 @@ __global__ void validate_kernel(const OffT* __restrict__ off, const int32_t* __r
 // One graph: wavefront w < main_waves sweeps sources [v_begin + w *
 // wave_vertices, ...); the wavefronts after them (dispatched last) take the
 // hub tier's pieces, 64 to a wavefront, as one launch with the main pass.
+// chunk_count (device, or null): the number of pieces when only the device
+// knows it (the table was filled by this pass's own stream); n_chunks is then
+// the table's capacity, which sizes the grid.
 template <typename OffT, class Layout, bool HINT, bool LAZY, bool STATS>
 __global__ __launch_bounds__(256) void sweep_kernel(SweepParams p, const OffT* __restrict__ off,
                                                    const int32_t* __restrict__ nbr, int64_t n,
                                                    int64_t v_begin, int64_t main_waves,
-                                                   int64_t n_chunks, Layout L,
+                                                   int64_t n_chunks,
+                                                   const unsigned long long* chunk_count, Layout L,
                                                    unsigned long long* stats) {
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   int64_t vb, nv;
@@ -213,6 +218,10 @@ __global__ __launch_bounds__(256) void sweep_kernel(SweepParams p, const OffT* _
     nv = (n - vb < p.wave_vertices) ? (n - vb) : p.wave_vertices;
     p.chunks = nullptr;
   } else {
+    if (chunk_count) {
+      const int64_t c = (int64_t)*chunk_count;
+      n_chunks = c < n_chunks ? c : n_chunks;
+    }
     vb = (wave - main_waves) * 64;
     if (vb >= n_chunks) return;
     nv = (n_chunks - vb < 64) ? (n_chunks - vb) : 64;
@@ -285,6 +294,10 @@ struct mm_graph {
   TimingRing* timing;
   mmk::HubChunk* chunks = nullptr;  // hub tier table (device, owned), or null
   int64_t n_chunks = 0;
+  // mm_run_static: the pieces are counted on the device (n_chunks is then the
+  // table's capacity), and the loop-budget flag may go to the caller's word
+  const unsigned long long* chunk_count = nullptr;
+  uint32_t* err_out = nullptr;
   // with a hub table: recorded on the create stream once the table is
   // filled (every run waits for it), and on the run stream after each run
   // (the destroy call orders the table's release after it)
@@ -324,7 +337,7 @@ SweepParams make_params(const mm_graph* g) {
   p.stream_loads = g->tun.stream_loads;
   p.wait_release = g->tun.wait_release;
   p.iter_cap = g->tun.iter_cap;
-  p.err = reinterpret_cast<uint32_t*>(g->ws);
+  p.err = g->err_out ? g->err_out : reinterpret_cast<uint32_t*>(g->ws);
   p.hub_degree = g->n_chunks > 0 ? g->tun.hub_degree : 0;
   p.hub_chunk = g->tun.hub_chunk;
   p.chunks = nullptr;
@@ -394,7 +407,7 @@ hipError_t launch_sweep(const mm_graph* g, const Layout& L, hipStream_t s) {
   }
   hipLaunchKernelGGL((sweep_kernel<OffT, Layout, HINT, LAZY, STATS>), dim3((unsigned)blocks),
                      dim3(g->tun.wg_size), 0, s, pl, off, nbr, g->n, v_begin, waves, g->n_chunks,
-                     L, stats);
+                     g->chunk_count, L, stats);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (g->timing) {
@@ -508,9 +521,46 @@ hipError_t run_typed(const mm_graph* g, int32_t* mate, hipStream_t s) {
 
 }  // namespace
 
+// ---------------------------------------------------------------- static scratch
+// The working memory of mm_run_static: the control block (error word, hub
+// piece cursor), then the packed states and the matched hint when the tuning
+// has them, then the hub piece table. Each device holds its own copy from
+// module load until the process ends. In host code `scratch` names a host-side
+// stand-in, never the device memory: kernels get the address
+// hipGetSymbolAddress returns for the current device (static_scratch below).
+constexpr size_t kStaticScratchBytes = MM_STATIC_SCRATCH_BYTES;
+static __device__ __align__(256) uint8_t scratch[kStaticScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint8_t* g_scratch[kMaxDevices] = {};
+
+// The device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept.
+mm_status static_scratch(uint8_t** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(MM_ERR_UNSUPPORTED, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(MM_ERR_HIP, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev,
+                  hipGetErrorString(e));
+    g_scratch[dev] = static_cast<uint8_t*>(p);
+  }
+  *out = g_scratch[dev];
+  return MM_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
-const char* mm_version(void) { return "skipper-gfx950 0.2"; }
+const char* mm_version(void) { return "skipper-gfx950 0.3"; }
 
 const char* mm_last_error(void) { return g_last_error.c_str(); }
 
@@ -716,6 +766,87 @@ mm_status mm_run(mm_handle g, void* stream, int32_t* match_out) {
     e = stats ? run_typed<int32_t, true>(g, match_out, s) : run_typed<int32_t, false>(g, match_out, s);
   if (e != hipSuccess) return fail(MM_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e));
   if (g->last_run) HIP_TRY(hipEventRecord(g->last_run, s));
+  return MM_OK;
+}
+
+mm_status mm_run_static(const void* offsets, mm_offset_type off_type, const int32_t* neighbors,
+                        int64_t n, int64_t m, uint32_t flags, const mm_tuning* tuning, void* stream,
+                        int32_t* match_out, uint32_t* status_out) {
+  if (off_type != MM_OFF_I32 && off_type != MM_OFF_I64)
+    return fail(MM_ERR_INVALID_ARG, "off_type must be MM_OFF_I32 or MM_OFF_I64");
+  if (n < 0 || n > INT32_MAX)
+    return fail(MM_ERR_INVALID_ARG, "n = %lld out of [0, 2^31-1]", (long long)n);
+  if (m < 0) return fail(MM_ERR_INVALID_ARG, "m = %lld is negative", (long long)m);
+  if (off_type == MM_OFF_I32 && m > INT32_MAX)
+    return fail(MM_ERR_INVALID_ARG, "m = %lld does not fit int32 offsets", (long long)m);
+  if (!offsets) return fail(MM_ERR_INVALID_ARG, "offsets is null");
+  if (!neighbors && m > 0) return fail(MM_ERR_INVALID_ARG, "neighbors is null");
+  if (!match_out && n > 0) return fail(MM_ERR_INVALID_ARG, "match_out is null");
+  if (flags & ~(uint32_t)MM_SYMMETRIC)
+    return fail(MM_ERR_UNSUPPORTED, "mm_run_static takes MM_SYMMETRIC only (flags 0x%x)", flags);
+  mm_tuning t;
+  if (tuning) t = *tuning; else mm_default_tuning(&t);
+  mm_status st = check_tuning(t);
+  if (st != MM_OK) return st;
+  if (n > mmi::max_vertices(t))
+    return fail(MM_ERR_INVALID_ARG, "n = %lld: the word layout with the two-phase protocol "
+                "takes at most 2^31-2 vertices", (long long)n);
+  if (t.relabel)
+    return fail(MM_ERR_UNSUPPORTED, "mm_run_static: tuning.relabel needs a workspace (mm_create)");
+  // what the pass needs of the scratch, as mm_create's workspace would hold it
+  const size_t base = kCtrlBytes + mmi::state_bytes(n, t) + mmi::hint_bytes(n, t);
+  const int64_t pieces =
+      n > t.whole_graph_vertices ? mmi::hub_pieces_bound(m, t.hub_degree, t.hub_chunk) : 0;
+  const size_t need = base + round_up(sizeof(mmk::HubChunk) * (size_t)pieces, 256);
+  if (need > kStaticScratchBytes)
+    return fail(MM_ERR_OUT_OF_MEMORY,
+                "mm_run_static: this graph and tuning need %zu bytes of the static scratch, which "
+                "holds %zu (states %zu, hint %zu, hub pieces up to %lld); the word layout needs no "
+                "state array, hint = 0 no hint, hub_degree = 0 no piece table",
+                need, kStaticScratchBytes, mmi::state_bytes(n, t), mmi::hint_bytes(n, t),
+                (long long)pieces);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // the caller's status word starts at 0 (a fill kernel, so that the call can
+  // be captured into a graph)
+  if (status_out) {
+    fill(status_out, 1, 0u, s);
+    HIP_TRY(hipGetLastError());
+  }
+  if (n == 0) return MM_OK;
+  uint8_t* ws = nullptr;
+  st = static_scratch(&ws);
+  if (st != MM_OK) return st;
+  // the control block starts at zero: error word, hub piece cursor
+  fill(reinterpret_cast<uint32_t*>(ws), (int64_t)(kCtrlBytes / 4), 0u, s);
+  HIP_TRY(hipGetLastError());
+  mm_graph g;
+  g.off = offsets;
+  g.off64 = off_type == MM_OFF_I64;
+  g.nbr = neighbors;
+  g.n = n;
+  g.m = m;
+  g.ws = ws;
+  g.ws_bytes = kStaticScratchBytes;
+  g.flags = flags;
+  g.tun = t;
+  g.device = 0;
+  g.timing = nullptr;
+  g.relabel = false;
+  g.rl = mmi::RelabelView{};
+  g.rl_state = nullptr;
+  g.err_out = status_out;
+  g.lazy = t.lazy_init && (flags & MM_SYMMETRIC) && pieces == 0 &&
+           !(t.layout == MM_LAYOUT_U32 && t.protocol == MM_PROTOCOL_CAS);
+  if (pieces > 0) {
+    auto* cursor = reinterpret_cast<unsigned long long*>(ws + mmi::kHubOffset);
+    g.chunks = reinterpret_cast<mmk::HubChunk*>(ws + base);
+    g.n_chunks = pieces;  // capacity: the sweep reads the count from the cursor
+    g.chunk_count = cursor;
+    HIP_TRY(mmi::fill_hub_chunks(offsets, g.off64, n, t.hub_degree, t.hub_chunk, cursor, g.chunks, s));
+  }
+  hipError_t e = g.off64 ? run_typed<int64_t, false>(&g, match_out, s)
+                         : run_typed<int32_t, false>(&g, match_out, s);
+  if (e != hipSuccess) return fail(MM_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e));
   return MM_OK;
 }
 

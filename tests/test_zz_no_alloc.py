@@ -1,0 +1,123 @@
+"""mm_run_static (the entry point that allocates nothing) against mm_run on
+the same graphs: through the C ABI, two calls in a row on the static scratch,
+the second with a smaller graph, each checked by the oracle's exact checker
+(zero violations), bitwise equal to mm_run where the result cannot depend on
+the schedule (a unique maximal matching, a graph swept whole by one
+wavefront), otherwise the same size within the alone-vs-mix tolerance
+max(2, 1% of SGMM's size)."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2507_04420_amd as mm  # noqa: E402
+from paper_2507_04420_amd import _lib  # noqa: E402
+
+
+def run_static(csr, tuning=None, off32=False):
+    """One mm_run_static call through ctypes; returns (mate, status word)."""
+    lib = _lib.load()
+    off_np = csr.off.astype(np.int32 if off32 else np.int64)
+    off = torch.from_numpy(off_np).cuda()
+    nbr = torch.from_numpy(csr.nbr).cuda()
+    out = torch.empty(max(csr.n, 1), dtype=torch.int32, device="cuda")
+    status = torch.full((1,), 7, dtype=torch.int32, device="cuda")
+    ct = (tuning or mm.Tuning.default()).to_c()
+    s = torch.cuda.current_stream()
+    _lib.check(lib.mm_run_static(ctypes.c_void_p(off.data_ptr()),
+                                 _lib.MM_OFF_I32 if off32 else _lib.MM_OFF_I64,
+                                 ctypes.c_void_p(nbr.data_ptr()), csr.n, csr.m, _lib.MM_SYMMETRIC,
+                                 ctypes.byref(ct), ctypes.c_void_p(s.cuda_stream),
+                                 ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(status.data_ptr())))
+    torch.cuda.synchronize()
+    return out[:csr.n].cpu().numpy(), int(status.item())
+
+
+def run_handle(csr, tuning=None):
+    off = torch.from_numpy(csr.off.astype(np.int64)).cuda()
+    nbr = torch.from_numpy(csr.nbr).cuda()
+    g = mm.Graph(off, nbr, symmetric=True, tuning=tuning)
+    out = g.run()
+    g.sync()
+    g.close()
+    return out.cpu().numpy()
+
+
+def compare(csr, a, b, exact):
+    ca, cb = oracle.check(csr, a), oracle.check(csr, b)
+    assert ca.ok and cb.ok, (csr.name, ca, cb)
+    if exact:
+        np.testing.assert_array_equal(a, b)
+    else:
+        bound = max(2, 0.01 * oracle.sgmm(csr).pairs)
+        assert abs(ca.size - cb.size) <= bound, (csr.name, ca.size, cb.size, bound)
+
+
+HUBS = mm.Tuning(hub_degree=256, hub_chunk=64, whole_graph_vertices=0)
+CASES = [
+    # (first graph, second smaller graph, tuning, exact)
+    (lambda: graphgen.rmat(17, seed=7), lambda: graphgen.rmat(13, seed=8), None, False),
+    (lambda: graphgen.rmat(16, seed=9), lambda: graphgen.er(3000, 6, seed=2), HUBS, False),
+    (lambda: graphgen.grid(400, 300), lambda: graphgen.grid(60, 50), None, False),
+    (lambda: graphgen.er(12000, 8, seed=3), lambda: graphgen.er(900, 5, seed=4), None, True),
+    (lambda: graphgen.rmat(15, seed=5), lambda: graphgen.rmat(12, seed=6),
+     mm.Tuning(layout=_lib.MM_LAYOUT_U8, hint=1, whole_graph_vertices=0), False),
+    (lambda: graphgen.rmat(15, seed=5), lambda: graphgen.rmat(12, seed=6),
+     mm.Tuning(layout=_lib.MM_LAYOUT_U2, protocol=_lib.MM_PROTOCOL_TWO_PHASE, lazy_init=1,
+               whole_graph_vertices=0), False),
+]
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_static_equals_mm_run_on_two_calls(case):
+    big, small, tuning, exact = CASES[case]
+    for csr in (big(), small()):
+        a, status = run_static(csr, tuning)
+        assert status == 0
+        b = run_handle(csr, tuning)
+        whole = csr.n <= (tuning or mm.Tuning()).whole_graph_vertices
+        compare(csr, a, b, exact or whole)
+
+
+def test_static_unique_result_and_int32_offsets():
+    # disjoint edges: the one maximal matching, bit for bit; twice, the second
+    # call smaller, with int32 offsets
+    for k in (50000, 700):
+        csr = graphgen.from_edges(2 * k, [(2 * i, 2 * i + 1) for i in range(k)])
+        a, status = run_static(csr, mm.Tuning(whole_graph_vertices=0), off32=True)
+        assert status == 0
+        np.testing.assert_array_equal(a, np.arange(2 * k, dtype=np.int32) ^ 1)
+
+
+def test_static_status_reports_the_loop_budget():
+    # a budget of one loop trip per wavefront cannot finish a sweep: the status
+    # word says so (every kernel still exits normally); the next call clears it
+    csr = graphgen.rmat(12, seed=1)
+    _, status = run_static(csr, mm.Tuning(iter_cap=1, whole_graph_vertices=0))
+    assert status == 1
+    a, status = run_static(csr, mm.Tuning(whole_graph_vertices=0))
+    assert status == 0 and oracle.check(csr, a).ok
+
+
+def test_static_rejects_what_the_scratch_cannot_hold():
+    lib = _lib.load()
+    out = torch.empty(1, dtype=torch.int32, device="cuda")
+    big_n = 1 << 24  # U8 states of 16 MiB > the 8 MiB scratch
+    ct = mm.Tuning(layout=_lib.MM_LAYOUT_U8).to_c()
+    st = lib.mm_run_static(ctypes.c_void_p(out.data_ptr()), _lib.MM_OFF_I64,
+                           ctypes.c_void_p(out.data_ptr()), big_n, 0, 0, ctypes.byref(ct), None,
+                           ctypes.c_void_p(out.data_ptr()), None)
+    assert st == _lib.MM_ERR_OUT_OF_MEMORY
+    assert b"static scratch" in lib.mm_last_error()
+    ct = mm.Tuning(relabel=1).to_c()
+    st = lib.mm_run_static(ctypes.c_void_p(out.data_ptr()), _lib.MM_OFF_I64,
+                           ctypes.c_void_p(out.data_ptr()), 10, 0, 0, ctypes.byref(ct), None,
+                           ctypes.c_void_p(out.data_ptr()), None)
+    assert st == _lib.MM_ERR_UNSUPPORTED
+    assert _lib.MM_STATIC_SCRATCH_BYTES == 8 << 20
