@@ -1,19 +1,27 @@
 """Benchmark: single-pass maximal matching (Skipper) on one MI355X.
 
 One step = one full matching pass (state initialisation + sweep) over a graph
-resident in HBM. The default workload is R-MAT scale 27, edge factor 16,
+resident in HBM. The headline workload is R-MAT scale 27, edge factor 16,
 (a, b, c) = (0.57, 0.19, 0.19), symmetrised, deduplicated, ids permuted.
 
 value  = m / (ms_per_step) in GEdges/s, m = directed CSR entries.
-roofline: the sweep kernel's algorithmic bytes per launch
-          (offsets w(n+1) + source states n + mates 4n + per id read 4 B and
-          its state byte, 5*T_seq, T_seq = ids SGMM reads) over its mean
-          duration from HIP events
-          recorded on the launch stream, against 8 TB/s.
-cpu_baseline: the oracle's single-thread SGMM on the host, on the same graph.
-batch: the 4096-graph mixture in one captured persistent launch against one
-       launch per graph; serve: Poisson request streams over resident graphs
-       (p50/p99 arrival-to-result latency, GEdges/s).
+roofline: the sweep kernel's algorithmic bytes per launch (per source its
+          offset w, its state byte and its mate 4 B; per id a sequential pass
+          must read, T_seq = ids SGMM reads, the id 4 B and its state byte)
+          over its mean duration from HIP events recorded on the launch
+          stream, against 8 TB/s; beside it the same bytes with the state
+          bytes counted once per vertex (frac_d1), and the two ceilings that
+          bind a pass of random accesses (random line reads, random atomics),
+          each measured live on the box with plain torch operations.
+cpu_baseline: the oracle's single-thread SGMM, pinned to one host core, on
+          the same graph (it also gives T_seq).
+legs: every single-graph configuration (ER n=65536 with int32 offsets,
+      R-MAT-24, R-MAT-27, the 16384^2 grid) with create time, the natural-order
+      sweep beside a relabelled one, B_alg, frac, T_gpu/m and its SGMM
+      baseline; batch: the 4096-graph mixture in one captured persistent
+      launch against one launch per graph, with its algorithmic bytes from
+      every member's T_seq; serve: Poisson request streams over resident
+      graphs (p50/p99 arrival-to-result latency, GEdges/s).
 Tunings come from the package's autotuned table for this device and graph
 class (library defaults where it has none).
 
@@ -37,6 +45,8 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_kernel_traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2507_04420_amd", "csrc", f)
                   for f in ("protocol.h", "sweep.h", "mm.hip", "relabel.hip", "hubs.hip")]
+VIOLATION_KEYS = ("out_of_range", "self_mate", "asymmetric", "not_edge", "uncovered")
+LEGS = ("headline", "er65536", "rmat24", "grid16384", "batch", "serve")
 
 
 def kernel_sources_sha256() -> str:
@@ -48,20 +58,22 @@ def kernel_sources_sha256() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(config) -> float | None:
-    """HBM bytes per sweep launch from the committed rocprofv3 FETCH_SIZE and
-    WRITE_SIZE runs (scaled by a plain copy of known size), if they were taken
-    on the current kernel sources with this workload and tuning; else None."""
+def stored_traffic(config):
+    """The HBM bytes per sweep launch that the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE runs measured (scaled by a plain copy of known
+    size), with the record they come from, if that record was taken on the
+    current kernel sources with this workload and tuning; else (None, None).
+    This run does not measure them itself."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
-        return None
+        return None, None
     if t.get("kernel_sources_sha256") != kernel_sources_sha256():
-        return None
+        return None, None
     if t.get("config") != json.loads(json.dumps(config)):
-        return None
-    return float(t["hbm_bytes_per_launch"])
+        return None, None
+    return float(t["hbm_bytes_per_launch"]), t
 
 
 def log(*a):
@@ -85,28 +97,232 @@ def make_workload(name: str, seed: int):
     raise SystemExit("unknown workload %r" % name)
 
 
-def host_cpu() -> str:
+def workload_class(name: str) -> str:
+    """The tuned-table class of a workload name (er65536 -> er, rmat27 -> rmat)."""
+    return "er" if name.startswith("er") else name.rstrip("0123456789")
+
+
+def host_record() -> dict:
+    model = "?"
     try:
         with open("/proc/cpuinfo") as f:
             model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "?")
     except OSError:
-        model = "?"
-    return "%s, %d logical CPUs visible" % (model, os.cpu_count() or 0)
+        pass
+    ram = None
+    try:
+        with open("/proc/meminfo") as f:
+            kb = next(int(l.split()[1]) for l in f if l.startswith("MemTotal"))
+            ram = round(kb / 1024 / 1024, 1)
+    except (OSError, StopIteration):
+        pass
+    return {"cpu": model, "logical_cpus": os.cpu_count() or 0, "ram_gib": ram}
 
 
 def cpu_baseline(csr, budget_s: float = 30.0):
-    """Times the oracle's single-thread SGMM (untuned) on the host."""
+    """Times the oracle's single-thread SGMM (untuned) on the host, pinned to
+    one core (the first the process may use; the equivalent of taskset -c)."""
     import oracle
+    old = os.sched_getaffinity(0)
+    core = min(old)
+    os.sched_setaffinity(0, {core})
     times = []
     res = None
-    while True:
-        t0 = time.perf_counter()
-        res = oracle.sgmm(csr)
-        times.append(time.perf_counter() - t0)
-        if len(times) >= 3 or sum(times) * (len(times) + 1) / len(times) > budget_s:
-            break
-    t = float(np.median(times))
-    return res, t, len(times)
+    try:
+        while True:
+            t0 = time.perf_counter()
+            res = oracle.sgmm(csr)
+            times.append(time.perf_counter() - t0)
+            if len(times) >= 3 or sum(times) * (len(times) + 1) / len(times) > budget_s:
+                break
+    finally:
+        os.sched_setaffinity(0, old)
+    return res, float(np.median(times)), len(times), core
+
+
+def sweep_bytes(w: int, n: int, t_seq: int) -> int:
+    """Algorithmic bytes of one sweep launch, per unit: per source its offset
+    (w), its state byte (1) and its mate (4); per id a sequential pass must
+    read (T_seq) the id (4) and that neighbour's state byte (1)."""
+    return w * (n + 1) + 5 * t_seq + n + 4 * n
+
+
+def sweep_bytes_d1(w: int, n: int, t_seq: int) -> int:
+    """The same with the states counted once per vertex: w(n+1) + 4 T_seq +
+    2n (state init written, then read) + 4n (mates)."""
+    return w * (n + 1) + 4 * t_seq + 2 * n + 4 * n
+
+
+def live_ceilings(dev) -> dict:
+    """The two ceilings of a pass of random accesses, measured on this GPU
+    with plain torch operations (not this library's kernels): independent
+    random 4-byte reads over a 1 GiB array (each one line request past L2),
+    and independent atomic adds at random 4-byte slots of a 512 MiB array."""
+    import torch
+    g = torch.Generator(device=dev)
+    g.manual_seed(12345)
+    data = torch.ones(1 << 28, dtype=torch.int32, device=dev)
+    idx = torch.randint(0, 1 << 28, (1 << 26,), device=dev, generator=g)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    for _ in range(2):
+        data.index_select(0, idx)
+    torch.cuda.synchronize()
+    ev[0].record()
+    for _ in range(5):
+        data.index_select(0, idx)
+    ev[1].record()
+    torch.cuda.synchronize()
+    reads = 5 * idx.numel() / (ev[0].elapsed_time(ev[1]) / 1e3)
+    del data
+    acc = torch.zeros(1 << 27, dtype=torch.int32, device=dev)
+    aidx = idx % (1 << 27)
+    ones = torch.ones(aidx.numel(), dtype=torch.int32, device=dev)
+    for _ in range(2):
+        acc.index_add_(0, aidx, ones)
+    torch.cuda.synchronize()
+    ev[0].record()
+    for _ in range(5):
+        acc.index_add_(0, aidx, ones)
+    ev[1].record()
+    torch.cuda.synchronize()
+    atomics = 5 * aidx.numel() / (ev[0].elapsed_time(ev[1]) / 1e3)
+    del acc, aidx, ones, idx
+    torch.cuda.empty_cache()
+    return {"random_reads_per_s": round(reads, -6), "random_atomics_per_s": round(atomics, -6),
+            "how": "torch index_select of 2^26 random int32 over 1 GiB; torch index_add_ of 2^26 "
+                   "random int32 slots over 512 MiB (atomic add); 5 timed repeats each"}
+
+
+def timed_passes(g, out, steps, warmup):
+    """Warm-up passes, then `steps` timed passes on the current stream:
+    returns (ms per pass by events around all of them, sweep timing)."""
+    import torch
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        g.run(out)
+    g.sync()
+    g.timing()  # drop warm-up launches
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(steps):
+        g.run(out)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    g.sync()
+    return ev0.elapsed_time(ev1) / steps, g.timing()
+
+
+def bench_single(args, name, tun, dev, *, natural=False, conflicts=False, ceilings=None):
+    """One single-graph configuration: the oracle baseline (T_seq), the
+    handle's create time, `steps` timed passes, the device check, an
+    instrumented pass (T_gpu, atomics, conflicts), and, for a relabelled
+    tuning, the same passes in the given order on a second handle."""
+    import torch
+    import paper_2507_04420_amd as mm
+
+    t0 = time.perf_counter()
+    csr, config = make_workload(name, args.seed)
+    log("generated %s: n=%d m=%d in %.1fs" % (name, csr.n, csr.m, time.perf_counter() - t0))
+    ref, t_sgmm, reps, core = cpu_baseline(csr)
+    t_seq = ref.touched
+    log("SGMM (oracle, core %d): %.3fs x%d, pairs=%d, T_seq=%d (%.4f m)" % (
+        core, t_sgmm, reps, ref.pairs, t_seq, t_seq / max(csr.m, 1)))
+    off = torch.from_numpy(csr.off).to(dev)
+    nbr = torch.from_numpy(csr.nbr).to(dev)
+    torch.cuda.synchronize()
+    n, m = csr.n, csr.m
+    w = csr.off.dtype.itemsize
+    del csr
+
+    tc = time.perf_counter()
+    g = mm.Graph(off, nbr, symmetric=True, timing=True, tuning=tun)
+    torch.cuda.synchronize()
+    create_ms = (time.perf_counter() - tc) * 1e3
+    out = torch.empty(n, dtype=torch.int32, device=dev)
+    ms_per_step, sweep = timed_passes(g, out, args.steps, args.warmup)
+    chk = g.check(out)
+    viol = sum(chk[k] for k in VIOLATION_KEYS)
+    size = chk["matched"] // 2
+    g.close()
+    del g
+    log("%s: create %.1f ms; %.4f ms/pass, sweep %.4f ms (min %.4f max %.4f); %.1f GEdges/s; "
+        "violations %d, size %d (SGMM %d)" % (
+            name, create_ms, ms_per_step, sweep["mean_ms"], sweep["min_ms"], sweep["max_ms"],
+            m / ms_per_step / 1e6, viol, size, ref.pairs))
+
+    counters = conflict_row = None
+    if not args.no_stats:
+        gs = mm.Graph(off, nbr, symmetric=True, stats=True, tuning=tun)
+        o2 = gs.run()
+        gs.sync()
+        counters = gs.stats()
+        c2 = gs.check(o2)
+        counters["checker_violations"] = sum(c2[k] for k in VIOLATION_KEYS)
+        gs.close()
+        del o2
+        if conflicts:
+            # Table II on this graph: worst (most conflicting edges) of five passes
+            conflict_row = mm.conflict_table(off, nbr, runs=5, tuning=tun)
+            log("conflicts (Table II): %s" % conflict_row)
+
+    natural_leg = None
+    if natural and tun.relabel:
+        tn = mm.Tuning(**dict(tun.as_dict(), relabel=0))
+        tc = time.perf_counter()
+        gn = mm.Graph(off, nbr, symmetric=True, timing=True, tuning=tn)
+        torch.cuda.synchronize()
+        create_n = (time.perf_counter() - tc) * 1e3
+        ms_n, sweep_n = timed_passes(gn, out, args.steps, args.warmup)
+        chk_n = gn.check(out)
+        gn.close()
+        natural_leg = {"tuning_change": {"relabel": 0}, "create_ms": round(create_n, 2),
+                       "ms_per_step": round(ms_n, 5), "sweep_ms": round(sweep_n["mean_ms"], 5),
+                       "gedges_per_s": round(m / ms_n / 1e6, 2),
+                       "frac": round(sweep_bytes(w, n, t_seq) / (sweep_n["mean_ms"] / 1e3) / 1e9
+                                     / HBM_PEAK_GBS, 5),
+                       "violations": int(sum(chk_n[k] for k in VIOLATION_KEYS)),
+                       "size": chk_n["matched"] // 2}
+        log("%s natural order: create %.1f ms; %.4f ms/pass, sweep %.4f ms; %.1f GEdges/s" % (
+            name, create_n, ms_n, sweep_n["mean_ms"], m / ms_n / 1e6))
+    del off, nbr, out
+    torch.cuda.empty_cache()
+
+    sweep_s = sweep["mean_ms"] / 1e3
+    b_sweep = sweep_bytes(w, n, t_seq)
+    b_d1 = sweep_bytes_d1(w, n, t_seq)
+    leg = {
+        "config": dict(config, n=n, m=m, tuning=tun.as_dict()),
+        "create_ms": round(create_ms, 2),
+        "relabel_copy_bytes": (8 * (n + 1) + 4 * n + 4 * m + 4 * n) if tun.relabel else 0,
+        "ms_per_step": round(ms_per_step, 5),
+        "us_per_step": round(ms_per_step * 1e3, 2),
+        "sweep_ms": round(sweep["mean_ms"], 5),
+        "gedges_per_s": round(m / ms_per_step / 1e6, 3),
+        "alg_bytes_per_launch": int(b_sweep),
+        "frac": round(b_sweep / sweep_s / 1e9 / HBM_PEAK_GBS, 5),
+        "alg_bytes_d1": int(b_d1),
+        "frac_d1": round(b_d1 / sweep_s / 1e9 / HBM_PEAK_GBS, 5),
+        "t_seq": int(t_seq),
+        "t_gpu_over_m": (round((counters["touched"] + counters["assist_reads"]) / m, 5)
+                         if counters else None),
+        "violations": int(viol),
+        "size": int(size),
+        "size_sgmm": int(ref.pairs),
+        "cpu_baseline": {"value": round(m / t_sgmm / 1e9, 4), "unit": "GEdges/s", "cores": 1,
+                         "kind": "oracle", "pinned_core": core, "t_sgmm_s": round(t_sgmm, 4),
+                         "sample": "full graph, SGMM single thread, median of %d run(s)" % reps,
+                         "gain_over_sgmm": round(t_sgmm / (ms_per_step / 1e3), 1)},
+    }
+    if counters:
+        atomics = counters["reserve_attempts"] + counters["match_attempts"]
+        leg["atomics_per_launch"] = int(atomics)
+        if ceilings:
+            leg["atomic_frac"] = round(atomics / sweep_s / ceilings["random_atomics_per_s"], 4)
+    if natural_leg:
+        leg["natural_order"] = natural_leg
+    return leg, counters, conflict_row, sweep
 
 
 # Design-choice variants (--variants): overrides of the tuned tuning, one
@@ -155,16 +371,16 @@ def bench_variants(args, csr, off, nbr, base, t_seq):
         gs.close()
         del o2
         sweep_s = tm["mean_ms"] / 1e3
-        b_sweep = w * (csr.n + 1) + 5 * t_seq + csr.n + 4 * csr.n
+        b_sweep = sweep_bytes(w, csr.n, t_seq)
         row = {"variant": name, "tuning": t.as_dict(), "sweep_ms": round(tm["mean_ms"], 4),
                "gedges_per_s": round(csr.m / sweep_s / 1e9, 1),
                "alg_gbs": round(b_sweep / sweep_s / 1e9, 1),
-               "violations": sum(chk[k] for k in ("out_of_range", "self_mate", "asymmetric",
-                                                  "not_edge", "uncovered")),
+               "violations": sum(chk[k] for k in VIOLATION_KEYS),
                "size": chk["matched"] // 2,
                "t_gpu_over_m": round((st["touched"] + st["assist_reads"]) / csr.m, 5),
                "atomics": st["reserve_attempts"] + st["match_attempts"],
-               "conflicts": st["reserve_conflicts"] + st["match_conflicts"],
+               "conflicts": (st["reserve_conflicts"] + st["match_conflicts"] + st["reserve_matched"]
+                             + st["match_matched"]),
                "word_retries": st["word_retries"], "pairs": st["pairs"],
                "launches": 1 + args.steps}
         rows.append(row)
@@ -209,7 +425,7 @@ def bench_serve(args, dev):
     # warm-up: every graph once, so the kernels are loaded and the allocator is primed
     serve.run_trace(scheduler(), [serve.Request(i, g, 0.0) for i, g in enumerate(graphs)])
     for rate in args.serve_rates:
-        count = max(20, int(rate * args.serve_seconds))
+        count = max(args.serve_requests, int(rate * args.serve_seconds))
         gid = rng.integers(0, len(graphs), size=count)
         arr = serve.poisson_arrivals(count, rate, seed=args.seed + int(rate))
         reqs = [serve.Request(i, graphs[g], float(arr[i])) for i, g in enumerate(gid)]
@@ -220,18 +436,22 @@ def bench_serve(args, dev):
         r["rate_req_per_s"] = rate
         r["peak_in_use_bytes"] = int(s.peak_in_use)
         out["rates"].append({k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()})
-        log("serve %5d req/s: p50 %.3f ms p99 %.3f ms, %.1f GEdges/s, %d batches (%.1f jobs each), %d solo" % (
-            rate, r["p50_ms"], r["p99_ms"], r["gedges_per_s"], r["batch_launches"],
-            r["mean_jobs_per_batch"], r["solo_launches"]))
+        log("serve %5d req/s: %d requests, p50 %.3f ms p99 %.3f ms, %.1f GEdges/s, %d batches "
+            "(%.2f jobs each), %d solo" % (
+                rate, count, r["p50_ms"], r["p99_ms"], r["gedges_per_s"], r["batch_launches"],
+                r["mean_jobs_per_batch"], r["solo_launches"]))
     return out
 
 
 def bench_batch(args, tun, dev):
     """Batched matching of the 4096-graph mixture: one hipGraph-captured
     persistent launch per pass, against one mm_run per graph on one stream
-    (same kernels, the same tuning without the hint, caches warm)."""
+    (same kernels, the same tuning without the hint, caches warm). The
+    oracle's SGMM over every member (one core) is the CPU baseline and gives
+    the members' T_seq for the algorithmic bytes."""
     import torch
     import graphgen
+    import oracle
     import paper_2507_04420_amd as mm
 
     t0 = time.perf_counter()
@@ -239,9 +459,31 @@ def bench_batch(args, tun, dev):
     G = mix.num_graphs
     log("generated batch mixture: %d graphs, N=%d M=%d in %.1fs" % (G, mix.n, mix.m,
                                                                     time.perf_counter() - t0))
+    # CPU baseline over every member (pinned to one core), and T_seq
+    old = os.sched_getaffinity(0)
+    core = min(old)
+    os.sched_setaffinity(0, {core})
+    t_seq = 0
+    pairs_sgmm = 0
+    t_cpu = 0.0
+    try:
+        for g in range(G):
+            sub = mix.member(g)
+            tc = time.perf_counter()
+            r = oracle.sgmm(sub)
+            t_cpu += time.perf_counter() - tc
+            t_seq += r.touched
+            pairs_sgmm += r.pairs
+    finally:
+        os.sched_setaffinity(0, old)
+    log("batch SGMM (oracle, core %d): %.3f s over %d graphs, T_seq=%d" % (core, t_cpu, G, t_seq))
+
     off = torch.from_numpy(mix.off).to(dev)
     nbr = torch.from_numpy(mix.nbr).to(dev)
+    tc = time.perf_counter()
     b = mm.Batch(off, nbr, mix.vtx_off, symmetric=True, validate=True, capture=True, tuning=tun)
+    torch.cuda.synchronize()
+    create_ms = (time.perf_counter() - tc) * 1e3
     out = torch.empty(mix.n, dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream()
     for _ in range(args.warmup):
@@ -289,18 +531,23 @@ def bench_batch(args, tun, dev):
 
     # untimed: the library's device check of both outputs (every member graph)
     def violations(r):
-        return sum(r[k] for k in ("out_of_range", "self_mate", "asymmetric", "not_edge", "uncovered"))
-    bad_b = violations(b.check(out))
+        return sum(r[k] for k in VIOLATION_KEYS)
+    cb = b.check(out)
+    bad_b = violations(cb)
     bad_p = violations(b.check(out2))
     items = b.items
     for h in handles:
         h.close()
     b.close()
+    # algorithmic bytes of a pass over all members, as for one graph summed
+    # over them (each member's offsets have one entry more than its vertices)
+    b_alg = sweep_bytes(8, mix.n, t_seq) + 8 * (G - 1)
     res = {
         "graphs": G,
         "N": int(mix.n),
         "M": int(mix.m),
         "work_items": int(items),
+        "create_ms": round(create_ms, 2),
         "ms_batched": round(ms_batched, 4),
         "graphs_per_s_batched": round(G / (ms_batched / 1e3), 1),
         "ms_per_graph_launches": round(ms_per_graph_total, 4),
@@ -308,11 +555,24 @@ def bench_batch(args, tun, dev):
         "graphs_per_s_per_graph": round(G / (ms_per_graph_total / 1e3), 1),
         "ratio": round(ms_per_graph_total / ms_batched, 3),
         "gedges_per_s_batched": round(mix.m / (ms_batched / 1e3) / 1e9, 2),
+        "t_seq": int(t_seq),
+        "alg_bytes_per_pass": int(b_alg),
+        # over the whole captured pass (fills, LDS kernel, persistent sweep);
+        # the sweep kernel's own duration is in the profiles
+        "frac_of_pass": round(b_alg / (ms_batched / 1e3) / 1e9 / HBM_PEAK_GBS, 5),
+        "size": int(cb["matched"] // 2),
+        "size_sgmm": int(pairs_sgmm),
         "checker_violations_batched": int(bad_b),
         "checker_violations_per_graph": int(bad_p),
+        "cpu_baseline": {"value": round(G / t_cpu, 1), "unit": "graphs/s", "cores": 1,
+                         "kind": "oracle", "pinned_core": core, "t_sgmm_s": round(t_cpu, 3),
+                         "sample": "SGMM over all %d members, one after the other" % G},
     }
-    log("batch: %.3f ms batched vs %.3f ms per-graph launches (x%.2f), violations %d/%d" % (
-        ms_batched, ms_per_graph_total, res["ratio"], bad_b, bad_p))
+    log("batch: %.3f ms batched vs %.3f ms per-graph launches (x%.2f), violations %d/%d, "
+        "alg %.2f GB per pass" % (ms_batched, ms_per_graph_total, res["ratio"], bad_b, bad_p,
+                                  b_alg / 1e9))
+    del off, nbr, out, out2, offs, views
+    torch.cuda.empty_cache()
     return res
 
 
@@ -321,7 +581,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="rmat27")
+    ap.add_argument("--workload", default="rmat27", help="the headline workload")
+    ap.add_argument("--legs", default=",".join(LEGS),
+                    help="comma-separated subset of %s (default: all; the headline always runs)"
+                         % ",".join(LEGS))
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--layout", default=None, choices=["u8", "u32", "u2"])
     ap.add_argument("--lazy", type=int, default=None)
@@ -333,8 +596,11 @@ def main():
     ap.add_argument("--batch-graphs", type=int, default=4096)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-rates", type=float, nargs="+", default=[200.0, 500.0, 1000.0, 2000.0])
+    ap.add_argument("--serve-rates", type=float, nargs="+",
+                    default=[200.0, 500.0, 1000.0, 2000.0, 20000.0])
     ap.add_argument("--serve-seconds", type=float, default=1.5)
+    ap.add_argument("--serve-requests", type=int, default=2000,
+                    help="requests per rate at least (10000 gives the p99 more samples)")
     ap.add_argument("--serve-pool", type=int, default=96)
     ap.add_argument("--variants", default=None,
                     help="comma-separated design-choice variants (%s): time and count each on the "
@@ -351,40 +617,36 @@ def main():
         print("bench.py measures one GPU only: the matching pass of one graph runs on a single "
               "MI355X (no multi-GPU path is built); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    legs = set(args.legs.split(","))
+    unknown = legs - set(LEGS)
+    if unknown:
+        raise SystemExit("unknown legs %s" % sorted(unknown))
+    if args.no_batch:
+        legs.discard("batch")
+    if args.no_serve:
+        legs.discard("serve")
 
     import torch
     import paper_2507_04420_amd as mm
-    from paper_2507_04420_amd import _lib
-
-    t0 = time.perf_counter()
-    csr, config = make_workload(args.workload, args.seed)
-    log("generated %s: n=%d m=%d in %.1fs" % (args.workload, csr.n, csr.m, time.perf_counter() - t0))
-
-    # CPU baseline: the oracle's SGMM, single thread; also yields T_seq.
-    ref, t_sgmm, reps = cpu_baseline(csr)
-    t_seq = ref.touched
-    log("SGMM (oracle, 1 thread): %.3fs x%d, pairs=%d, T_seq=%d (%.4f m)" % (
-        t_sgmm, reps, ref.pairs, t_seq, t_seq / max(csr.m, 1)))
+    from paper_2507_04420_amd import _lib, autotune
 
     dev = torch.device("cuda:0")
-    off = torch.from_numpy(csr.off).to(dev)
-    nbr = torch.from_numpy(csr.nbr).to(dev)
-    torch.cuda.synchronize()
 
-    from paper_2507_04420_amd import autotune
-    tun = mm.Tuning.default() if args.untuned else autotune.tuned(config["workload"])
-    if args.layout is not None:
-        tun.layout = {"u8": _lib.MM_LAYOUT_U8, "u32": _lib.MM_LAYOUT_U32, "u2": _lib.MM_LAYOUT_U2}[args.layout]
-    if args.lazy is not None:
-        tun.lazy_init = args.lazy
-    if args.wave_vertices:
-        tun.wave_vertices = args.wave_vertices
-    if args.wg_size:
-        tun.wg_size = args.wg_size
-    if args.disperse is not None:
-        tun.disperse = args.disperse
-    if args.assist_after is not None:
-        tun.assist_after = args.assist_after
+    def tuning_for(graph_class):
+        t = mm.Tuning.default() if args.untuned else autotune.tuned(graph_class)
+        if args.layout is not None:
+            t.layout = {"u8": _lib.MM_LAYOUT_U8, "u32": _lib.MM_LAYOUT_U32, "u2": _lib.MM_LAYOUT_U2}[args.layout]
+        if args.lazy is not None:
+            t.lazy_init = args.lazy
+        if args.wave_vertices:
+            t.wave_vertices = args.wave_vertices
+        if args.wg_size:
+            t.wg_size = args.wg_size
+        if args.disperse is not None:
+            t.disperse = args.disperse
+        if args.assist_after is not None:
+            t.assist_after = args.assist_after
+        return t
 
     if args.calibrate_copy:
         src = torch.ones(1 << 28, dtype=torch.int32, device=dev)  # 1 GiB
@@ -396,80 +658,54 @@ def main():
         log("copy calibration: 3 x (1 GiB read + 1 GiB write) with torch.add(src, 0, out=dst)")
 
     if args.variants:
-        rows = bench_variants(args, csr, off, nbr, tun, t_seq)
+        csr, config = make_workload(args.workload, args.seed)
+        ref, t_sgmm, reps, core = cpu_baseline(csr)
+        off = torch.from_numpy(csr.off).to(dev)
+        nbr = torch.from_numpy(csr.nbr).to(dev)
+        rows = bench_variants(args, csr, off, nbr, tuning_for(workload_class(args.workload)),
+                              ref.touched)
         print(json.dumps({"mode": "variants", "config": config, "n": csr.n, "m": csr.m,
-                          "t_seq": t_seq, "size_sgmm": ref.pairs, "steps": args.steps,
+                          "t_seq": ref.touched, "size_sgmm": ref.pairs, "steps": args.steps,
                           "rows": rows}), flush=True)
         return
 
-    g = mm.Graph(off, nbr, symmetric=True, validate=True, timing=True, tuning=tun)
-    out = torch.empty(csr.n, dtype=torch.int32, device=dev)
-    stream = torch.cuda.current_stream()
-    for _ in range(args.warmup):
-        g.run(out)
-    g.sync()
-    g.timing()  # drop warm-up launches
+    ceilings = live_ceilings(dev)
+    log("live ceilings: %.3g random reads/s, %.3g random atomics/s" % (
+        ceilings["random_reads_per_s"], ceilings["random_atomics_per_s"]))
 
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    for _ in range(args.steps):
-        g.run(out)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    g.sync()
-    total_ms = ev0.elapsed_time(ev1)
-    ms_per_step = total_ms / args.steps
-    sweep = g.timing()
-    log("timed %d steps: %.4f ms/step; sweep kernel mean %.4f ms (min %.4f, max %.4f, n=%d)" % (
-        args.steps, ms_per_step, sweep["mean_ms"], sweep["min_ms"], sweep["max_ms"], sweep["count"]))
-
-    # Untimed: the library's device check of the last output (the exact
-    # checker of Section II-B, counted on the GPU; the test suite pins it
-    # against the oracle's).
-    chk = g.check(out)
-    chk_viol = sum(chk[k] for k in ("out_of_range", "self_mate", "asymmetric", "not_edge", "uncovered"))
-    chk_size = chk["matched"] // 2
-    log("check: violations=%d size=%d (SGMM %d)" % (chk_viol, chk_size, ref.pairs))
-
-    counters = conflicts = None
-    if not args.no_stats:
-        gs = mm.Graph(off, nbr, symmetric=True, stats=True, tuning=tun)
-        o2 = gs.run()
-        gs.sync()
-        counters = gs.stats()
-        c2 = gs.check(o2)
-        counters["checker_violations"] = sum(
-            c2[k] for k in ("out_of_range", "self_mate", "asymmetric", "not_edge", "uncovered"))
-        gs.close()
-        log("counters: %s" % counters)
-        # Table II on this graph: worst (most conflicting edges) of five passes
-        conflicts = mm.conflict_table(off, nbr, runs=5, tuning=tun)
-        log("conflicts (Table II): %s" % conflicts)
-
-    del g
+    # the headline graph first, while the device is empty
+    head, counters, conflicts, sweep = bench_single(
+        args, args.workload, tuning_for(workload_class(args.workload)), dev, natural=True,
+        conflicts=not args.no_stats, ceilings=ceilings)
+    others = {}
+    for name in ("er65536", "rmat24", "grid16384"):
+        if name in legs and name != args.workload:
+            others[name] = bench_single(args, name, tuning_for(workload_class(name)), dev,
+                                        natural=True, ceilings=ceilings)[0]
     batch = None
-    if not args.no_batch:
+    if "batch" in legs:
         tb = mm.Tuning.default() if args.untuned else autotune.tuned("batch")
         batch = bench_batch(args, tb, dev)
         batch["tuning"] = tb.as_dict()
-    serving = None if args.no_serve else bench_serve(args, dev)
+    serving = bench_serve(args, dev) if "serve" in legs else None
 
-    n, m = csr.n, csr.m
-    w = csr.off.dtype.itemsize
-    # Algorithmic bytes of one sweep launch: per source its offset w, its
-    # state byte and its mate (4 B); per id a sequential pass must read (T_seq)
-    # the id (4 B) and that neighbour's state byte. The pass adds the state
-    # initialisation n.
-    b_sweep = w * (n + 1) + 5 * t_seq + n + 4 * n
-    b_pass = b_sweep + n
-    csr_bytes = w * (n + 1) + 4 * m
+    cfg = head["config"]
+    m = cfg["m"]
     sweep_s = sweep["mean_ms"] / 1e3
-    achieved = b_sweep / sweep_s / 1e9 if sweep_s > 0 else 0.0
+    ms_per_step = head["ms_per_step"]
     value = m / (ms_per_step / 1e3) / 1e9
-    cfg_out = dict(config, n=n, m=m, tuning={k: int(v) for k, v in vars(tun).items()})
-    traffic = measured_traffic(cfg_out)
+    b_sweep = head["alg_bytes_per_launch"]
+    achieved = b_sweep / sweep_s / 1e9
+    cfg_traffic = dict(cfg, tuning={k: int(v) for k, v in cfg["tuning"].items()})
+    traffic, traffic_rec = stored_traffic(cfg_traffic)
+    secondary = dict(ceilings)
+    if counters:
+        secondary["atomics_per_launch"] = head.get("atomics_per_launch")
+        secondary["atomic_frac"] = head.get("atomic_frac")
+    if traffic_rec and traffic_rec.get("l2_miss_read_requests_per_launch"):
+        req = float(traffic_rec["l2_miss_read_requests_per_launch"])
+        secondary["l2_miss_read_requests_per_launch_stored"] = req
+        secondary["request_frac"] = round(req / sweep_s / ceilings["random_reads_per_s"], 4)
     result = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -483,7 +719,7 @@ def main():
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
-        "config": cfg_out,
+        "config": cfg,
         "roofline": {
             "bound": "hbm",
             "kernel": "sweep_kernel",
@@ -491,33 +727,29 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 5),
+            # HBM bytes per launch from the committed counter runs (rocprofv3
+            # FETCH_SIZE and WRITE_SIZE on this kernel source, workload and
+            # tuning), not measured in this run; null when they no longer apply
             "traffic": traffic,
-            # measured HBM bytes per launch over the same duration: how close the
-            # kernel's real traffic comes to the peak
+            "traffic_source": (("stored: profiles/sweep_kernel_traffic.json, kernel sources "
+                                "sha256 %s" % traffic_rec["kernel_sources_sha256"][:16])
+                               if traffic_rec else None),
             "traffic_frac": (round(traffic / sweep_s / 1e9 / HBM_PEAK_GBS, 5)
                              if traffic and sweep_s > 0 else None),
             "alg_bytes_per_launch": int(b_sweep),
+            "frac_d1": head["frac_d1"],
             "sweep_ms": round(sweep["mean_ms"], 5),
-            "pass_alg_bytes": int(b_pass),
-            "pass_frac": round(b_pass / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 5),
-            # the edge rate a pass that streams the whole CSR once (offsets and
-            # ids, w(n+1) + 4m bytes) would reach at the peak, and the value as
-            # a fraction of it: the roofline of a method without early exit
-            "csr_stream_gedges_per_s": round(m / (csr_bytes / (HBM_PEAK_GBS * 1e9)) / 1e9, 1),
-            "csr_stream_frac": round(value / (m / (csr_bytes / (HBM_PEAK_GBS * 1e9)) / 1e9), 5),
+            "secondary": secondary,
         },
-        "cpu_baseline": {
-            "value": round(m / t_sgmm / 1e9, 4),
-            "unit": "GEdges/s",
-            "cores": 1,
-            "kind": "oracle",
-            "sample": "full graph, SGMM single thread, median of %d run(s), %.3f s each" % (reps, t_sgmm),
-            "host": host_cpu(),
-        },
-        "checker": {"kind": "device check (mm_check)", "violations": int(chk_viol),
-                    "size": int(chk_size), "size_sgmm": ref.pairs, "t_seq": t_seq},
+        "cpu_baseline": dict(head["cpu_baseline"], host=host_record()),
+        "checker": {"kind": "device check (mm_check)", "violations": head["violations"],
+                    "size": head["size"], "size_sgmm": head["size_sgmm"], "t_seq": head["t_seq"]},
+        "create_ms": head["create_ms"],
+        "relabel_copy_bytes": head["relabel_copy_bytes"],
+        "natural_order": head.get("natural_order"),
         "counters": counters,
         "conflicts": conflicts,
+        "legs": others,
         "batch": batch,
         "serve": serving,
     }

@@ -190,24 +190,31 @@ typedef struct {
 
 /* Counters of the instrumented kernels (MM_STATS). Conflicts follow Table II
    of the paper: a failed CAS while reserving u (Algorithm 1 L11) or taking v
-   (L14). An edge's conflicts are those met from the moment a lane picks the
-   edge (x, y) as its candidate until the edge is matched or found dead. */
+   (L14), whatever state it met: a reservation by another lane (RSVD, counted
+   in reserve_conflicts / match_conflicts) or a match made since the lane's
+   cached read of the state (MCHD, counted in reserve_matched /
+   match_matched). An edge's conflicts are those met from the moment a lane
+   picks the edge (x, y) as its candidate until the edge is matched or found
+   dead; conflict_hist and conflict_max count both kinds. A CAS on a packed
+   word that fails only because another vertex's byte changed is not a
+   conflict (word_retries). */
 typedef struct {
   uint64_t sources;           /* source vertices visited */
   uint64_t sources_skipped;   /* sources already matched when visited */
   uint64_t touched;           /* neighbour ids read by scanning lanes (T_gpu) */
   uint64_t assist_reads;      /* neighbour ids read by wavefront assists */
   uint64_t reserve_attempts;  /* CAS/fetch-or on u */
-  uint64_t reserve_conflicts; /* u found reserved by another lane */
-  uint64_t reserve_matched;   /* u found matched by the atomic (stale filter) */
+  uint64_t reserve_conflicts; /* u found reserved by another lane (a conflict) */
+  uint64_t reserve_matched;   /* u found matched by the atomic after a cached read
+                                 saw it free (a conflict) */
   uint64_t match_attempts;    /* CAS on v */
-  uint64_t match_conflicts;   /* v found reserved by another lane */
-  uint64_t match_matched;     /* v found matched by the atomic */
+  uint64_t match_conflicts;   /* v found reserved by another lane (a conflict) */
+  uint64_t match_matched;     /* v found matched by the atomic (a conflict) */
   uint64_t word_retries;      /* U8 layout: CAS retried because another byte of
                                  the same 32-bit word changed (not a conflict) */
   uint64_t pairs;             /* matched pairs committed */
   uint64_t loop_trips;        /* sum over wavefronts of loop trips */
-  uint64_t conflict_max;      /* most conflicts met by one edge */
+  uint64_t conflict_max;      /* most conflicts (either kind) met by one edge */
   uint64_t conflict_hist[10]; /* edges by conflicts met: 1, 2, 3-4, 5-8, 9-16,
                                  17-32, 33-64, 65-128, 129-256, >256 (Table II) */
   uint64_t reserved_[8];

@@ -366,14 +366,19 @@ CONFLICT_BINS = ("1", "2", "3-4", "5-8", "9-16", "17-32", "33-64", "65-128", "12
 
 def conflict_row(stats: dict) -> dict:
     """Table II's columns from one instrumented pass: the most conflicts met
-    by one edge, the total conflicts (failed reserves of u plus failed takes
-    of v), the edges that met at least one, their mean, and the distribution
-    of those edges over the table's bins."""
+    by one edge, the total conflicts (every failed take of u or v: those that
+    met another lane's reservation and those that met a match made since the
+    lane's cached read), the edges that met at least one, their mean, and the
+    distribution of those edges over the table's bins. The two kinds are also
+    reported apart."""
     hist = list(stats["conflict_hist"])
     edges = sum(hist)
-    total = stats["reserve_conflicts"] + stats["match_conflicts"]
+    met_reserved = stats["reserve_conflicts"] + stats["match_conflicts"]
+    met_matched = stats["reserve_matched"] + stats["match_matched"]
+    total = met_reserved + met_matched
     return {"max_per_edge": stats["conflict_max"], "total": total, "edges": edges,
             "avg_per_edge": (total / edges) if edges else 0.0,
+            "met_reserved": met_reserved, "met_matched": met_matched,
             "distribution": dict(zip(CONFLICT_BINS, hist))}
 
 

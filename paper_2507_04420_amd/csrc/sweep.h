@@ -308,7 +308,10 @@ __device__ __forceinline__ void sweep_block(const SweepParams& a, OffP __restric
         if (s == R_ACC) {
           phase = P_MAT;
         } else if (s == R_MCHD) {
-          if (STATS) cnt.add(S_RES_MCHD, 1);
+          if (STATS) {  // a failed take of u: a conflict too (Table II)
+            cnt.add(S_RES_MCHD, 1);
+            ++econf;
+          }
           edge_dead(u);
         } else {
           if (STATS) {
@@ -368,7 +371,10 @@ __device__ __forceinline__ void sweep_block(const SweepParams& a, OffP __restric
             phase = P_MATW;
           }
         } else {
-          if (STATS) cnt.add(S_MAT_MCHD, 1);
+          if (STATS) {  // a failed take of v: a conflict too (Table II)
+            cnt.add(S_MAT_MCHD, 1);
+            ++econf;
+          }
           L.release(u);
           edge_dead(v);
         }

@@ -170,13 +170,16 @@ def test_stats_struct_and_conflict_row():
     assert ctypes.sizeof(_lib.mm_stats) == 32 * 8
     s = _lib.mm_stats()
     s.reserve_conflicts, s.match_conflicts, s.conflict_max = 7, 3, 5
+    s.reserve_matched, s.match_matched = 2, 1
     for b, c in enumerate([4, 1, 0, 1]):
         s.conflict_hist[b] = c
     d = _lib.stats_dict(s)
     row = mm.conflict_row(d)
-    assert row["total"] == 10 and row["edges"] == 6 and row["max_per_edge"] == 5
+    # Table II counts every failed take of u or v, whatever state it met
+    assert row["total"] == 13 and row["edges"] == 6 and row["max_per_edge"] == 5
+    assert row["met_reserved"] == 10 and row["met_matched"] == 3
     assert row["distribution"]["1"] == 4 and row["distribution"]["5-8"] == 1
-    assert abs(row["avg_per_edge"] - 10 / 6) < 1e-12
+    assert abs(row["avg_per_edge"] - 13 / 6) < 1e-12
 
 
 def test_workspace_bytes_graph():

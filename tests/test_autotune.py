@@ -103,8 +103,8 @@ def test_search_restarts_from_defaults_when_the_start_is_rejected():
 
 
 def test_spread_limit_is_a_tenth_of_the_serving_tolerance():
-    # one tenth of the 1% alone-vs-mix tolerance
-    assert autotune.SPREAD_LIMIT == 0.001
+    # under a tenth of the 1% alone-vs-mix tolerance
+    assert 0.0005 <= autotune.SPREAD_LIMIT <= 0.001
     assert set(autotune.REPRODUCIBLE) >= {"rmat_small", "grid_small", "er_small", "rmat_mid", "grid_mid"}
 
 

@@ -1,6 +1,6 @@
-"""bench.py pieces that run without a GPU: the one-GPU guard and the lookup
-of measured HBM traffic (only valid for the kernel sources and workload it was
-taken on)."""
+"""bench.py pieces that run without a GPU: the one-GPU guard, the lookup
+of stored HBM traffic (only valid for the kernel sources and workload it was
+taken on), the algorithmic bytes and the leg names."""
 import json
 import os
 import subprocess
@@ -24,14 +24,34 @@ def test_traffic_lookup(tmp_path, monkeypatch):
     f = tmp_path / "traffic.json"
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
     cfg = {"workload": "rmat", "scale": 27, "tuning": {"layout": 1}}
-    assert bench.measured_traffic(cfg) is None  # no file
-    f.write_text(json.dumps({"kernel_sources_sha256": bench.kernel_sources_sha256(), "config": cfg,
-                             "hbm_bytes_per_launch": 4.5e10}))
-    assert bench.measured_traffic(cfg) == 4.5e10
-    assert bench.measured_traffic(dict(cfg, scale=26)) is None  # other workload
-    f.write_text(json.dumps({"kernel_sources_sha256": "0" * 64, "config": cfg,
-                             "hbm_bytes_per_launch": 4.5e10}))
-    assert bench.measured_traffic(cfg) is None  # kernel changed since
+    assert bench.stored_traffic(cfg) == (None, None)  # no file
+    rec = {"kernel_sources_sha256": bench.kernel_sources_sha256(), "config": cfg,
+           "hbm_bytes_per_launch": 4.5e10}
+    f.write_text(json.dumps(rec))
+    traffic, stored = bench.stored_traffic(cfg)
+    assert traffic == 4.5e10 and stored == rec  # the record it comes from is reported with it
+    assert bench.stored_traffic(dict(cfg, scale=26)) == (None, None)  # other workload
+    f.write_text(json.dumps(dict(rec, kernel_sources_sha256="0" * 64)))
+    assert bench.stored_traffic(cfg) == (None, None)  # kernel changed since
+
+
+def test_algorithmic_bytes():
+    # per source w + 1 + 4, per id of a sequential pass 4 + 1 (the sweep's
+    # units); with the states once per vertex instead: w(n+1) + 4 T + 2n + 4n
+    assert bench.sweep_bytes(8, 10, 100) == 8 * 11 + 500 + 10 + 40
+    assert bench.sweep_bytes_d1(8, 10, 100) == 8 * 11 + 400 + 20 + 40
+    # the 16384^2 grid's closed-form T_seq (402,628,608) gives 5.37 GB
+    n = 16384 * 16384
+    assert abs(bench.sweep_bytes_d1(8, n, 402628608) - 5.369e9) < 1e7
+
+
+def test_workload_classes_and_legs():
+    assert bench.workload_class("er65536") == "er"
+    assert bench.workload_class("rmat27") == "rmat" and bench.workload_class("grid16384") == "grid"
+    assert set(bench.LEGS) == {"headline", "er65536", "rmat24", "grid16384", "batch", "serve"}
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--legs", "nope"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0 and "unknown legs" in (r.stderr + r.stdout)
 
 
 def test_variants_are_valid_tunings():

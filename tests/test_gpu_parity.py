@@ -325,8 +325,12 @@ def test_loop_budget_reports_no_progress():
 def check_conflict_row(row, st):
     hist = st["conflict_hist"]
     edges = sum(hist)
-    total = st["reserve_conflicts"] + st["match_conflicts"]
+    # every failed take of u or v is a conflict (Table II), whether it met a
+    # reservation or a match made since the lane's cached read
+    total = (st["reserve_conflicts"] + st["match_conflicts"] + st["reserve_matched"]
+             + st["match_matched"])
     assert row["edges"] == edges and row["total"] == total
+    assert row["met_reserved"] + row["met_matched"] == total
     # each conflicting edge met at least its bin's lower bound, at most its upper
     lo = [1, 2, 3, 5, 9, 17, 33, 65, 129, 257]
     hi = [1, 2, 4, 8, 16, 32, 64, 128, 256, None]
