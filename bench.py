@@ -343,6 +343,10 @@ VARIANTS = {
     "contiguous_lanes": {"disperse": 0},
     "dispersed_lanes": {"disperse": 1},
     "wait_release": {"wait_release": 1},
+    "upper_only": {"upper_only": 1},
+    "upper_only_hint_bytes": {"upper_only": 1, "hint": 2},
+    "upper_only_u8": {"upper_only": 1, "layout": 0, "protocol": 0, "lazy_init": 0},
+    "upper_only_natural": {"upper_only": 1, "relabel": 0},
 }
 
 

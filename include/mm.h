@@ -178,6 +178,15 @@ typedef struct {
                             so no chain of reservations forms, which on meshes
                             swept by many lanes at once can grow as long as a
                             column. 0: as printed */
+  int32_t upper_only;    /* 1 (MM_SYMMETRIC input only; ignored otherwise): a lane
+                            examines only the neighbours whose id is above its
+                            source's (in the swept order: the relabelled ids
+                            with relabel), without reading the states of the
+                            others. Each undirected edge is then examined from
+                            its lower endpoint, as Algorithm 1 iterates each
+                            edge of E once; its mirror entry in the higher
+                            endpoint's list is passed over. Output is eager
+                            (lazy_init does not apply) */
   int32_t min_waves;     /* a graph alone (mm_run) or a batch whose blocked sources
                             are too few for this many wavefronts of wave_vertices
                             sources gets shorter blocks, so that about this many

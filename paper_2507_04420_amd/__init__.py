@@ -49,6 +49,7 @@ class Tuning:
     whole_graph_lds: int = 1
     mesh_wave_vertices: int = 0
     wait_release: int = 0
+    upper_only: int = 0
     min_waves: int = 32
     iter_cap: int = 0
 

@@ -620,6 +620,7 @@ mm_status finish_create(std::vector<mmb::GraphDesc>& descs, const std::vector<in
   p.params.scan_width = t.scan_width;
   p.params.stream_loads = t.stream_loads;
   p.params.wait_release = t.wait_release;
+  p.params.upper_only = (t.upper_only && (flags & MM_SYMMETRIC)) ? 1 : 0;
   p.params.iter_cap = t.iter_cap;
   p.params.hub_degree = n_chunks > 0 ? t.hub_degree : 0;
   p.params.hub_chunk = t.hub_chunk;
@@ -635,7 +636,7 @@ mm_status finish_create(std::vector<mmb::GraphDesc>& descs, const std::vector<in
   p.layout = t.layout;
   p.protocol = t.protocol;
   p.hint = t.hint != 0;
-  p.lazy = t.lazy_init && (flags & MM_SYMMETRIC) && n_chunks == 0 &&
+  p.lazy = t.lazy_init && (flags & MM_SYMMETRIC) && n_chunks == 0 && !t.upper_only &&
            !(t.layout == MM_LAYOUT_U32 && t.protocol == MM_PROTOCOL_CAS);
   p.stats_on = (flags & MM_STATS) != 0;
   p.wg_size = t.wg_size;

@@ -73,6 +73,8 @@ mm_status check_tuning(const mm_tuning& t) {
   if (t.wait_release != 0 && t.wait_release != 1)
     return fail(MM_ERR_INVALID_ARG, "tuning.wait_release must be 0 or 1");
   if (t.min_waves < 0) return fail(MM_ERR_INVALID_ARG, "tuning.min_waves must be >= 0");
+  if (t.upper_only != 0 && t.upper_only != 1)
+    return fail(MM_ERR_INVALID_ARG, "tuning.upper_only must be 0 or 1");
   if (t.mesh_wave_vertices < 0 || t.mesh_wave_vertices % 64)
     return fail(MM_ERR_INVALID_ARG, "tuning.mesh_wave_vertices must be 0 or a positive multiple of 64");
   return MM_OK;
@@ -336,6 +338,7 @@ SweepParams make_params(const mm_graph* g) {
   p.scan_width = g->tun.scan_width;
   p.stream_loads = g->tun.stream_loads;
   p.wait_release = g->tun.wait_release;
+  p.upper_only = (g->tun.upper_only && (g->flags & MM_SYMMETRIC)) ? 1 : 0;
   p.iter_cap = g->tun.iter_cap;
   p.err = g->err_out ? g->err_out : reinterpret_cast<uint32_t*>(g->ws);
   p.hub_degree = g->n_chunks > 0 ? g->tun.hub_degree : 0;
@@ -585,6 +588,7 @@ void mm_default_tuning(mm_tuning* t) {
   t->whole_graph_lds = 1;
   // a small graph alone keeps about 32 wavefronts in flight: fewer sources
   // racing at once, so repeated passes give matchings of nearly the same size
+  t->upper_only = 0;
   t->min_waves = 32;
   t->iter_cap = 0;
 }
@@ -702,8 +706,9 @@ mm_status mm_create(const void* offsets, mm_offset_type off_type, const int32_t*
   g->ws_bytes = workspace_bytes;
   g->flags = flags;
   g->tun = t;
-  // Lazy output is only sound when every edge is in both endpoints' lists.
-  g->lazy = t.lazy_init && (flags & MM_SYMMETRIC) && !t.relabel &&
+  // Lazy output is only sound when every edge is in both endpoints' lists
+  // and both endpoints examine it.
+  g->lazy = t.lazy_init && (flags & MM_SYMMETRIC) && !t.relabel && !t.upper_only &&
             !(t.layout == MM_LAYOUT_U32 && t.protocol == MM_PROTOCOL_CAS);
   // a graph swept whole by one wavefront gets no hub pieces (as in batches)
   if (t.hub_degree > 0 && m > t.hub_degree && n > t.whole_graph_vertices) {
@@ -835,7 +840,7 @@ mm_status mm_run_static(const void* offsets, mm_offset_type off_type, const int3
   g.rl = mmi::RelabelView{};
   g.rl_state = nullptr;
   g.err_out = status_out;
-  g.lazy = t.lazy_init && (flags & MM_SYMMETRIC) && pieces == 0 &&
+  g.lazy = t.lazy_init && (flags & MM_SYMMETRIC) && pieces == 0 && !t.upper_only &&
            !(t.layout == MM_LAYOUT_U32 && t.protocol == MM_PROTOCOL_CAS);
   if (pieces > 0) {
     auto* cursor = reinterpret_cast<unsigned long long*>(ws + mmi::kHubOffset);

@@ -82,6 +82,7 @@ struct SweepParams {
   int32_t scan_width;      // 1..kMaxW
   int32_t stream_loads;    // 1: offsets and ids through non-temporal loads
   int32_t wait_release;    // 1: release u while waiting for a reserved v
+  int32_t upper_only;      // 1 (symmetric input): examine only neighbours above the source
   int64_t iter_cap;        // 0: per-block default budget
   uint32_t* err;           // bit 0: loop-trip budget exceeded
   // Hub tier. Main pass: sources with more than hub_degree entries are left
@@ -189,6 +190,11 @@ __device__ __forceinline__ void sweep_block(const SweepParams& a, OffP __restric
   const int lane = (int)(threadIdx.x & 63);
   const int W = a.scan_width;
   const bool nt = a.stream_loads != 0;
+  // Each undirected edge once (Algorithm 1 iterates over E): on symmetric
+  // input the edge {x, y} is also in y's list, and the lane of min(x, y)
+  // examines it whenever that endpoint is unmatched, so a lane may skip the
+  // neighbours below its source without reading their states.
+  const bool upper = a.upper_only != 0;
   // Dispersed lanes: hand-out index kk goes to source (kk & 63) * stride +
   // (kk >> 6), so that the lanes of a wavefront work stride sources apart;
   // indices whose source lies past the block are skipped.
@@ -260,7 +266,8 @@ __device__ __forceinline__ void sweep_block(const SweepParams& a, OffP __restric
     uint32_t fw = 0;
 #pragma unroll
     for (int j = kMaxW - 1; j >= 0; --j) {
-      if (j >= k && j < nids && (int64_t)ids[j] != x && !filter_matched(rw[j], ids[j])) {
+      if (j >= k && j < nids && (int64_t)ids[j] != x && (!upper || ids[j] > x) &&
+          !filter_matched(rw[j], ids[j])) {
         found = j;
         fy = ids[j];
         fw = rw[j];
@@ -297,7 +304,15 @@ __device__ __forceinline__ void sweep_block(const SweepParams& a, OffP __restric
         steps += nids;
         k = 0;
         if (STATS) cnt.add(S_TOUCHED, (uint32_t)nids);
-        phase = P_STS;
+        bool any = !upper;
+#pragma unroll
+        for (int j = 0; j < kMaxW; ++j) any = any || (j < nids && ids[j] > x);
+        if (any) {
+          phase = P_STS;
+        } else {  // every id read is below the source: read on, no states
+          k = nids;
+          phase = (i < e) ? P_IDS : (LAZY ? P_FIN : P_IDLE);
+        }
         break;
       }
       case P_STS:
@@ -430,7 +445,7 @@ __device__ __forceinline__ void sweep_block(const SweepParams& a, OffP __restric
       case P_STS:
 #pragma unroll
         for (int j = 0; j < kMaxW; ++j)
-          if (j < nids && (int64_t)ids[j] != x) rw[j] = filter_word(ids[j]);
+          if (j < nids && (int64_t)ids[j] != x && (!upper || ids[j] > x)) rw[j] = filter_word(ids[j]);
         break;
       case P_RES:
         if (STATS) cnt.add(S_RES_ATT, 1);
@@ -467,7 +482,8 @@ __device__ __forceinline__ void sweep_block(const SweepParams& a, OffP __restric
 
     // ---------------- wavefront assist: consume
     if (asst == 2) {
-      const bool cand = aid >= 0 && (int64_t)aid != ax && !filter_matched(aw, aid);
+      const bool cand = aid >= 0 && (int64_t)aid != ax && (!upper || aid > ax) &&
+                        !filter_matched(aw, aid);
       const uint64_t cm = __ballot(cand);
       if (lane == al) {
         if (filter_matched(axw, x)) {
@@ -569,7 +585,7 @@ __device__ __forceinline__ void sweep_block(const SweepParams& a, OffP __restric
 
     // ---------------- wavefront assist: issue
     if (asst == 1) {
-      aw = (aid >= 0 && (int64_t)aid != ax) ? filter_word(aid) : 0u;
+      aw = (aid >= 0 && (int64_t)aid != ax && (!upper || aid > ax)) ? filter_word(aid) : 0u;
       if (lane == al) axw = filter_word(x);
       if (STATS && aid >= 0) cnt.add(S_ASSIST, 1);
       asst = 2;

@@ -42,7 +42,7 @@ def test_version_and_defaults():
     assert t.wg_size % 64 == 0 and t.wave_vertices % 64 == 0
     # the ctypes mirror has the C layout: the last fields read back as written
     assert t.whole_graph_vertices == 16384 and t.iter_cap == 0 and t.whole_graph_lds == 1
-    assert ctypes.sizeof(_lib.mm_tuning) == 80
+    assert ctypes.sizeof(_lib.mm_tuning) == 88
     from paper_2507_04420_amd import Tuning
     assert Tuning.default() == Tuning()  # the Python defaults mirror the library's
 

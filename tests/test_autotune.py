@@ -152,3 +152,29 @@ def test_multi_target_objective():
     assert abs(mt.measure(Tuning()) - 2.0) < 1e-9
     mt.parts.append(Part(5, None))
     assert mt.measure(Tuning()) is None
+
+
+def test_relabelling_must_win_by_its_premium():
+    # relabelled candidates count 3% slower: a 2% gain does not buy the copy,
+    # a 5% gain does, and a relabelled start gives way to a natural order
+    # that measures 1% slower
+    class Relabel(FakeTarget):
+        dims = ["relabel"]
+
+        def __init__(self, gain):
+            super().__init__()
+            self.gain = gain
+
+        def measure(self, t):
+            return 100.0 * (self.gain if t.relabel else 1.0)
+    assert autotune.search(Relabel(1.02), passes=1, log=lambda s: None)["tuning"]["relabel"] == 0
+    assert autotune.search(Relabel(1.05), passes=1, log=lambda s: None)["tuning"]["relabel"] == 1
+    r = autotune.search(Relabel(1.01), start=Tuning(relabel=1), passes=1, log=lambda s: None)
+    assert r["tuning"]["relabel"] == 0
+
+
+def test_paired_dimensions_move_together():
+    t = autotune._with(Tuning(), "upper_wait", (1, 1))
+    assert t.upper_only == 1 and t.wait_release == 1
+    assert autotune._value(t, "upper_wait") == (1, 1)
+    assert autotune._value(t, "layout_protocol") == (t.layout, t.protocol)

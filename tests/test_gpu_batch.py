@@ -29,6 +29,9 @@ TUNINGS = {
     "u32_bytehint": mm.Tuning(hint=2, whole_graph_vertices=0),
     "u32_whole_in_device_memory": mm.Tuning(whole_graph_lds=0),
     "u32_mesh128": mm.Tuning(whole_graph_vertices=0, mesh_wave_vertices=128),
+    "u32_upper_only": mm.Tuning(upper_only=1, whole_graph_vertices=0, hint=2),
+    "u8_upper_only_lazy_hubs": mm.Tuning(upper_only=1, layout=_lib.MM_LAYOUT_U8, lazy_init=1,
+                                         hub_degree=6, hub_chunk=3),
     "u8_mesh64_hubs": mm.Tuning(layout=_lib.MM_LAYOUT_U8, whole_graph_vertices=0, mesh_wave_vertices=64,
                                 hub_degree=8, hub_chunk=4, lazy_init=1),
     "u32_mesh128_wait_release": mm.Tuning(whole_graph_vertices=0, mesh_wave_vertices=128,

@@ -74,6 +74,14 @@ TUNINGS = {
     "wait_release_u8_two_lazy": mm.Tuning(layout=U8, protocol=TWO, wait_release=1, lazy_init=1,
                                           whole_graph_vertices=0, wave_vertices=64, wg_size=64),
     "wait_release_whole_lds": mm.Tuning(wait_release=1),
+    # each undirected edge examined from its lower endpoint only
+    "upper_only": mm.Tuning(upper_only=1),
+    "upper_only_multi_wave_u8": mm.Tuning(upper_only=1, layout=U8, whole_graph_vertices=0,
+                                          wave_vertices=64, lazy_init=1),
+    "upper_only_relabel": mm.Tuning(upper_only=1, relabel=1),
+    "upper_only_two_hub_assist": mm.Tuning(upper_only=1, protocol=TWO, hub_degree=5, hub_chunk=2,
+                                           whole_graph_vertices=0, assist_after=2, scan_width=1),
+    "upper_only_whole_device_wr": mm.Tuning(upper_only=1, whole_graph_lds=0, wait_release=1),
 }
 
 

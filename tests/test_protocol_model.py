@@ -1,0 +1,202 @@
+"""The reservation protocol under every schedule, in a CPU model of the
+sweep's lanes (tests/model/protocol_model.c; test infrastructure, no code
+shared with the library).
+
+Section V-A argues that the JIT protocol of Algorithm 1 is safe and ends;
+the library runs it in forms the argument does not cover: lanes of a
+wavefront advance together and poll instead of spinning, every memory
+operation of a trip is in flight until the wavefront's next trip, cached
+reads may be stale, and the options take v in two phases, give u back while
+waiting for v (wait_release), keep states in packed words whose CAS must be
+retried when another field changes, write unmatched outputs lazily, or
+examine each edge only from its lower endpoint (upper_only). The model runs
+the lanes' state machine with the memory operations applied in an order an
+adversary picks. Pins:
+
+* exhaustive: on every graph of up to 4 vertices (two-wavefront placements
+  of the packed layouts: the sparser ones), every state reachable under any
+  schedule can still reach the end of the sweep (no deadlock, and no
+  livelock under fair scheduling), and every output at the end is a maximal
+  matching of the graph (a member of the oracle's brute-force set);
+* adversarial schedules: on every graph of up to 6 vertices, under four
+  scheduling strategies (uniform, operations in flight as long as possible,
+  near lockstep, one wavefront starved), the sweep ends within its trip
+  bound with an output in the brute-force set; the same on random 8-vertex
+  graphs with four lanes in two wavefronts;
+* the model is sharp: three mistakes planted in it (no id order, no release
+  of u, v taken by a plain store) are each caught on a small graph.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+
+from model import explore, graph, lanes, load, run, variant
+
+VARIANTS = {
+    "word_cas": dict(layout="word"),
+    "word_cas_wait_release": dict(layout="word", wait_release=1),
+    "word_two_phase": dict(layout="word", two_phase=1),
+    "word_two_phase_lazy_wait_release": dict(layout="word", two_phase=1, lazy=1, wait_release=1),
+    "word_cas_upper": dict(layout="word", upper=1),
+    "u8_cas_word_retries": dict(layout="u8"),
+    "u8_cas_lazy_wait_release": dict(layout="u8", lazy=1, wait_release=1),
+    "u8_two_phase": dict(layout="u8", two_phase=1),
+    "u2_cas_upper_wait_release": dict(layout="u2", upper=1, wait_release=1),
+    "u2_two_phase_lazy": dict(layout="u2", two_phase=1, lazy=1),
+}
+STRATEGIES = (0, 1, 2, 3)
+
+
+def all_graphs(n):
+    pairs = list(itertools.combinations(range(n), 2))
+    for mask in range(1 << len(pairs)):
+        yield graphgen.from_edges(n, [pairs[i] for i in range(len(pairs)) if mask >> i & 1])
+
+
+_MAXIMAL = {}
+
+
+def maximal_set(csr):
+    """The maximal matchings of a small graph as mate tuples (brute force)."""
+    key = (csr.n, tuple(csr.off.tolist()), tuple(csr.nbr.tolist()))
+    if key not in _MAXIMAL:
+        _MAXIMAL[key] = {tuple(int(v) for v in m)
+                         for m in oracle.enumerate_matchings(csr, maximal_only=True)}
+    return _MAXIMAL[key]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _built():
+    load()
+
+
+def test_model_on_the_worked_example():
+    # the graph of Figs. 1 and 6: two lanes in one wavefront reach one of its
+    # three maximal matchings on every schedule
+    g = graphgen.from_edges(4, [(0, 1), (0, 2), (0, 3), (1, 2), (2, 3)])
+    ok = maximal_set(g)
+    assert ok == {(2, -1, 0, -1), (1, 0, 3, 2), (3, 2, 1, 0)}
+    for name, v in VARIANTS.items():
+        wave_of, src = lanes(4, 1, 2, "round")
+        states, stuck, n_outs, outs = explore(graph(g), variant(**v), wave_of, src)
+        assert states > 0 and stuck == 0 and n_outs > 0, name
+        assert {tuple(o.tolist()) for o in outs} <= ok, name
+
+
+EXHAUSTIVE_CONFIGS = [(2, 1, "round"), (1, 2, "round"), (2, 1, "blocks")]
+
+
+@pytest.mark.parametrize("name", sorted(VARIANTS))
+def test_every_schedule_ends_in_a_maximal_matching(name):
+    # all 64 graphs on 4 vertices (smaller graphs are among them, with
+    # isolated vertices). Word layouts: every placement of the sources on
+    # lanes below. Packed layouts: stale reads are left to the random
+    # schedules (a stale copy of a shared word multiplies the states), two
+    # lanes of one wavefront on every graph, and two wavefronts on the
+    # sparser graphs (at most 4 edges for the CAS protocol, 2 for two-phase,
+    # whose commits of u and v and their mate writes interleave in every
+    # order)
+    v = dict(VARIANTS[name])
+    packed = v["layout"] != "word"
+    if packed:
+        v["stale"] = 0
+    var = variant(**v)
+    graphs = list(all_graphs(4))
+    total = 0
+    for w, p, mode in EXHAUSTIVE_CONFIGS:
+        wave_of, src = lanes(4, w, p, mode)
+        for idx, g in enumerate(graphs):
+            edges = bin(idx).count("1")
+            if packed and w > 1 and (mode != "round" or edges > (2 if v.get("two_phase") else 4)):
+                continue
+            states, stuck, n_outs, outs = explore(graph(g), var, wave_of, src, max_states=400000)
+            assert states > 0, (name, idx, (w, p, mode), states)
+            assert stuck == 0, (name, idx, (w, p, mode), stuck)
+            assert n_outs > 0, (name, idx, n_outs)
+            ok = maximal_set(g)
+            for o in outs:
+                assert tuple(o.tolist()) in ok, (name, idx, o)
+            total += states
+    assert total > 1000
+
+
+def _adversarial(graphs, lanes_cfg, name, strategies=STRATEGIES, seed0=1):
+    var = variant(**VARIANTS[name])
+    worst = 0
+    for idx, g in enumerate(graphs):
+        ok = maximal_set(g)
+        G = graph(g)
+        w, p, mode = lanes_cfg[idx % len(lanes_cfg)]
+        wave_of, src = lanes(g.n, w, p, mode)
+        for s in strategies:
+            trips, mate = run(G, var, wave_of, src, strategy=s, seed=seed0 + 7919 * idx + s,
+                              max_trips=20000)
+            assert trips >= 0, (name, g.n, idx, s, trips)
+            assert tuple(mate.tolist()) in ok, (name, g.n, idx, s, mate)
+            worst = max(worst, trips)
+    return worst
+
+
+@pytest.mark.parametrize("name", sorted(VARIANTS))
+def test_adversarial_schedules_on_every_graph_up_to_6_vertices(name):
+    cfgs = [(2, 1, "round"), (1, 2, "blocks"), (2, 2, "round"), (3, 1, "blocks")]
+    worst = 0
+    for n in range(1, 6):
+        worst = max(worst, _adversarial(list(all_graphs(n)), cfgs, name))
+    # 6 vertices: every graph, one strategy each (all four over the set)
+    var = variant(**VARIANTS[name])
+    for idx, g in enumerate(all_graphs(6)):
+        ok = maximal_set(g)
+        w, p, mode = cfgs[idx % len(cfgs)]
+        wave_of, src = lanes(6, w, p, mode)
+        trips, mate = run(graph(g), var, wave_of, src, strategy=idx % 4, seed=idx, max_trips=20000)
+        assert trips >= 0, (name, idx, trips)
+        assert tuple(mate.tolist()) in ok, (name, idx, mate)
+        worst = max(worst, trips)
+    # far inside the bound: polling never runs away
+    assert worst < 2000, worst
+
+
+@pytest.mark.parametrize("name", sorted(VARIANTS))
+def test_adversarial_schedules_on_larger_graphs(name):
+    # 8 vertices, four lanes in two wavefronts (and the other placements)
+    rng = np.random.default_rng(11)
+    graphs = []
+    for _ in range(150):
+        p = rng.uniform(0.2, 0.8)
+        E = [(a, b) for a, b in itertools.combinations(range(8), 2) if rng.random() < p]
+        graphs.append(graphgen.from_edges(8, E))
+    _adversarial(graphs, [(2, 2, "round"), (2, 2, "blocks"), (4, 1, "round"), (1, 4, "round")],
+                 name, seed0=3)
+
+
+@pytest.mark.parametrize("mutant", [1, 2, 3])
+def test_model_catches_planted_mistakes(mutant):
+    # the model is sharp: each mistake planted in it (in the model, on the
+    # CPU) is caught on some small graph as a state from which the sweep can
+    # never end, or as an output that is not a maximal matching
+    #   1: no id order (u = the source): two lanes hold each other's v
+    #   2: u is never given back after a failed take of v: its holder's
+    #      neighbours wait for it forever
+    #   3: v taken by a plain store after a read saw it free: two lanes both
+    #      "take" the same v
+    caught = False
+    for n in (2, 3, 4):
+        for g in all_graphs(n):
+            ok = maximal_set(g)
+            for w, p, mode in EXHAUSTIVE_CONFIGS:
+                wave_of, src = lanes(n, w, p, mode)
+                states, stuck, n_outs, outs = explore(graph(g), variant("word", mutant=mutant),
+                                                      wave_of, src, max_states=200000)
+                if stuck > 0 or n_outs < 0 or any(tuple(o.tolist()) not in ok for o in outs):
+                    caught = True
+                    break
+            if caught:
+                break
+        if caught:
+            break
+    assert caught, mutant
