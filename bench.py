@@ -347,6 +347,12 @@ VARIANTS = {
     "upper_only_hint_bytes": {"upper_only": 1, "hint": 2},
     "upper_only_u8": {"upper_only": 1, "layout": 0, "protocol": 0, "lazy_init": 0},
     "upper_only_natural": {"upper_only": 1, "relabel": 0},
+    "hub_wave": {"hub_wave": 1},
+    "hub_wave_1024": {"hub_wave": 1, "hub_chunk": 1024},
+    "hub_lane_64": {"hub_chunk": 64},
+    "no_hub_tier": {"hub_degree": 0},
+    "u32": {"layout": 1, "protocol": 0, "lazy_init": 0},
+    "u8": {"layout": 0, "protocol": 0, "lazy_init": 0},
 }
 
 
@@ -392,6 +398,55 @@ def bench_variants(args, csr, off, nbr, base, t_seq):
             name, row["sweep_ms"], row["gedges_per_s"], row["t_gpu_over_m"], row["atomics"],
             row["conflicts"], row["violations"]))
     return rows
+
+
+def bench_ab(args, csr, off, nbr, base):
+    """Interleaved A/B of two variants: one handle each, created once and
+    kept; rounds alternate A then B (then B then A) so that neither gains
+    from its position; every round times `steps` passes of each by the
+    handles' sweep events. Reports per variant the median and spread of the
+    round means, and the median of the paired differences B - A."""
+    import paper_2507_04420_amd as mm
+    names = args.ab.split(",")
+    if len(names) != 2:
+        raise SystemExit("--ab takes two variant names")
+    tun = [mm.Tuning(**dict(base.as_dict(), **VARIANTS[nm])) for nm in names]
+    hs = [mm.Graph(off, nbr, symmetric=True, timing=True, tuning=t) for t in tun]
+    outs = [h.run() for h in hs]
+    for h in hs:
+        h.sync()
+        h.timing()
+    means = [[], []]
+    for r in range(args.ab_rounds):
+        order = (0, 1) if r % 2 == 0 else (1, 0)
+        for k in order:
+            for _ in range(args.steps):
+                hs[k].run(outs[k])
+            hs[k].sync()
+            means[k].append(hs[k].timing()["mean_ms"])
+    viol = [sum(h.check(o)[k] for k in VIOLATION_KEYS) for h, o in zip(hs, outs)]
+    for h in hs:
+        h.close()
+    diff = [b - a for a, b in zip(means[0], means[1])]
+    rows = []
+    for k in range(2):
+        v = np.array(means[k])
+        rows.append({"variant": names[k], "tuning": tun[k].as_dict(),
+                     "median_ms": round(float(np.median(v)), 4), "min_ms": round(float(v.min()), 4),
+                     "max_ms": round(float(v.max()), 4), "sd_ms": round(float(v.std()), 4),
+                     "gedges_per_s": round(csr.m / float(np.median(v)) / 1e6, 1),
+                     "violations": int(viol[k]), "round_means_ms": [round(x, 4) for x in v]})
+        log("ab %-20s median %.4f ms (min %.4f max %.4f sd %.4f) over %d rounds" % (
+            names[k], rows[-1]["median_ms"], rows[-1]["min_ms"], rows[-1]["max_ms"],
+            rows[-1]["sd_ms"], args.ab_rounds))
+    d = np.array(diff)
+    res = {"rows": rows, "median_diff_ms": round(float(np.median(d)), 4),
+           "diff_min_ms": round(float(d.min()), 4), "diff_max_ms": round(float(d.max()), 4),
+           "b_faster_rounds": int((d < 0).sum()), "rounds": args.ab_rounds, "steps": args.steps}
+    log("ab %s - %s: median %.4f ms, range %.4f .. %.4f, %s faster in %d of %d rounds" % (
+        names[1], names[0], res["median_diff_ms"], res["diff_min_ms"], res["diff_max_ms"], names[1],
+        res["b_faster_rounds"], args.ab_rounds))
+    return res
 
 
 def bench_serve(args, dev):
@@ -587,8 +642,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="rmat27", help="the headline workload")
     ap.add_argument("--legs", default=",".join(LEGS),
-                    help="comma-separated subset of %s (default: all; the headline always runs)"
-                         % ",".join(LEGS))
+                    help="comma-separated subset of %s (default: all; without the headline "
+                         "the line holds only the legs asked for)" % ",".join(LEGS))
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--layout", default=None, choices=["u8", "u32", "u2"])
     ap.add_argument("--lazy", type=int, default=None)
@@ -610,6 +665,12 @@ def main():
                     help="comma-separated design-choice variants (%s): time and count each on the "
                          "workload and print one JSON line of rows instead of the benchmark line"
                          % ",".join(VARIANTS))
+    ap.add_argument("--no-ceilings", action="store_true",
+                    help="skip the live random-read and random-atomic probes (profiling runs)")
+    ap.add_argument("--ab", default=None,
+                    help="two variants (names as for --variants): interleaved A/B rounds on one "
+                         "handle each; prints one JSON line of the comparison")
+    ap.add_argument("--ab-rounds", type=int, default=20)
     ap.add_argument("--untuned", action="store_true",
                     help="library default tunings instead of the autotuned table")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -661,6 +722,15 @@ def main():
         del src, dst
         log("copy calibration: 3 x (1 GiB read + 1 GiB write) with torch.add(src, 0, out=dst)")
 
+    if args.ab:
+        csr, config = make_workload(args.workload, args.seed)
+        off = torch.from_numpy(csr.off).to(dev)
+        nbr = torch.from_numpy(csr.nbr).to(dev)
+        res = bench_ab(args, csr, off, nbr, tuning_for(workload_class(args.workload)))
+        print(json.dumps(dict({"mode": "ab", "config": config, "n": csr.n, "m": csr.m}, **res)),
+              flush=True)
+        return
+
     if args.variants:
         csr, config = make_workload(args.workload, args.seed)
         ref, t_sgmm, reps, core = cpu_baseline(csr)
@@ -673,9 +743,25 @@ def main():
                           "rows": rows}), flush=True)
         return
 
-    ceilings = live_ceilings(dev)
-    log("live ceilings: %.3g random reads/s, %.3g random atomics/s" % (
-        ceilings["random_reads_per_s"], ceilings["random_atomics_per_s"]))
+    ceilings = None if args.no_ceilings else live_ceilings(dev)
+    if ceilings:
+        log("live ceilings: %.3g random reads/s, %.3g random atomics/s" % (
+            ceilings["random_reads_per_s"], ceilings["random_atomics_per_s"]))
+
+    if "headline" not in legs:
+        # a subset of the legs (profiling runs): one JSON line of those
+        out = {"mode": "legs", "ceilings": ceilings}
+        for name in ("er65536", "rmat24", "grid16384"):
+            if name in legs:
+                out[name] = bench_single(args, name, tuning_for(workload_class(name)), dev,
+                                         natural=True, ceilings=ceilings)[0]
+        if "batch" in legs:
+            tb = mm.Tuning.default() if args.untuned else autotune.tuned("batch")
+            out["batch"] = dict(bench_batch(args, tb, dev), tuning=tb.as_dict())
+        if "serve" in legs:
+            out["serve"] = bench_serve(args, dev)
+        print(json.dumps(out), flush=True)
+        return
 
     # the headline graph first, while the device is empty
     head, counters, conflicts, sweep = bench_single(
@@ -702,14 +788,15 @@ def main():
     achieved = b_sweep / sweep_s / 1e9
     cfg_traffic = dict(cfg, tuning={k: int(v) for k, v in cfg["tuning"].items()})
     traffic, traffic_rec = stored_traffic(cfg_traffic)
-    secondary = dict(ceilings)
+    secondary = dict(ceilings or {})
     if counters:
         secondary["atomics_per_launch"] = head.get("atomics_per_launch")
         secondary["atomic_frac"] = head.get("atomic_frac")
     if traffic_rec and traffic_rec.get("l2_miss_read_requests_per_launch"):
         req = float(traffic_rec["l2_miss_read_requests_per_launch"])
         secondary["l2_miss_read_requests_per_launch_stored"] = req
-        secondary["request_frac"] = round(req / sweep_s / ceilings["random_reads_per_s"], 4)
+        if ceilings:
+            secondary["request_frac"] = round(req / sweep_s / ceilings["random_reads_per_s"], 4)
     result = {
         "metric": METRIC,
         "value": round(value, 3),

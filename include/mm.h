@@ -187,6 +187,11 @@ typedef struct {
                             edge of E once; its mirror entry in the higher
                             endpoint's list is passed over. Output is eager
                             (lazy_init does not apply) */
+  int32_t hub_wave;      /* 1: each piece of a long list (hub_degree) is swept by a
+                            whole wavefront, 64 ids per step read together, the
+                            first candidate found by a ballot and reserved by one
+                            lane, the source's state checked before every step;
+                            0: by one lane, like any other source's list */
   int32_t min_waves;     /* a graph alone (mm_run) or a batch whose blocked sources
                             are too few for this many wavefronts of wave_vertices
                             sources gets shorter blocks, so that about this many

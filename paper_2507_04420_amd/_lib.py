@@ -54,6 +54,7 @@ class mm_tuning(ctypes.Structure):
         ("mesh_wave_vertices", ctypes.c_int32),
         ("wait_release", ctypes.c_int32),
         ("upper_only", ctypes.c_int32),
+        ("hub_wave", ctypes.c_int32),
         ("min_waves", ctypes.c_int32),
         ("iter_cap", ctypes.c_int64),
     ]

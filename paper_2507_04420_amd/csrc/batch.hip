@@ -21,6 +21,7 @@
 #include "batch.h"
 #include "internal.h"
 #include "mm.h"
+#include "pieces.h"
 #include "sweep.h"
 #include "whole.h"
 
@@ -169,6 +170,10 @@ __global__ __launch_bounds__(256) void batch_sweep_kernel(SweepParams p,
       pp.wave_vertices = 64;
       pp.disperse = 0;
       pp.hub_degree = 0;
+      if (pp.hub_wave) {
+        sweep_pieces_wave<Layout, HINT, STATS>(pp, d.nbr, L, w.vb, nv, cnt);
+        continue;
+      }
     } else {
       pp.chunks = nullptr;
       if (d.flags & kWholeGraph) {  // as mm_run sweeps a graph whole
@@ -546,11 +551,12 @@ mm_status finish_create(std::vector<mmb::GraphDesc>& descs, const std::vector<in
     int64_t first = 0;
     for (int32_t g = 0; g < G; ++g) {
       const int64_t k = descs[g].pieces;
-      for (int64_t c = 0; c < k; c += 64) {
+      const int64_t per = t.hub_wave ? mmk::kWavePieces : 64;  // pieces per item
+      for (int64_t c = 0; c < k; c += per) {
         mmb::WorkItem w;
         w.desc = g;
         w.vb = first + c;
-        w.nv = -(int32_t)std::min<int64_t>(64, k - c);
+        w.nv = -(int32_t)std::min<int64_t>(per, k - c);
         items.push_back(w);
       }
       descs[g].pieces = first;
@@ -621,6 +627,7 @@ mm_status finish_create(std::vector<mmb::GraphDesc>& descs, const std::vector<in
   p.params.stream_loads = t.stream_loads;
   p.params.wait_release = t.wait_release;
   p.params.upper_only = (t.upper_only && (flags & MM_SYMMETRIC)) ? 1 : 0;
+  p.params.hub_wave = t.hub_wave;
   p.params.iter_cap = t.iter_cap;
   p.params.hub_degree = n_chunks > 0 ? t.hub_degree : 0;
   p.params.hub_chunk = t.hub_chunk;
@@ -696,9 +703,10 @@ size_t mm_batch_create_device_bytes(int32_t num_graphs, const int64_t* vtx_off, 
   const int64_t pieces = blocked ? mmi::hub_pieces_bound(M, t.hub_degree, t.hub_chunk) : 0;
   if (pieces == 0) return 0;
   // the item table moves to the handle's own allocation, with one item per
-  // run of 64 pieces of a graph (at most pieces / 64 + num_graphs of them),
-  // followed by the piece table
-  const int64_t items = L.n_items + pieces / 64 + num_graphs;
+  // run of 64 pieces of a graph (kWavePieces in the wavefront tier: at most
+  // pieces / per + num_graphs of them), followed by the piece table
+  const int64_t per = t.hub_wave ? mmk::kWavePieces : 64;
+  const int64_t items = L.n_items + pieces / per + num_graphs;
   return round_up(sizeof(mmb::WorkItem) * (size_t)items, 256) +
          round_up(sizeof(mmk::HubChunk) * (size_t)pieces, 256);
 }

@@ -14,6 +14,7 @@
 
 #include "internal.h"
 #include "mm.h"
+#include "pieces.h"
 #include "sweep.h"
 #include "whole.h"
 
@@ -75,6 +76,8 @@ mm_status check_tuning(const mm_tuning& t) {
   if (t.min_waves < 0) return fail(MM_ERR_INVALID_ARG, "tuning.min_waves must be >= 0");
   if (t.upper_only != 0 && t.upper_only != 1)
     return fail(MM_ERR_INVALID_ARG, "tuning.upper_only must be 0 or 1");
+  if (t.hub_wave != 0 && t.hub_wave != 1)
+    return fail(MM_ERR_INVALID_ARG, "tuning.hub_wave must be 0 or 1");
   if (t.mesh_wave_vertices < 0 || t.mesh_wave_vertices % 64)
     return fail(MM_ERR_INVALID_ARG, "tuning.mesh_wave_vertices must be 0 or a positive multiple of 64");
   return MM_OK;
@@ -201,7 +204,8 @@ __global__ void validate_kernel(const OffT* __restrict__ off, const int32_t* __r
 
 // One graph: wavefront w < main_waves sweeps sources [v_begin + w *
 // wave_vertices, ...); the wavefronts after them (dispatched last) take the
-// hub tier's pieces, 64 to a wavefront, as one launch with the main pass.
+// hub tier's pieces, as one launch with the main pass: 64 to a wavefront, one
+// per lane, or (hub_wave) kWavePieces, swept by the whole wavefront.
 // chunk_count (device, or null): the number of pieces when only the device
 // knows it (the table was filled by this pass's own stream); n_chunks is then
 // the table's capacity, which sizes the grid.
@@ -224,12 +228,19 @@ __global__ __launch_bounds__(256) void sweep_kernel(SweepParams p, const OffT* _
       const int64_t c = (int64_t)*chunk_count;
       n_chunks = c < n_chunks ? c : n_chunks;
     }
-    vb = (wave - main_waves) * 64;
+    const int64_t per = p.hub_wave ? kWavePieces : 64;
+    vb = (wave - main_waves) * per;
     if (vb >= n_chunks) return;
-    nv = (n_chunks - vb < 64) ? (n_chunks - vb) : 64;
+    nv = (n_chunks - vb < per) ? (n_chunks - vb) : per;
     p.wave_vertices = 64;
     p.disperse = 0;
     p.hub_degree = 0;
+    if (p.hub_wave) {
+      Counters<STATS> cnt;
+      sweep_pieces_wave<Layout, HINT, STATS>(p, nbr, L, vb, nv, cnt);
+      if (STATS) cnt.flush(stats);
+      return;
+    }
   }
   __shared__ QSlot queues[4][kQueue];  // one ring per wavefront (wg_size <= 256)
   Counters<STATS> cnt;
@@ -339,6 +350,7 @@ SweepParams make_params(const mm_graph* g) {
   p.stream_loads = g->tun.stream_loads;
   p.wait_release = g->tun.wait_release;
   p.upper_only = (g->tun.upper_only && (g->flags & MM_SYMMETRIC)) ? 1 : 0;
+  p.hub_wave = g->tun.hub_wave;
   p.iter_cap = g->tun.iter_cap;
   p.err = g->err_out ? g->err_out : reinterpret_cast<uint32_t*>(g->ws);
   p.hub_degree = g->n_chunks > 0 ? g->tun.hub_degree : 0;
@@ -397,8 +409,10 @@ hipError_t launch_sweep(const mm_graph* g, const Layout& L, hipStream_t s) {
                                : static_cast<const OffT*>(g->off);
   const int32_t* nbr = g->relabel ? g->rl.nbr : g->nbr;
   const int64_t waves = (g->n - v_begin + p.wave_vertices - 1) / p.wave_vertices;
-  // the hub tier's pieces: 64 to a wavefront, after the main pass's waves
-  const int64_t chunk_waves = (g->n_chunks + 63) / 64;
+  // the hub tier's pieces: 64 to a wavefront (kWavePieces in the wavefront
+  // tier), after the main pass's waves
+  const int64_t per = p.hub_wave ? kWavePieces : 64;
+  const int64_t chunk_waves = (g->n_chunks + per - 1) / per;
   SweepParams pl = p;
   pl.chunks = g->chunks;
   const int wpb = g->tun.wg_size / 64;
@@ -589,6 +603,7 @@ void mm_default_tuning(mm_tuning* t) {
   // a small graph alone keeps about 32 wavefronts in flight: fewer sources
   // racing at once, so repeated passes give matchings of nearly the same size
   t->upper_only = 0;
+  t->hub_wave = 0;
   t->min_waves = 32;
   t->iter_cap = 0;
 }

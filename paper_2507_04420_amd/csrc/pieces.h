@@ -1,0 +1,212 @@
+// The wavefront tier of long lists (tuning.hub_wave): one wavefront sweeps a
+// piece of a long list (the hub tier's table entry: entries b .. e-1 of source
+// x), 64 ids per step.
+//
+// Per step the 64 lanes read 64 consecutive ids (256 bytes, coalesced) and
+// the states of those neighbours, and every lane re-reads the source's own
+// state, so the piece stops as soon as the source is matched elsewhere (the
+// early exit of Fig. 6g, per step instead of per id). A ballot finds the
+// candidates in list order; for the first one, lane 0 runs the reservation of
+// Algorithm 1 (take u = min(x, y), take v = max(x, y), commit or give u back)
+// while the other lanes wait. Only lane 0 ever holds a vertex, and only while
+// it runs one edge, so no lane of the wavefront waits on another lane of the
+// same wavefront: lane 0 may poll a reservation another wavefront holds until
+// it is released or committed (every such wait is on a higher id, as in the
+// per-lane sweep). The list is read once, coalesced, with the source checked
+// before every 64 ids: the GPU form of a thread walking a hub's list.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "protocol.h"
+#include "sweep.h"
+
+namespace mmk {
+
+enum : int { E_MATCHED = 0, E_X_DEAD, E_Y_DEAD, E_BUDGET };
+
+// Pieces a wavefront takes per launch slot (single graphs) or work item
+// (batches) in the wavefront tier; the lane tier takes 64, one per lane.
+constexpr int kWavePieces = 4;
+
+__device__ __forceinline__ uint32_t bcast(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+
+// One edge (x, y) by lane 0 for the whole wavefront (every lane runs the
+// same uniform loop; only lane 0 touches memory). guess: the word the filter
+// read for v (packed layouts' CAS guess). Returns E_MATCHED, E_X_DEAD (the
+// source is matched: the piece is done), E_Y_DEAD (the edge is dead), or
+// E_BUDGET (the loop budget ran out; nothing is held).
+template <class Layout, bool STATS>
+__device__ __forceinline__ int run_edge(const SweepParams& a, const Layout& L, int32_t x, int32_t y,
+                                        uint32_t guess, uint32_t xorig, int64_t& budget,
+                                        Counters<STATS>& cnt) {
+  const bool l0 = (threadIdx.x & 63) == 0;
+  const int32_t u = x < y ? x : y, v = x < y ? y : x;
+  uint32_t vguess = guess;
+  uint32_t econf = 0;
+  enum { RES, CHK, MAT, MATW, VW } ph = RES;
+  auto dead = [&](int32_t w) {
+    if (STATS && l0) cnt.edge_done(econf);
+    return w == x ? E_X_DEAD : E_Y_DEAD;
+  };
+  while (true) {
+    if (--budget < 0) {
+      if (l0 && (ph == MAT || ph == MATW)) L.release(u);  // held: give it back
+      return E_BUDGET;
+    }
+    if (ph == RES) {
+      uint32_t r = 0;
+      if (l0) {
+        r = L.reserve(u);
+        if (STATS) cnt.add(S_RES_ATT, 1);
+      }
+      r = bcast(r);
+      const int s = Layout::decode(r, u);
+      if (s == R_ACC) {
+        ph = MAT;
+      } else {
+        ++econf;
+        if (STATS && l0) cnt.add(s == R_MCHD ? S_RES_MCHD : S_RES_CONF, 1);
+        if (s == R_MCHD) return dead(u);
+        ph = CHK;
+      }
+    } else if (ph == CHK) {
+      uint32_t ru = 0, rv = 0;
+      if (l0) {
+        ru = L.word_coherent(u);
+        rv = L.word_coherent(v);
+      }
+      ru = bcast(ru);
+      rv = bcast(rv);
+      if (Layout::decode(rv, v) == R_MCHD) return dead(v);
+      const int su = Layout::decode(ru, u);
+      if (su == R_MCHD) return dead(u);
+      if (su == R_ACC) ph = RES;
+    } else if (ph == MAT) {
+      uint32_t r = 0;
+      if (l0) {
+        r = Layout::kTwoPhase ? L.reserve(v) : L.match(v, u, vguess);
+        if (STATS) cnt.add(S_MAT_ATT, 1);
+      }
+      r = bcast(r);
+      bool won;
+      int s;
+      if (Layout::kTwoPhase) {
+        s = Layout::decode(r, v);
+        won = s == R_ACC;
+      } else {
+        won = Layout::match_ok(r, vguess, v);
+        s = won ? R_ACC : Layout::decode(r, v);
+      }
+      if (won) {
+        if (l0) {
+          if constexpr (Layout::kRelabelled)
+            L.commit_src(u, v, x, (int32_t)xorig);
+          else
+            L.commit(u, v);
+          if (STATS) {
+            cnt.add(S_PAIRS, 1);
+            cnt.edge_done(econf);
+          }
+        }
+        return E_MATCHED;
+      }
+      if (s == R_ACC) {  // another field of v's word changed: try again
+        if (STATS && l0) cnt.add(S_WORD_RETRY, 1);
+        vguess = r;
+      } else if (s == R_RSVD) {
+        ++econf;
+        if (STATS && l0) cnt.add(S_MAT_CONF, 1);
+        if (a.wait_release) {
+          if (l0) L.release(u);
+          ph = VW;
+        } else {
+          ph = MATW;
+        }
+      } else {
+        ++econf;
+        if (STATS && l0) cnt.add(S_MAT_MCHD, 1);
+        if (l0) L.release(u);
+        return dead(v);
+      }
+    } else {  // MATW (holding u) or VW (holding nothing): wait for v
+      uint32_t r = 0;
+      if (l0) r = L.word_coherent(v);
+      r = bcast(r);
+      const int s = Layout::decode(r, v);
+      if (s == R_ACC) {
+        vguess = r;
+        ph = ph == MATW ? MAT : RES;
+      } else if (s == R_MCHD) {
+        if (ph == MATW && l0) L.release(u);
+        return dead(v);
+      }
+    }
+  }
+}
+
+// Sweeps pieces p0 .. p0+np-1 of the hub table a.chunks with this wavefront.
+template <class Layout, bool HINT, bool STATS, class NbrP = const int32_t*>
+__device__ __forceinline__ void sweep_pieces_wave(const SweepParams& a, NbrP __restrict__ nbr,
+                                                  const Layout& L, int64_t p0, int64_t np,
+                                                  Counters<STATS>& cnt) {
+  const int lane = (int)(threadIdx.x & 63);
+  const bool upper = a.upper_only != 0;
+  const bool nt = a.stream_loads != 0;
+  auto filter_word = [&](int64_t y) -> uint32_t {
+    if (HINT) return ld_cached(L.hint.word(y));
+    return L.word_cached(y);
+  };
+  auto filter_matched = [&](uint32_t word, int64_t y) -> bool {
+    if (HINT) return ((word >> L.hint.shift(y)) & 1u) != 0;
+    return Layout::matched(word, y);
+  };
+  // loop budget: one step per 64 entries of every piece and the polls of its
+  // edges, with the per-block default's slack
+  int64_t budget = a.iter_cap > 0 ? a.iter_cap : 65536 + 8 * np * a.hub_chunk;
+  int64_t steps = 0;
+  for (int64_t q = p0; q < p0 + np; ++q) {
+    const HubChunk c = a.chunks[q];
+    const int32_t x = c.x;
+    uint32_t xorig = 0;
+    if constexpr (Layout::kRelabelled) xorig = (uint32_t)L.orig[x];
+    bool done = false;
+    for (int64_t i = c.b; i < c.e && !done; i += 64) {
+      ++steps;
+      if (--budget < 0) {
+        if (lane == 0) atomicOr(a.err, 1u);
+        return;
+      }
+      const bool have = i + lane < c.e;
+      const int32_t y = have ? ld_stream(nbr + i + lane, nt) : x;
+      const bool ok = have && y != x && (!upper || y > x);
+      const uint32_t yw = ok ? filter_word(y) : 0u;
+      const uint32_t xw = bcast(filter_word(x));
+      if (STATS && lane == 0) cnt.add(S_TOUCHED, (uint32_t)(c.e - i < 64 ? c.e - i : 64));
+      if (filter_matched(xw, x)) break;  // the source is matched: the rest is skipped
+      uint64_t cand = __ballot(ok && !filter_matched(yw, y));
+      while (cand) {
+        const int l = __builtin_ctzll(cand);
+        cand &= cand - 1;
+        const int32_t yy = __builtin_amdgcn_readlane(y, l);
+        const uint32_t yyw = (uint32_t)__builtin_amdgcn_readlane((int)yw, l);
+        // the CAS guess for v: the word read for it (the hint carries none)
+        const uint32_t guess = HINT ? 0u : (x < yy ? yyw : xw);
+        const int r = run_edge<Layout, STATS>(a, L, x, yy, guess, xorig, budget, cnt);
+        if (r == E_BUDGET) {
+          if (lane == 0) atomicOr(a.err, 1u);
+          return;
+        }
+        if (r != E_Y_DEAD) {
+          done = true;
+          break;
+        }
+      }
+    }
+  }
+  if (STATS) cnt.add(S_TRIPS, lane == 0 ? (uint32_t)steps : 0u);
+}
+
+}  // namespace mmk

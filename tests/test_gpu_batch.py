@@ -30,6 +30,10 @@ TUNINGS = {
     "u32_whole_in_device_memory": mm.Tuning(whole_graph_lds=0),
     "u32_mesh128": mm.Tuning(whole_graph_vertices=0, mesh_wave_vertices=128),
     "u32_upper_only": mm.Tuning(upper_only=1, whole_graph_vertices=0, hint=2),
+    "u32_hub_wave": mm.Tuning(hub_wave=1, hub_degree=6, hub_chunk=65, whole_graph_vertices=0),
+    "u2_two_hub_wave_upper": mm.Tuning(hub_wave=1, hub_degree=3, hub_chunk=5, layout=_lib.MM_LAYOUT_U2,
+                                       protocol=_lib.MM_PROTOCOL_TWO_PHASE, upper_only=1,
+                                       whole_graph_vertices=0),
     "u8_upper_only_lazy_hubs": mm.Tuning(upper_only=1, layout=_lib.MM_LAYOUT_U8, lazy_init=1,
                                          hub_degree=6, hub_chunk=3),
     "u8_mesh64_hubs": mm.Tuning(layout=_lib.MM_LAYOUT_U8, whole_graph_vertices=0, mesh_wave_vertices=64,
@@ -263,6 +267,7 @@ def test_batch_hub_pieces_are_fast():
     import time
     parts = [hub_trap(100_000)]
     for name, t in (("tier", mm.Tuning(whole_graph_vertices=0)),
+                    ("wave_tier", mm.Tuning(whole_graph_vertices=0, hub_wave=1)),
                     ("no_tier", mm.Tuning(whole_graph_vertices=0, hub_degree=0))):
         b = mm.Batch.from_list(list_of(parts), symmetric=True, tuning=t)
         out = b.run()
@@ -273,8 +278,8 @@ def test_batch_hub_pieces_are_fast():
         dt = time.perf_counter() - t0
         assert oracle.check(parts[0], out.cpu().numpy()).ok
         print("batch hub trap", name, "%.3f ms" % (dt * 1e3))
-        if name == "tier":
-            tier = dt
+        if name != "no_tier":
+            tier = max(dt, tier if name == "wave_tier" else 0.0)
         else:
             assert tier * 3 < dt
 

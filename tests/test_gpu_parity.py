@@ -82,6 +82,13 @@ TUNINGS = {
     "upper_only_two_hub_assist": mm.Tuning(upper_only=1, protocol=TWO, hub_degree=5, hub_chunk=2,
                                            whole_graph_vertices=0, assist_after=2, scan_width=1),
     "upper_only_whole_device_wr": mm.Tuning(upper_only=1, whole_graph_lds=0, wait_release=1),
+    # long lists swept by whole wavefronts, 64 ids per step
+    "hub_wave_every_list": mm.Tuning(hub_wave=1, hub_degree=1, hub_chunk=3, whole_graph_vertices=0),
+    "hub_wave_u8_relabel": mm.Tuning(hub_wave=1, hub_degree=5, hub_chunk=70, relabel=1, layout=U8),
+    "hub_wave_two_upper_wr": mm.Tuning(hub_wave=1, hub_degree=8, hub_chunk=100, protocol=TWO,
+                                       upper_only=1, wait_release=1, whole_graph_vertices=0),
+    "hub_wave_bit_hint_u2": mm.Tuning(hub_wave=1, hub_degree=4, hub_chunk=64, hint=1, layout=U2,
+                                      protocol=TWO, whole_graph_vertices=0),
 }
 
 
@@ -489,7 +496,8 @@ def test_hub_tier_spreads_a_long_dead_list():
     g = hub_trap(1_000_000)
     off, nbr = to_dev(g)
     times = {}
-    for name, t in (("tier", mm.Tuning()), ("no_tier", mm.Tuning(hub_degree=0))):
+    for name, t in (("tier", mm.Tuning()), ("wave_tier", mm.Tuning(hub_wave=1)),
+                    ("no_tier", mm.Tuning(hub_degree=0))):
         h = mm.Graph(off, nbr, symmetric=True, tuning=t, timing=True)
         out = h.run()
         h.sync()
@@ -501,3 +509,4 @@ def test_hub_tier_spreads_a_long_dead_list():
         h.close()
     print("hub trap sweep ms:", times)
     assert times["tier"] * 5 < times["no_tier"]
+    assert times["wave_tier"] * 5 < times["no_tier"]

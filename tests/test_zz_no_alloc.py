@@ -39,24 +39,36 @@ def run_static(csr, tuning=None, off32=False):
     return out[:csr.n].cpu().numpy(), int(status.item())
 
 
-def run_handle(csr, tuning=None):
+def run_handle(csr, tuning=None, passes=5):
+    """`passes` mm_run passes of one handle (the outputs of each)."""
     off = torch.from_numpy(csr.off.astype(np.int64)).cuda()
     nbr = torch.from_numpy(csr.nbr).cuda()
     g = mm.Graph(off, nbr, symmetric=True, tuning=tuning)
-    out = g.run()
-    g.sync()
+    outs = []
+    for _ in range(passes):
+        out = g.run()
+        g.sync()
+        outs.append(out.cpu().numpy())
     g.close()
-    return out.cpu().numpy()
+    return outs
 
 
-def compare(csr, a, b, exact):
-    ca, cb = oracle.check(csr, a), oracle.check(csr, b)
-    assert ca.ok and cb.ok, (csr.name, ca, cb)
+def compare(csr, a, runs, exact):
+    """a: the static pass's output; runs: mm_run's. Both checker-clean; equal
+    where the result cannot depend on the schedule; otherwise the static
+    pass's size lies within the spread of mm_run's sizes widened by the
+    alone-vs-mix tolerance (results vary from pass to pass, Section V-C, so
+    one pass against one pass would test the schedule, not the entry point)."""
+    ca = oracle.check(csr, a)
+    cbs = [oracle.check(csr, b) for b in runs]
+    assert ca.ok and all(cb.ok for cb in cbs), (csr.name, ca, cbs)
     if exact:
-        np.testing.assert_array_equal(a, b)
+        for b in runs:
+            np.testing.assert_array_equal(a, b)
     else:
         bound = max(2, 0.01 * oracle.sgmm(csr).pairs)
-        assert abs(ca.size - cb.size) <= bound, (csr.name, ca.size, cb.size, bound)
+        sizes = [cb.size for cb in cbs]
+        assert min(sizes) - bound <= ca.size <= max(sizes) + bound, (csr.name, ca.size, sizes, bound)
 
 
 HUBS = mm.Tuning(hub_degree=256, hub_chunk=64, whole_graph_vertices=0)
