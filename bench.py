@@ -44,17 +44,47 @@ METRIC = "GEdges/s single-pass MM + % HBM roofline; batched vs per-graph graphs/
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_kernel_traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2507_04420_amd", "csrc", f)
-                  for f in ("protocol.h", "sweep.h", "mm.hip", "relabel.hip", "hubs.hip")]
+                  for f in ("protocol.h", "sweep.h", "pieces.h", "internal.h", "mm.hip", "relabel.hip",
+                            "hubs.hip")]
 VIOLATION_KEYS = ("out_of_range", "self_mate", "asymmetric", "not_edge", "uncovered")
 LEGS = ("headline", "er65536", "rmat24", "grid16384", "batch", "serve")
 
 
+def strip_comments(src: str) -> str:
+    """C/C++ source without its comments and with runs of whitespace
+    collapsed (string and character literals kept as they are), so that a
+    change of comments alone leaves the code's hash unchanged."""
+    out = []
+    i, n = 0, len(src)
+    while i < n:
+        c = src[i]
+        if c in "\"'":
+            j = i + 1
+            while j < n and src[j] != c:
+                j += 2 if src[j] == "\\" else 1
+            out.append(src[i:j + 1])
+            i = j + 1
+        elif src.startswith("//", i):
+            j = src.find("\n", i)
+            i = n if j < 0 else j
+        elif src.startswith("/*", i):
+            j = src.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        else:
+            out.append(c)
+            i += 1
+    return "\n".join(" ".join(line.split()) for line in "".join(out).splitlines() if line.strip())
+
+
 def kernel_sources_sha256() -> str:
+    """SHA-256 of the code (comments stripped) of the sources that decide
+    what the sweep kernel does and which graph it reads."""
     import hashlib
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(f, "rb") as fh:
-            h.update(fh.read())
+        with open(f, encoding="utf-8") as fh:
+            h.update(strip_comments(fh.read()).encode())
     return h.hexdigest()
 
 
@@ -330,6 +360,9 @@ def bench_single(args, name, tun, dev, *, natural=False, conflicts=False, ceilin
 VARIANTS = {
     "tuned": {},
     "natural_order": {"relabel": 0},
+    "relabelled": {"relabel": 1},
+    "all_entries": {"upper_only": 0},
+    "all_entries_relabelled": {"upper_only": 0, "relabel": 1},
     "u8_byte_cas": {"layout": 0, "protocol": 0, "lazy_init": 0},
     "u8_byte_cas_lazy": {"layout": 0, "protocol": 0, "lazy_init": 1},
     "u2_two_phase": {"layout": 2, "protocol": 1, "lazy_init": 0},
@@ -347,6 +380,7 @@ VARIANTS = {
     "upper_only_hint_bytes": {"upper_only": 1, "hint": 2},
     "upper_only_u8": {"upper_only": 1, "layout": 0, "protocol": 0, "lazy_init": 0},
     "upper_only_natural": {"upper_only": 1, "relabel": 0},
+    "upper_wait": {"upper_only": 1, "wait_release": 1},
     "hub_wave": {"hub_wave": 1},
     "hub_wave_1024": {"hub_wave": 1, "hub_chunk": 1024},
     "hub_lane_64": {"hub_chunk": 64},

@@ -94,7 +94,7 @@ enum {
                          for a given output and replay it afterwards */
 };
 
-/* How the higher endpoint v of an edge is taken (Algorithm 1, L13-14). */
+/* How the higher endpoint v of an edge is taken (Algorithm 1's second step). */
 typedef enum {
   /* As printed: one CAS moves v from accessible to matched. */
   MM_PROTOCOL_CAS = 0,
@@ -173,7 +173,7 @@ typedef struct {
                             the tuning alone */
   int32_t wait_release;  /* 1: a lane that finds v reserved by another lane
                             releases u while it waits, and takes u again once
-                            v is accessible (Algorithm 1 holds u, L13-14). No
+                            v is accessible (Algorithm 1 holds u meanwhile). No
                             lane then waits on a lane that is itself waiting,
                             so no chain of reservations forms, which on meshes
                             swept by many lanes at once can grow as long as a
@@ -203,8 +203,8 @@ typedef struct {
 } mm_tuning;
 
 /* Counters of the instrumented kernels (MM_STATS). Conflicts follow Table II
-   of the paper: a failed CAS while reserving u (Algorithm 1 L11) or taking v
-   (L14), whatever state it met: a reservation by another lane (RSVD, counted
+   of the paper: a failed CAS while reserving u or taking v (Algorithm 1),
+   whatever state it met: a reservation by another lane (RSVD, counted
    in reserve_conflicts / match_conflicts) or a match made since the lane's
    cached read of the state (MCHD, counted in reserve_matched /
    match_matched). An edge's conflicts are those met from the moment a lane

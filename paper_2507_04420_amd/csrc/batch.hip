@@ -271,7 +271,7 @@ hipError_t enqueue_typed(const BatchPlan& bp, hipStream_t s) {
   if (bp.hint) fill(bp.hint_base, bp.hint_words, 0u, s);
   hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(64), 0, s, bp.queue);
   const bool two = bp.protocol == MM_PROTOCOL_TWO_PHASE;
-  // init (Algorithm 1, L1-4) for every graph; the graphs kept in LDS then
+  // init (the start of Algorithm 1) for every graph; the graphs kept in LDS then
   // overwrite their own mates, ahead of the persistent sweep of the rest
   if (bp.layout == MM_LAYOUT_U32) {
     fill(mate_w, bp.N, two ? LayoutU32<true>::kAcc : LayoutU32<false>::kAcc, s);

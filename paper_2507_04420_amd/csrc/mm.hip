@@ -145,8 +145,8 @@ __host__ __device__ inline FillRegion fill_region(uint32_t* p, int64_t words, ui
   return r;
 }
 
-// Fills `words` 32-bit words with `value` (state and mate initialisation,
-// Alg. 1 L3-4). Any 4-byte alignment.
+// Fills `words` 32-bit words with `value` (the initialisation of states and
+// mates that opens Algorithm 1). Any 4-byte alignment.
 __global__ void fill_u32_kernel(FillRegion r) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -1,4 +1,4 @@
-// Matched-pair list output (the `matches` array of Algorithm 1, L16 and L19).
+// Matched-pair list output (the `matches` array that Algorithm 1 fills and returns).
 //
 // The sweep records its result in the mate array; this pass turns a mate
 // array into the list of matched pairs (u, v), u < v, each pair once. Every

@@ -7,7 +7,7 @@
 // absorbing.
 //
 // Two ways to take v (template parameter TWO_PHASE):
-//   * as printed in Algorithm 1 (L14): one CAS moves v from ACC to MCHD;
+//   * as printed in Algorithm 1: one CAS moves v from ACC to MCHD;
 //   * two-phase: v is reserved with the same operation as u (ACC -> RSVD),
 //     and once both are held the holder marks both matched. The transitions
 //     are still those of Fig. 4 (ACC -> RSVD -> MCHD). The linearisation

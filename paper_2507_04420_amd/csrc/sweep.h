@@ -12,11 +12,11 @@
 //
 // Per lane, one source x at a time (Section II-B, CSR form):
 //   * skip x if it is already matched (Fig. 6g);
-//   * walk N_x in stored order, W ids at a time; skip self-loops (Alg. 1 L6-7)
+//   * walk N_x in stored order, W ids at a time; skip self-loops (Algorithm 1)
 //     and neighbours seen matched; for a candidate y take u = min(x,y),
-//     v = max(x,y) (L8-9, which rules out reservation cycles) and run the
-//     reservation: reserve u (L11), take v (L13-14), then mark u matched (L15)
-//     or release it (L17-18);
+//     v = max(x,y) (the id order of Algorithm 1, which rules out reservation
+//     cycles) and run the reservation: reserve u, take v, then mark u matched
+//     or release it;
 //   * stop at the first matched pair: the rest of N_x is never read.
 //
 // Pipelining. A lane's work is a chain of dependent memory operations
@@ -27,8 +27,8 @@
 //
 // Waiting without intra-wavefront spin. Lanes of a wavefront share one
 // instruction stream, so no lane may loop waiting for a reservation that
-// another lane of its wavefront holds. Every wait of Algorithm 1 (L11's
-// "continue" on a reserved u, L13's loop on a reserved v) is "stay in this
+// another lane of its wavefront holds. Every wait of Algorithm 1 (the retry
+// on a reserved u, the loop on a reserved v) is "stay in this
 // phase and poll again next trip". Reservation chains only wait on higher ids
 // (u < v), so the lane at the top of any chain meets ACC or MCHD and finishes.
 // With wait_release a lane releases u before it waits for v, so no lane waits
@@ -55,10 +55,10 @@ enum : int {
   P_IDLE = 0,  // needs a source
   P_IDS,       // next W neighbour ids requested
   P_STS,       // states of the buffered ids requested
-  P_RES,       // reserve(u) issued (Alg. 1 L11)
-  P_CHK,       // u was reserved by another lane: coherent re-read of u and v (L10)
-  P_MAT,       // v requested: CAS ACC -> MCHD (L14), or reserve(v) (two-phase)
-  P_MATW,      // v was reserved by another lane: coherent re-read of v (L13)
+  P_RES,       // reserve(u) issued (Algorithm 1's take of u)
+  P_CHK,       // u was reserved by another lane: coherent re-read of u and v
+  P_MAT,       // v requested: CAS ACC -> MCHD, or reserve(v) (two-phase)
+  P_MATW,      // v was reserved by another lane: coherent re-read of v
   P_VW,        // the same wait with u released first (wait_release): then u again
   P_FIN,       // list exhausted: final check of the source's own state
   P_ASST,      // paused while the wavefront scans ahead for this lane

@@ -5,10 +5,9 @@
  *
  * What it models. Every lane of the GPU sweep walks the lists of its sources
  * and, for a candidate edge (x, y), runs the reservation of Algorithm 1 with
- * u = min(x, y), v = max(x, y): take u (L11), take v (L13-14), then mark u
- * matched (L15) or give u back (L17-18). On the GPU the lanes of a wavefront
- * share one instruction stream, so the model follows the library's form of
- * the protocol, not a thread's:
+ * u = min(x, y), v = max(x, y): take u, take v, then mark u matched or give
+ * u back. On the GPU the lanes of a wavefront share one instruction stream,
+ * so the model follows the library's form of the protocol, not a thread's:
  *   * a wavefront advances in trips; a trip first consumes, for every lane of
  *     the wavefront, the result of the memory operation the lane issued on the
  *     previous trip, then lets every lane issue its next operation;

@@ -35,6 +35,17 @@ def test_traffic_lookup(tmp_path, monkeypatch):
     assert bench.stored_traffic(cfg) == (None, None)  # kernel changed since
 
 
+def test_code_hash_ignores_comments_only():
+    # the stored traffic stays valid across a change of comments, and not
+    # across a change of code (string literals are code)
+    a = 'int f(int x) { // one\n  return x + 1; /* two */ }\nconst char* s = "// kept";\n'
+    b = '/* header */\nint f(int x) {\n\n  return x + 1;   }\nconst char* s = "// kept";  // more\n'
+    assert bench.strip_comments(a) == bench.strip_comments(b)
+    assert bench.strip_comments(a) != bench.strip_comments(a.replace("x + 1", "x + 2"))
+    assert bench.strip_comments(a) != bench.strip_comments(a.replace('"// kept"', '"kept"'))
+    assert "one" not in bench.strip_comments(a) and "two" not in bench.strip_comments(a)
+
+
 def test_algorithmic_bytes():
     # per source w + 1 + 4, per id of a sequential pass 4 + 1 (the sweep's
     # units); with the states once per vertex instead: w(n+1) + 4 T + 2n + 4n
