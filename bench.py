@@ -361,6 +361,11 @@ VARIANTS = {
     "tuned": {},
     "natural_order": {"relabel": 0},
     "relabelled": {"relabel": 1},
+    "relabel_hot": {"relabel": 2},
+    "relabel_hot_512": {"relabel": 2, "hot_degree": 512},
+    "relabel_hot_1024": {"relabel": 2, "hot_degree": 1024},
+    "relabel_hot_4096": {"relabel": 2, "hot_degree": 4096},
+    "relabel_hot_8192": {"relabel": 2, "hot_degree": 8192},
     "all_entries": {"upper_only": 0},
     "all_entries_relabelled": {"upper_only": 0, "relabel": 1},
     "u8_byte_cas": {"layout": 0, "protocol": 0, "lazy_init": 0},
@@ -385,6 +390,14 @@ VARIANTS = {
     "hub_wave_1024": {"hub_wave": 1, "hub_chunk": 1024},
     "hub_lane_64": {"hub_chunk": 64},
     "no_hub_tier": {"hub_degree": 0},
+    "stream_loads": {"stream_loads": 1},
+    "scan_2": {"scan_width": 2},
+    "scan_3": {"scan_width": 3},
+    "hub_2048": {"hub_degree": 2048},
+    "hub_16384": {"hub_degree": 16384},
+    "wg_256": {"wg_size": 256},
+    "wv_1024": {"wave_vertices": 1024},
+    "wv_4096": {"wave_vertices": 4096},
     "u32": {"layout": 1, "protocol": 0, "lazy_init": 0},
     "u8": {"layout": 0, "protocol": 0, "lazy_init": 0},
 }

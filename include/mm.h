@@ -127,7 +127,7 @@ typedef struct {
   int32_t lazy_init;     /* 1: unmatched outputs written by the sweep itself instead
                             of a separate fill (needs MM_SYMMETRIC; not with
                             MM_LAYOUT_U32 + MM_PROTOCOL_CAS, where it is implicit) */
-  int32_t scan_width;    /* neighbour ids a lane reads per scan step: 1..8 */
+  int32_t scan_width;    /* neighbour ids a lane reads per scan step: 1..4 */
   int32_t stream_loads;  /* 1: read offsets and neighbour ids with non-temporal loads,
                             so that their lines are evicted first and the state (or
                             hint) lines stay in L2 longer */
@@ -135,12 +135,19 @@ typedef struct {
                             by one wavefront (one work item of a batch), which makes
                             its result independent of concurrent work: the same
                             alone as inside any batch; 0 disables */
-  int32_t relabel;       /* 1 (single graphs only): mm_create builds, in the
-                            workspace, a copy of the graph with vertices renumbered
-                            by ascending log2-degree bucket (isolated first, given
-                            order kept inside a bucket). The sweep runs on it: low-
-                            degree sources first, hub states packed into few cache
-                            lines. Output stays in the given ids. Workspace from
+  int32_t relabel;       /* single graphs only: mm_create builds, in the
+                            workspace, a copy of the graph with vertices renumbered,
+                            and the sweep runs on it; output stays in the given
+                            ids. 1: by ascending log2-degree bucket (isolated
+                            first, given order kept inside a bucket; lists of up
+                            to 64 entries sorted by new id): low-degree sources
+                            first, hub states packed into few cache lines.
+                            2: the given order, except that isolated vertices come
+                            first and vertices of more than hot_degree entries
+                            last (given order kept inside each group; lists in
+                            their given order): the sweep keeps the given order
+                            of sources while the states most scans read share a
+                            few cache lines. 0: none. Workspace from
                             mm_workspace_bytes_graph; create allocates temporary
                             device memory for the sort */
   int32_t hub_degree;    /* lists longer than this are not swept by their block's
@@ -187,16 +194,21 @@ typedef struct {
                             edge of E once; its mirror entry in the higher
                             endpoint's list is passed over. Output is eager
                             (lazy_init does not apply) */
-  int32_t hub_wave;      /* 1: each piece of a long list (hub_degree) is swept by a
-                            whole wavefront, 64 ids per step read together, the
-                            first candidate found by a ballot and reserved by one
+  int32_t hub_wave;      /* 1: a wavefront takes 64 pieces of long lists
+                            (hub_degree), checks their sources one per lane, and
+                            sweeps each piece whose source is still free with all
+                            its lanes: 64 ids per step read together, the first
+                            candidate found by a ballot and reserved by one
                             lane, the source's state checked before every step;
-                            0: by one lane, like any other source's list */
+                            0: each piece by one lane, like any other source's
+                            list */
   int32_t min_waves;     /* a graph alone (mm_run) or a batch whose blocked sources
                             are too few for this many wavefronts of wave_vertices
                             sources gets shorter blocks, so that about this many
                             wavefronts share it (never shorter than 64 sources);
                             0 keeps wave_vertices whatever the size */
+  int32_t hot_degree;    /* relabel = 2: vertices with more entries than this go to
+                            the top of the new ids; >= 1 */
   int64_t iter_cap;      /* loop-trip budget per wavefront; 0 = default of
                             65536 + 8 x (neighbour entries of its block);
                             exceeding it raises MM_ERR_NO_PROGRESS */
@@ -242,8 +254,8 @@ void mm_default_tuning(mm_tuning* t);
 size_t mm_workspace_bytes_graph(int64_t n, int64_t m, const mm_tuning* t);
 
 /* Bytes of device workspace a graph of n vertices needs under tuning t
-   (NULL = defaults). Returns 0 if n or t is invalid, and for t.relabel = 1,
-   whose workspace depends on m (use mm_workspace_bytes_graph). */
+   (NULL = defaults). Returns 0 if n or t is invalid, and for a nonzero
+   t.relabel, whose workspace depends on m (use mm_workspace_bytes_graph). */
 size_t mm_workspace_bytes(int64_t n, const mm_tuning* t);
 
 /* Upper bound of the device memory mm_create allocates by itself for a graph

@@ -52,6 +52,7 @@ class Tuning:
     upper_only: int = 0
     hub_wave: int = 0
     min_waves: int = 32
+    hot_degree: int = 2048
     iter_cap: int = 0
 
     @classmethod

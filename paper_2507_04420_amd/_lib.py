@@ -56,6 +56,7 @@ class mm_tuning(ctypes.Structure):
         ("upper_only", ctypes.c_int32),
         ("hub_wave", ctypes.c_int32),
         ("min_waves", ctypes.c_int32),
+        ("hot_degree", ctypes.c_int32),
         ("iter_cap", ctypes.c_int64),
     ]
 

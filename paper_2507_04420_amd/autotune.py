@@ -36,7 +36,8 @@ SPACE = {
                         (_lib.MM_LAYOUT_U8, _lib.MM_PROTOCOL_CAS),
                         (_lib.MM_LAYOUT_U2, _lib.MM_PROTOCOL_TWO_PHASE),
                         (_lib.MM_LAYOUT_U32, _lib.MM_PROTOCOL_TWO_PHASE)],
-    "relabel": [0, 1],
+    "relabel": [0, 1, 2],
+    "hot_degree": [512, 1024, 2048, 4096, 8192],
     "hint": [0, 1, 2],
     "disperse": [0, 1],
     "wave_vertices": [64, 128, 256, 512, 1024, 2048, 4096],

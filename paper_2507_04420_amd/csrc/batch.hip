@@ -551,7 +551,7 @@ mm_status finish_create(std::vector<mmb::GraphDesc>& descs, const std::vector<in
     int64_t first = 0;
     for (int32_t g = 0; g < G; ++g) {
       const int64_t k = descs[g].pieces;
-      const int64_t per = t.hub_wave ? mmk::kWavePieces : 64;  // pieces per item
+      const int64_t per = mmk::kPiecesPerWave;  // pieces per item
       for (int64_t c = 0; c < k; c += per) {
         mmb::WorkItem w;
         w.desc = g;
@@ -703,9 +703,9 @@ size_t mm_batch_create_device_bytes(int32_t num_graphs, const int64_t* vtx_off, 
   const int64_t pieces = blocked ? mmi::hub_pieces_bound(M, t.hub_degree, t.hub_chunk) : 0;
   if (pieces == 0) return 0;
   // the item table moves to the handle's own allocation, with one item per
-  // run of 64 pieces of a graph (kWavePieces in the wavefront tier: at most
-  // pieces / per + num_graphs of them), followed by the piece table
-  const int64_t per = t.hub_wave ? mmk::kWavePieces : 64;
+  // run of 64 pieces of a graph (at most pieces / 64 + num_graphs of them),
+  // followed by the piece table
+  const int64_t per = mmk::kPiecesPerWave;
   const int64_t items = L.n_items + pieces / per + num_graphs;
   return round_up(sizeof(mmb::WorkItem) * (size_t)items, 256) +
          round_up(sizeof(mmk::HubChunk) * (size_t)pieces, 256);

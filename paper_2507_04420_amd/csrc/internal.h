@@ -40,6 +40,8 @@ uint32_t handle_flags(const mm_graph* h);
 
 // A graph relabelled by degree (see relabel.hip), in a workspace region of
 // relabel_bytes(n, m) bytes: int64 offsets, new -> given id map, neighbours.
+// mode 1: by log2-degree bucket; mode 2: isolated first, then the given order,
+// vertices of more than hot entries last.
 struct RelabelView {
   int64_t* off;
   int32_t* orig;
@@ -58,7 +60,7 @@ inline int64_t hub_pieces_bound(int64_t m, int64_t hub_degree, int64_t chunk) {
   return m / chunk + m / (hub_degree + 1);
 }
 hipError_t build_relabel(const void* off, int off64, const int32_t* nbr, int64_t n, int64_t m,
-                         uint8_t* region, RelabelView* view, hipStream_t s);
+                         int mode, int64_t hot, uint8_t* region, RelabelView* view, hipStream_t s);
 
 // The hub tier's table (see hubs.hip), allocated stream-ordered on s and
 // released with free_owned by the handle's owner; *count = 0 and *table = null

@@ -63,8 +63,10 @@ mm_status check_tuning(const mm_tuning& t) {
     return fail(MM_ERR_INVALID_ARG, "tuning.stream_loads must be 0 or 1");
   if (t.whole_graph_vertices < 0)
     return fail(MM_ERR_INVALID_ARG, "tuning.whole_graph_vertices must be >= 0");
-  if (t.relabel != 0 && t.relabel != 1)
-    return fail(MM_ERR_INVALID_ARG, "tuning.relabel must be 0 or 1");
+  if (t.relabel < 0 || t.relabel > 2)
+    return fail(MM_ERR_INVALID_ARG, "tuning.relabel must be 0, 1 or 2");
+  if (t.relabel == 2 && t.hot_degree < 1)
+    return fail(MM_ERR_INVALID_ARG, "tuning.hot_degree must be >= 1 with relabel = 2");
   if (t.hub_degree < 0) return fail(MM_ERR_INVALID_ARG, "tuning.hub_degree must be >= 0");
   if (t.hub_degree > 0 && t.hub_chunk < 1)
     return fail(MM_ERR_INVALID_ARG, "tuning.hub_chunk must be >= 1 when hub_degree > 0");
@@ -204,8 +206,8 @@ __global__ void validate_kernel(const OffT* __restrict__ off, const int32_t* __r
 
 // One graph: wavefront w < main_waves sweeps sources [v_begin + w *
 // wave_vertices, ...); the wavefronts after them (dispatched last) take the
-// hub tier's pieces, as one launch with the main pass: 64 to a wavefront, one
-// per lane, or (hub_wave) kWavePieces, swept by the whole wavefront.
+// hub tier's pieces, as one launch with the main pass: 64 to a wavefront, each
+// swept by one lane, or (hub_wave) each live one by the whole wavefront.
 // chunk_count (device, or null): the number of pieces when only the device
 // knows it (the table was filled by this pass's own stream); n_chunks is then
 // the table's capacity, which sizes the grid.
@@ -228,7 +230,7 @@ __global__ __launch_bounds__(256) void sweep_kernel(SweepParams p, const OffT* _
       const int64_t c = (int64_t)*chunk_count;
       n_chunks = c < n_chunks ? c : n_chunks;
     }
-    const int64_t per = p.hub_wave ? kWavePieces : 64;
+    const int64_t per = kPiecesPerWave;
     vb = (wave - main_waves) * per;
     if (vb >= n_chunks) return;
     nv = (n_chunks - vb < per) ? (n_chunks - vb) : per;
@@ -409,9 +411,8 @@ hipError_t launch_sweep(const mm_graph* g, const Layout& L, hipStream_t s) {
                                : static_cast<const OffT*>(g->off);
   const int32_t* nbr = g->relabel ? g->rl.nbr : g->nbr;
   const int64_t waves = (g->n - v_begin + p.wave_vertices - 1) / p.wave_vertices;
-  // the hub tier's pieces: 64 to a wavefront (kWavePieces in the wavefront
-  // tier), after the main pass's waves
-  const int64_t per = p.hub_wave ? kWavePieces : 64;
+  // the hub tier's pieces: 64 to a wavefront, after the main pass's waves
+  const int64_t per = kPiecesPerWave;
   const int64_t chunk_waves = (g->n_chunks + per - 1) / per;
   SweepParams pl = p;
   pl.chunks = g->chunks;
@@ -605,6 +606,7 @@ void mm_default_tuning(mm_tuning* t) {
   t->upper_only = 0;
   t->hub_wave = 0;
   t->min_waves = 32;
+  t->hot_degree = 2048;
   t->iter_cap = 0;
 }
 
@@ -704,7 +706,8 @@ mm_status mm_create(const void* offsets, mm_offset_type off_type, const int32_t*
     const size_t base = kCtrlBytes + mmi::state_bytes(n, t) + mmi::hint_bytes(n, t);
     rl_state = reinterpret_cast<int32_t*>(ws + base);
     uint8_t* region = ws + base + mmi::round_up(sizeof(int32_t) * (size_t)n, 256);
-    hipError_t e = mmi::build_relabel(offsets, off_type == MM_OFF_I64, neighbors, n, m, region, &rl, s);
+    hipError_t e = mmi::build_relabel(offsets, off_type == MM_OFF_I64, neighbors, n, m, t.relabel,
+                                      t.hot_degree, region, &rl, s);
     if (e != hipSuccess) return fail(MM_ERR_HIP, "relabelling failed: %s", hipGetErrorString(e));
   }
   mm_graph* g = new (std::nothrow) mm_graph();

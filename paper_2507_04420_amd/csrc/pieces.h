@@ -1,19 +1,23 @@
-// The wavefront tier of long lists (tuning.hub_wave): one wavefront sweeps a
-// piece of a long list (the hub tier's table entry: entries b .. e-1 of source
-// x), 64 ids per step.
+// The wavefront tier of long lists (tuning.hub_wave): a wavefront takes 64
+// pieces of long lists (the hub tier's table entries: entries b .. e-1 of
+// source x), like the lane tier, but sweeps each live one with all its lanes.
 //
-// Per step the 64 lanes read 64 consecutive ids (256 bytes, coalesced) and
-// the states of those neighbours, and every lane re-reads the source's own
-// state, so the piece stops as soon as the source is matched elsewhere (the
-// early exit of Fig. 6g, per step instead of per id). A ballot finds the
-// candidates in list order; for the first one, lane 0 runs the reservation of
-// Algorithm 1 (take u = min(x, y), take v = max(x, y), commit or give u back)
-// while the other lanes wait. Only lane 0 ever holds a vertex, and only while
-// it runs one edge, so no lane of the wavefront waits on another lane of the
-// same wavefront: lane 0 may poll a reservation another wavefront holds until
-// it is released or committed (every such wait is on a higher id, as in the
-// per-lane sweep). The list is read once, coalesced, with the source checked
-// before every 64 ids: the GPU form of a thread walking a hub's list.
+// First every lane reads the state of one piece's source, so pieces whose
+// source is already matched (most of them, since hubs are usually matched as
+// neighbours before their pieces run) cost one parallel load, as in the lane
+// tier. Then, for each live piece in table order, the 64 lanes read 64
+// consecutive ids per step (256 bytes, coalesced) and the states of those
+// neighbours, and every lane re-reads the source's own state, so the piece
+// stops as soon as the source is matched elsewhere (the early exit of Fig. 6g,
+// per step instead of per id). A ballot finds the candidates in list order;
+// for the first one, lane 0 runs the reservation of Algorithm 1 (take
+// u = min(x, y), take v = max(x, y), commit or give u back) while the other
+// lanes wait. Only lane 0 ever holds a vertex, and only while it runs one
+// edge, so no lane of the wavefront waits on another lane of the same
+// wavefront: lane 0 may poll a reservation another wavefront holds until it
+// is released or committed (every such wait is on a higher id, as in the
+// per-lane sweep). A live list is read once, coalesced, with the source
+// checked before every 64 ids: the GPU form of a thread walking a hub's list.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -26,8 +30,8 @@ namespace mmk {
 enum : int { E_MATCHED = 0, E_X_DEAD, E_Y_DEAD, E_BUDGET };
 
 // Pieces a wavefront takes per launch slot (single graphs) or work item
-// (batches) in the wavefront tier; the lane tier takes 64, one per lane.
-constexpr int kWavePieces = 4;
+// (batches), in either tier: one per lane.
+constexpr int kPiecesPerWave = 64;
 
 __device__ __forceinline__ uint32_t bcast(uint32_t v) {
   return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
@@ -147,7 +151,8 @@ __device__ __forceinline__ int run_edge(const SweepParams& a, const Layout& L, i
   }
 }
 
-// Sweeps pieces p0 .. p0+np-1 of the hub table a.chunks with this wavefront.
+// Sweeps pieces p0 .. p0+np-1 (np <= 64) of the hub table a.chunks with this
+// wavefront.
 template <class Layout, bool HINT, bool STATS, class NbrP = const int32_t*>
 __device__ __forceinline__ void sweep_pieces_wave(const SweepParams& a, NbrP __restrict__ nbr,
                                                   const Layout& L, int64_t p0, int64_t np,
@@ -163,28 +168,41 @@ __device__ __forceinline__ void sweep_pieces_wave(const SweepParams& a, NbrP __r
     if (HINT) return ((word >> L.hint.shift(y)) & 1u) != 0;
     return Layout::matched(word, y);
   };
+  // one piece per lane: its source's state decides whether the piece is live
+  HubChunk mine{0, 0, 0, 0};
+  bool live = false;
+  if (lane < np) {
+    mine = a.chunks[p0 + lane];
+    live = !filter_matched(filter_word(mine.x), mine.x);
+  }
+  uint64_t todo = __ballot(live);
   // loop budget: one step per 64 entries of every piece and the polls of its
   // edges, with the per-block default's slack
   int64_t budget = a.iter_cap > 0 ? a.iter_cap : 65536 + 8 * np * a.hub_chunk;
-  int64_t steps = 0;
-  for (int64_t q = p0; q < p0 + np; ++q) {
-    const HubChunk c = a.chunks[q];
-    const int32_t x = c.x;
+  int64_t steps = 1;
+  while (todo) {
+    const int pl = __builtin_ctzll(todo);
+    todo &= todo - 1;
+    const int32_t x = __builtin_amdgcn_readlane(mine.x, pl);
+    const int64_t cb = ((int64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)mine.b, pl)) |
+                       ((int64_t)__builtin_amdgcn_readlane((int)(mine.b >> 32), pl) << 32);
+    const int64_t ce = ((int64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)mine.e, pl)) |
+                       ((int64_t)__builtin_amdgcn_readlane((int)(mine.e >> 32), pl) << 32);
     uint32_t xorig = 0;
     if constexpr (Layout::kRelabelled) xorig = (uint32_t)L.orig[x];
     bool done = false;
-    for (int64_t i = c.b; i < c.e && !done; i += 64) {
+    for (int64_t i = cb; i < ce && !done; i += 64) {
       ++steps;
       if (--budget < 0) {
         if (lane == 0) atomicOr(a.err, 1u);
         return;
       }
-      const bool have = i + lane < c.e;
+      const bool have = i + lane < ce;
       const int32_t y = have ? ld_stream(nbr + i + lane, nt) : x;
       const bool ok = have && y != x && (!upper || y > x);
       const uint32_t yw = ok ? filter_word(y) : 0u;
       const uint32_t xw = bcast(filter_word(x));
-      if (STATS && lane == 0) cnt.add(S_TOUCHED, (uint32_t)(c.e - i < 64 ? c.e - i : 64));
+      if (STATS && lane == 0) cnt.add(S_TOUCHED, (uint32_t)(ce - i < 64 ? ce - i : 64));
       if (filter_matched(xw, x)) break;  // the source is matched: the rest is skipped
       uint64_t cand = __ballot(ok && !filter_matched(yw, y));
       while (cand) {

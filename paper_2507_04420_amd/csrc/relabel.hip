@@ -1,17 +1,29 @@
-// Create-time relabelling of a graph by degree (tuning.relabel).
+// Create-time relabelling of a graph (tuning.relabel).
 //
-// New ids list the vertices by ascending log2-degree bucket (isolated
-// vertices first), keeping the given order inside a bucket. Two effects:
+// Mode 1, by degree: new ids list the vertices by ascending log2-degree
+// bucket (isolated vertices first), keeping the given order inside a bucket.
+// Two effects:
 //   * the sweep visits low-degree sources first, which shortens the scans
 //     (a low-degree source reaches a free neighbour early, and hubs are
 //     usually matched as neighbours before their own turn comes);
 //   * the high-degree vertices, whose states most scans read, get the
 //     highest ids, so their status words and hint bits share few cache lines
 //     and stay in L2.
-// The relabelled CSR (int64 offsets, neighbour lists in the given order with
-// ids mapped) and the map from new to given ids live in the workspace; the
-// sweep writes its output in the given ids. Temporary buffers of the sort are
-// allocated and freed here (create time only).
+// Lists of up to 64 entries are sorted by new id (low-degree neighbours
+// first).
+//
+// Mode 2, hot vertices last: isolated vertices first, then every vertex of
+// at most `hot` entries in the given order, then the others (the hot ones),
+// also in the given order; lists keep their given order. The sweep then
+// visits sources almost as given, but the states of the hot vertices, which
+// most scans of a skewed graph read, sit together at the top of the state
+// array: a few hundred thousand vertices in a few MB, which the L2 keeps,
+// where in the given ids each of them would hold a cache line of its own.
+//
+// The relabelled CSR (int64 offsets, neighbour lists with ids mapped) and the
+// map from new to given ids live in the workspace; the sweep writes its
+// output in the given ids. Temporary buffers of the sort are allocated and
+// freed here (create time only).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -29,11 +41,16 @@ __device__ __forceinline__ uint32_t bucket_of(int64_t d) {
   return d <= 0 ? 0u : 64u - (uint32_t)__clzll((unsigned long long)d);  // 1 + floor(log2 d)
 }
 
+// Sort keys: the log2-degree bucket (mode 1), or 0 isolated / 1 / 2 more than
+// `hot` entries (mode 2).
 template <typename OffT>
-__global__ void degree_keys_kernel(const OffT* __restrict__ off, int64_t n, uint32_t* __restrict__ keys) {
+__global__ void degree_keys_kernel(const OffT* __restrict__ off, int64_t n, int mode, int64_t hot,
+                                   uint32_t* __restrict__ keys) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride)
-    keys[v] = bucket_of((int64_t)off[v + 1] - (int64_t)off[v]);
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+    const int64_t d = (int64_t)off[v + 1] - (int64_t)off[v];
+    keys[v] = mode == 1 ? bucket_of(d) : (d <= 0 ? 0u : (d > hot ? 2u : 1u));
+  }
 }
 
 // inv[orig[v]] = v; rdeg[v] = degree of new vertex v; rdeg[n] = 0.
@@ -61,17 +78,18 @@ __global__ void count_isolated_kernel(const uint32_t* __restrict__ keys, int64_t
 }
 
 // Copies the lists. A wavefront takes 64 new vertices: each lane copies its
-// own vertex's list when it has at most 64 entries, sorted by new id (an
-// insertion sort in LDS, element k of lane l at k * 64 + l so that the lanes
-// use different banks); longer lists are then copied by the whole wavefront,
-// one after the other, lanes spread over it, in their given order. Ascending
-// new ids put a list's low-degree neighbours first, and those are the ones
-// still free when a low-degree source is swept: the sweep reads fewer ids.
+// own vertex's list when it has at most 64 entries, sorted by new id when
+// `sort_short` (an insertion sort in LDS, element k of lane l at k * 64 + l
+// so that the lanes use different banks); longer lists are then copied by the
+// whole wavefront, one after the other, lanes spread over it, in their given
+// order. Ascending new ids in the degree order put a list's low-degree
+// neighbours first, and those are the ones still free when a low-degree
+// source is swept: the sweep reads fewer ids.
 template <typename OffT>
 __global__ __launch_bounds__(256) void copy_lists_kernel(
     const OffT* __restrict__ off, const int32_t* __restrict__ nbr, const int32_t* __restrict__ orig,
     const int32_t* __restrict__ inv, const int64_t* __restrict__ roff, int32_t* __restrict__ rnbr,
-    int64_t n) {
+    int64_t n, int sort_short) {
   __shared__ int32_t sort_s[4][64 * 64];
   int32_t* srt = sort_s[threadIdx.x >> 6];
   const int lane = (int)(threadIdx.x & 63);
@@ -87,7 +105,9 @@ __global__ __launch_bounds__(256) void copy_lists_kernel(
       d = roff[v] - b;
     }
     const bool longl = e - b > 64;
-    if (!longl) {
+    if (!longl && !sort_short) {
+      for (int64_t k = b; k < e; ++k) rnbr[d + k] = inv[nbr[k]];
+    } else if (!longl) {
       const int len = (int)(e - b);
       for (int k = 0; k < len; ++k) {
         const int32_t key = inv[nbr[b + k]];
@@ -118,8 +138,11 @@ int blocks_for(int64_t n) {
 }
 
 template <typename OffT>
-hipError_t build_typed(const OffT* off, const int32_t* nbr, int64_t n, int64_t* roff,
-                       int32_t* rnbr, int32_t* orig, int64_t* n_isolated, hipStream_t s) {
+hipError_t build_typed(const OffT* off, const int32_t* nbr, int64_t n, int mode, int64_t hot,
+                       int64_t* roff, int32_t* rnbr, int32_t* orig, int64_t* n_isolated,
+                       hipStream_t s) {
+  // 7 key bits cover every bucket 0 .. 64 (mode 1); 2 bits the three groups
+  const int key_bits = mode == 1 ? 7 : 2;
   uint32_t *keys = nullptr, *keys_sorted = nullptr;
   int32_t* inv = nullptr;
   int64_t* rdeg = nullptr;
@@ -128,7 +151,8 @@ hipError_t build_typed(const OffT* off, const int32_t* nbr, int64_t n, int64_t* 
   size_t tmp_bytes = 0, sort_bytes = 0, scan_bytes = 0;
   hipError_t e = hipSuccess;
   auto ids = rocprim::counting_iterator<int32_t>(0);
-  e = rocprim::radix_sort_pairs(nullptr, sort_bytes, keys, keys_sorted, ids, orig, (size_t)n, 0, 7, s);
+  e = rocprim::radix_sort_pairs(nullptr, sort_bytes, keys, keys_sorted, ids, orig, (size_t)n, 0,
+                                key_bits, s);
   if (e == hipSuccess)
     e = rocprim::exclusive_scan(nullptr, scan_bytes, rdeg, roff, (int64_t)0, (size_t)(n + 1),
                                 rocprim::plus<int64_t>(), s);
@@ -147,12 +171,14 @@ hipError_t build_typed(const OffT* off, const int32_t* nbr, int64_t n, int64_t* 
                                           sizeof(unsigned long long), s);
   if (e == hipSuccess) e = hipMemsetAsync(iso, 0, sizeof(unsigned long long), s);
   if (e == hipSuccess) {
-    hipLaunchKernelGGL((degree_keys_kernel<OffT>), dim3(blocks_for(n)), dim3(256), 0, s, off, n, keys);
+    hipLaunchKernelGGL((degree_keys_kernel<OffT>), dim3(blocks_for(n)), dim3(256), 0, s, off, n,
+                       mode, hot, keys);
     e = hipGetLastError();
   }
-  // 7 key bits cover every bucket 0 .. 64; the sort is stable
+  // the sort is stable: the given order inside each key
   if (e == hipSuccess)
-    e = rocprim::radix_sort_pairs(tmp, sort_bytes, keys, keys_sorted, ids, orig, (size_t)n, 0, 7, s);
+    e = rocprim::radix_sort_pairs(tmp, sort_bytes, keys, keys_sorted, ids, orig, (size_t)n, 0,
+                                  key_bits, s);
   if (e == hipSuccess) {
     hipLaunchKernelGGL((invert_kernel<OffT>), dim3(blocks_for(n + 1)), dim3(256), 0, s, off, orig, n,
                        inv, rdeg);
@@ -167,7 +193,7 @@ hipError_t build_typed(const OffT* off, const int32_t* nbr, int64_t n, int64_t* 
   }
   if (e == hipSuccess) {
     hipLaunchKernelGGL((copy_lists_kernel<OffT>), dim3(blocks_for(n)), dim3(256), 0, s,
-                       off, nbr, orig, inv, roff, rnbr, n);
+                       off, nbr, orig, inv, roff, rnbr, n, mode == 1 ? 1 : 0);
     e = hipGetLastError();
   }
   unsigned long long h_iso = 0;
@@ -196,8 +222,13 @@ size_t relabel_temp_bytes(int64_t n) {
   int32_t* o = nullptr;
   int64_t* d = nullptr;
   auto ids = rocprim::counting_iterator<int32_t>(0);
-  hipError_t e = rocprim::radix_sort_pairs(nullptr, sort_bytes, k, k, ids, o, (size_t)n, 0, 7,
-                                           (hipStream_t)0);
+  hipError_t e = hipSuccess;
+  for (int bits : {7, 2}) {  // both modes' sorts
+    size_t b = 0;
+    if (e == hipSuccess)
+      e = rocprim::radix_sort_pairs(nullptr, b, k, k, ids, o, (size_t)n, 0, bits, (hipStream_t)0);
+    if (b > sort_bytes) sort_bytes = b;
+  }
   if (e == hipSuccess)
     e = rocprim::exclusive_scan(nullptr, scan_bytes, d, d, (int64_t)0, (size_t)(n + 1),
                                 rocprim::plus<int64_t>(), (hipStream_t)0);
@@ -215,7 +246,7 @@ size_t relabel_bytes(int64_t n, int64_t m) {
 }
 
 hipError_t build_relabel(const void* off, int off64, const int32_t* nbr, int64_t n, int64_t m,
-                         uint8_t* region, RelabelView* view, hipStream_t s) {
+                         int mode, int64_t hot, uint8_t* region, RelabelView* view, hipStream_t s) {
   view->off = reinterpret_cast<int64_t*>(region);
   view->orig = reinterpret_cast<int32_t*>(region + round_up(sizeof(int64_t) * (size_t)(n + 1), 256));
   view->nbr = reinterpret_cast<int32_t*>(reinterpret_cast<uint8_t*>(view->orig) +
@@ -224,10 +255,10 @@ hipError_t build_relabel(const void* off, int off64, const int32_t* nbr, int64_t
   (void)m;
   if (n == 0) return hipSuccess;
   if (off64)
-    return build_typed(static_cast<const int64_t*>(off), nbr, n, view->off, view->nbr, view->orig,
-                       &view->n_isolated, s);
-  return build_typed(static_cast<const int32_t*>(off), nbr, n, view->off, view->nbr, view->orig,
-                     &view->n_isolated, s);
+    return build_typed(static_cast<const int64_t*>(off), nbr, n, mode, hot, view->off, view->nbr,
+                       view->orig, &view->n_isolated, s);
+  return build_typed(static_cast<const int32_t*>(off), nbr, n, mode, hot, view->off, view->nbr,
+                     view->orig, &view->n_isolated, s);
 }
 
 }  // namespace mmi

@@ -42,7 +42,8 @@ def test_version_and_defaults():
     assert t.wg_size % 64 == 0 and t.wave_vertices % 64 == 0
     # the ctypes mirror has the C layout: the last fields read back as written
     assert t.whole_graph_vertices == 16384 and t.iter_cap == 0 and t.whole_graph_lds == 1
-    assert ctypes.sizeof(_lib.mm_tuning) == 88
+    assert t.hot_degree == 2048
+    assert ctypes.sizeof(_lib.mm_tuning) == 96
     from paper_2507_04420_amd import Tuning
     assert Tuning.default() == Tuning()  # the Python defaults mirror the library's
 
@@ -107,7 +108,8 @@ def test_create_bad_tuning():
     assert st == _lib.MM_ERR_INVALID_ARG
     assert b"wave_vertices" in lib.mm_last_error()
     for field, bad in (("protocol", 2), ("hint", 3), ("hint", -1), ("scan_width", 0), ("scan_width", 9),
-                       ("layout", 5), ("stream_loads", 2), ("whole_graph_vertices", -1), ("relabel", 2),
+                       ("layout", 5), ("stream_loads", 2), ("whole_graph_vertices", -1), ("relabel", 3),
+                       ("relabel", -1),
                        ("hub_degree", -1), ("whole_graph_lds", 2), ("wait_release", 2),
                        ("mesh_wave_vertices", 100),
                        ("iter_cap", -1)):
@@ -195,6 +197,11 @@ def test_workspace_bytes_graph():
     assert lib.mm_workspace_bytes_graph(1000, -1, ctypes.byref(t)) == 0
     vtx = (ctypes.c_int64 * 2)(0, 10)
     assert lib.mm_batch_workspace_bytes(1, vtx, ctypes.byref(t)) == 0
+    # the hot-vertices-last order needs the same copy, and a threshold
+    t.relabel = 2
+    assert lib.mm_workspace_bytes_graph(1000, 5000, ctypes.byref(t)) == big
+    t.hot_degree = 0
+    assert lib.mm_workspace_bytes_graph(1000, 5000, ctypes.byref(t)) == 0
 
 
 def _batch_bytes(lib, ns, **kw):

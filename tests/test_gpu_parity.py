@@ -89,6 +89,14 @@ TUNINGS = {
                                        upper_only=1, wait_release=1, whole_graph_vertices=0),
     "hub_wave_bit_hint_u2": mm.Tuning(hub_wave=1, hub_degree=4, hub_chunk=64, hint=1, layout=U2,
                                       protocol=TWO, whole_graph_vertices=0),
+    # relabelled with the vertices of more than hot_degree entries last
+    "relabel_hot_u32_cas": mm.Tuning(relabel=2, hot_degree=4),
+    "relabel_hot_upper_multi_wave": mm.Tuning(relabel=2, hot_degree=8, upper_only=1,
+                                              whole_graph_vertices=0, wave_vertices=64),
+    "relabel_hot_u8_two_bytehint": mm.Tuning(relabel=2, hot_degree=2, layout=U8, protocol=TWO,
+                                             hint=2, lazy_init=1),
+    "relabel_hot_hub_wave_upper": mm.Tuning(relabel=2, hot_degree=3, hub_wave=1, hub_degree=5,
+                                            hub_chunk=7, upper_only=1, whole_graph_vertices=0),
 }
 
 
@@ -427,14 +435,16 @@ def test_pair_list_small_buffer_reports_count():
 
 # ---------------------------------------------------------------- relabelled sweep
 
-def test_relabel_all_isolated_and_stats():
+@pytest.mark.parametrize("mode", [1, 2])
+def test_relabel_all_isolated_and_stats(mode):
     # every vertex isolated: the relabelled sweep has no source at all
     g = graphgen.from_edges(1000, np.zeros((0, 2)))
-    mate, st = gpu_match(g, mm.Tuning(relabel=1), stats=True)
+    mate, st = gpu_match(g, mm.Tuning(relabel=mode), stats=True)
     assert (mate == -1).all() and st["sources"] == 0
     # sources visited = vertices with entries
     g = graphgen.rmat(14, seed=6)
-    mate, st = gpu_match(g, mm.Tuning(relabel=1, whole_graph_vertices=0), stats=True)
+    mate, st = gpu_match(g, mm.Tuning(relabel=mode, hot_degree=40, whole_graph_vertices=0),
+                         stats=True)
     assert_parity(g, mate)
     assert st["sources"] == int((np.diff(g.off) > 0).sum())
     assert st["pairs"] == oracle.check(g, mate).size
@@ -456,7 +466,7 @@ def test_relabel_workspace_sizing():
 
 
 @pytest.mark.parametrize("name", ["default", "u8_cas_eager", "relabel_u32_cas", "relabel_u8_cas",
-                                  "u32_two_eager"])
+                                  "u32_two_eager", "relabel_hot_u32_cas"])
 @pytest.mark.parametrize("shift", [1, 2, 3])
 def test_unaligned_output(name, shift):
     # an output view at any 4-byte offset: fills and sweep write exactly its n entries
