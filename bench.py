@@ -388,6 +388,9 @@ VARIANTS = {
     "upper_wait": {"upper_only": 1, "wait_release": 1},
     "hub_wave": {"hub_wave": 1},
     "hub_wave_1024": {"hub_wave": 1, "hub_chunk": 1024},
+    "hub_group": {"hub_wave": 2},
+    "hub_group_1024": {"hub_wave": 2, "hub_chunk": 1024},
+    "hub_group_wg256": {"hub_wave": 2, "wg_size": 256},
     "hub_lane_64": {"hub_chunk": 64},
     "no_hub_tier": {"hub_degree": 0},
     "stream_loads": {"stream_loads": 1},

@@ -200,8 +200,12 @@ typedef struct {
                             its lanes: 64 ids per step read together, the first
                             candidate found by a ballot and reserved by one
                             lane, the source's state checked before every step;
-                            0: each piece by one lane, like any other source's
-                            list */
+                            2 (single graphs; batches take it as 1): the same,
+                            and the wavefronts of a workgroup, which take
+                            consecutive runs of pieces (mostly of the same long
+                            lists), share in LDS the sources they found matched,
+                            checked before every step; 0: each piece by one
+                            lane, like any other source's list */
   int32_t min_waves;     /* a graph alone (mm_run) or a batch whose blocked sources
                             are too few for this many wavefronts of wave_vertices
                             sources gets shorter blocks, so that about this many

@@ -50,7 +50,7 @@ class Tuning:
     mesh_wave_vertices: int = 0
     wait_release: int = 0
     upper_only: int = 0
-    hub_wave: int = 0
+    hub_wave: int = 1
     min_waves: int = 32
     hot_degree: int = 2048
     iter_cap: int = 0

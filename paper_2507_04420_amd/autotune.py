@@ -53,7 +53,7 @@ SPACE = {
     # together
     "upper_wait": [(0, 0), (0, 1), (1, 0), (1, 1)],
     "min_waves": [4, 8, 16, 32, 64, 2048],
-    "hub_wave": [0, 1],
+    "hub_wave": [0, 1, 2],
     "hub_chunk": [64, 256, 1024, 4096],
 }
 

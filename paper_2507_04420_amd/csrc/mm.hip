@@ -78,8 +78,8 @@ mm_status check_tuning(const mm_tuning& t) {
   if (t.min_waves < 0) return fail(MM_ERR_INVALID_ARG, "tuning.min_waves must be >= 0");
   if (t.upper_only != 0 && t.upper_only != 1)
     return fail(MM_ERR_INVALID_ARG, "tuning.upper_only must be 0 or 1");
-  if (t.hub_wave != 0 && t.hub_wave != 1)
-    return fail(MM_ERR_INVALID_ARG, "tuning.hub_wave must be 0 or 1");
+  if (t.hub_wave < 0 || t.hub_wave > 2)
+    return fail(MM_ERR_INVALID_ARG, "tuning.hub_wave must be 0, 1 or 2");
   if (t.mesh_wave_vertices < 0 || t.mesh_wave_vertices % 64)
     return fail(MM_ERR_INVALID_ARG, "tuning.mesh_wave_vertices must be 0 or a positive multiple of 64");
   return MM_OK;
@@ -218,6 +218,13 @@ __global__ __launch_bounds__(256) void sweep_kernel(SweepParams p, const OffT* _
                                                    int64_t n_chunks,
                                                    const unsigned long long* chunk_count, Layout L,
                                                    unsigned long long* stats) {
+  // the workgroup tier's slots (pieces.h), cleared before any wavefront of
+  // the workgroup reads them
+  __shared__ int32_t seen[4];
+  if (p.hub_wave == 2) {
+    if (threadIdx.x < 4) seen[threadIdx.x] = -1;
+    __syncthreads();
+  }
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   int64_t vb, nv;
   if (wave < main_waves) {
@@ -239,7 +246,10 @@ __global__ __launch_bounds__(256) void sweep_kernel(SweepParams p, const OffT* _
     p.hub_degree = 0;
     if (p.hub_wave) {
       Counters<STATS> cnt;
-      sweep_pieces_wave<Layout, HINT, STATS>(p, nbr, L, vb, nv, cnt);
+      if (p.hub_wave == 2)
+        sweep_pieces_wave<Layout, HINT, STATS>(p, nbr, L, vb, nv, cnt, seen, (int)(blockDim.x >> 6));
+      else
+        sweep_pieces_wave<Layout, HINT, STATS>(p, nbr, L, vb, nv, cnt);
       if (STATS) cnt.flush(stats);
       return;
     }
@@ -604,7 +614,10 @@ void mm_default_tuning(mm_tuning* t) {
   // a small graph alone keeps about 32 wavefronts in flight: fewer sources
   // racing at once, so repeated passes give matchings of nearly the same size
   t->upper_only = 0;
-  t->hub_wave = 0;
+  // long lists' pieces swept by whole wavefronts once their source is seen
+  // free: as fast as one lane a piece on R-MAT (0.3% faster in interleaved
+  // runs), and twice as fast where a long list is still live
+  t->hub_wave = 1;
   t->min_waves = 32;
   t->hot_degree = 2048;
   t->iter_cap = 0;

@@ -153,11 +153,33 @@ __device__ __forceinline__ int run_edge(const SweepParams& a, const Layout& L, i
 
 // Sweeps pieces p0 .. p0+np-1 (np <= 64) of the hub table a.chunks with this
 // wavefront.
+//
+// seen (LDS, or null): the workgroup tier (hub_wave = 2, single graphs). The
+// nseen wavefronts of a workgroup take consecutive runs of pieces, most of
+// them pieces of the same long lists, and each keeps in seen[its wavefront]
+// the last source it found matched. Every wavefront checks those slots as
+// well as the source's state before each step, so once one wavefront matches
+// a hub the others stop its pieces at their next step, without waiting for
+// the state word to reach them through a cache. A slot only ever holds a
+// matched vertex (matched is final), so a slot read late or overwritten
+// costs only a step.
 template <class Layout, bool HINT, bool STATS, class NbrP = const int32_t*>
 __device__ __forceinline__ void sweep_pieces_wave(const SweepParams& a, NbrP __restrict__ nbr,
                                                   const Layout& L, int64_t p0, int64_t np,
-                                                  Counters<STATS>& cnt) {
+                                                  Counters<STATS>& cnt, int32_t* seen = nullptr,
+                                                  int nseen = 0) {
   const int lane = (int)(threadIdx.x & 63);
+  auto seen_matched = [&](int32_t v) -> bool {
+    bool hit = false;
+    if (seen)
+      for (int k = 0; k < nseen; ++k)
+        hit |= __hip_atomic_load(seen + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) == v;
+    return hit;
+  };
+  auto mark = [&](int32_t v) {
+    if (seen && lane == 0)
+      __hip_atomic_store(seen + (threadIdx.x >> 6), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  };
   const bool upper = a.upper_only != 0;
   const bool nt = a.stream_loads != 0;
   auto filter_word = [&](int64_t y) -> uint32_t {
@@ -173,7 +195,7 @@ __device__ __forceinline__ void sweep_pieces_wave(const SweepParams& a, NbrP __r
   bool live = false;
   if (lane < np) {
     mine = a.chunks[p0 + lane];
-    live = !filter_matched(filter_word(mine.x), mine.x);
+    live = !filter_matched(filter_word(mine.x), mine.x) && !seen_matched(mine.x);
   }
   uint64_t todo = __ballot(live);
   // loop budget: one step per 64 entries of every piece and the polls of its
@@ -203,7 +225,10 @@ __device__ __forceinline__ void sweep_pieces_wave(const SweepParams& a, NbrP __r
       const uint32_t yw = ok ? filter_word(y) : 0u;
       const uint32_t xw = bcast(filter_word(x));
       if (STATS && lane == 0) cnt.add(S_TOUCHED, (uint32_t)(ce - i < 64 ? ce - i : 64));
-      if (filter_matched(xw, x)) break;  // the source is matched: the rest is skipped
+      if (filter_matched(xw, x) || seen_matched(x)) {  // the source is matched: the rest is skipped
+        mark(x);
+        break;
+      }
       uint64_t cand = __ballot(ok && !filter_matched(yw, y));
       while (cand) {
         const int l = __builtin_ctzll(cand);
@@ -217,7 +242,8 @@ __device__ __forceinline__ void sweep_pieces_wave(const SweepParams& a, NbrP __r
           if (lane == 0) atomicOr(a.err, 1u);
           return;
         }
-        if (r != E_Y_DEAD) {
+        if (r != E_Y_DEAD) {  // x is matched, by this edge or elsewhere
+          mark(x);
           done = true;
           break;
         }

@@ -83,7 +83,7 @@ struct SweepParams {
   int32_t stream_loads;    // 1: offsets and ids through non-temporal loads
   int32_t wait_release;    // 1: release u while waiting for a reserved v
   int32_t upper_only;      // 1 (symmetric input): examine only neighbours above the source
-  int32_t hub_wave;        // 1: hub pieces swept by a wavefront each (pieces.h), else a lane each
+  int32_t hub_wave;        // 1, 2: hub pieces swept by a wavefront each (pieces.h), else a lane each
   int64_t iter_cap;        // 0: per-block default budget
   uint32_t* err;           // bit 0: loop-trip budget exceeded
   // Hub tier. Main pass: sources with more than hub_degree entries are left

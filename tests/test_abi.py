@@ -111,7 +111,8 @@ def test_create_bad_tuning():
                        ("layout", 5), ("stream_loads", 2), ("whole_graph_vertices", -1), ("relabel", 3),
                        ("relabel", -1),
                        ("hub_degree", -1), ("whole_graph_lds", 2), ("wait_release", 2),
-                       ("mesh_wave_vertices", 100),
+                       ("mesh_wave_vertices", 100), ("hub_wave", 3), ("hub_wave", -1),
+                       ("upper_only", 2), ("min_waves", -1),
                        ("iter_cap", -1)):
         lib.mm_default_tuning(ctypes.byref(t))
         setattr(t, field, bad)

@@ -31,11 +31,14 @@ TUNINGS = {
     "u32_mesh128": mm.Tuning(whole_graph_vertices=0, mesh_wave_vertices=128),
     "u32_upper_only": mm.Tuning(upper_only=1, whole_graph_vertices=0, hint=2),
     "u32_hub_wave": mm.Tuning(hub_wave=1, hub_degree=6, hub_chunk=65, whole_graph_vertices=0),
+    # the workgroup tier is taken as the wavefront tier in batches
+    "u32_hub_group": mm.Tuning(hub_wave=2, hub_degree=5, hub_chunk=7, whole_graph_vertices=0,
+                               wg_size=256),
     "u2_two_hub_wave_upper": mm.Tuning(hub_wave=1, hub_degree=3, hub_chunk=5, layout=_lib.MM_LAYOUT_U2,
                                        protocol=_lib.MM_PROTOCOL_TWO_PHASE, upper_only=1,
                                        whole_graph_vertices=0),
     "u8_upper_only_lazy_hubs": mm.Tuning(upper_only=1, layout=_lib.MM_LAYOUT_U8, lazy_init=1,
-                                         hub_degree=6, hub_chunk=3),
+                                         hub_degree=6, hub_chunk=3, hub_wave=0),
     "u8_mesh64_hubs": mm.Tuning(layout=_lib.MM_LAYOUT_U8, whole_graph_vertices=0, mesh_wave_vertices=64,
                                 hub_degree=8, hub_chunk=4, lazy_init=1),
     "u32_mesh128_wait_release": mm.Tuning(whole_graph_vertices=0, mesh_wave_vertices=128,
@@ -266,7 +269,7 @@ def test_batch_hub_pieces(tuning):
 def test_batch_hub_pieces_are_fast():
     import time
     parts = [hub_trap(100_000)]
-    for name, t in (("tier", mm.Tuning(whole_graph_vertices=0)),
+    for name, t in (("tier", mm.Tuning(whole_graph_vertices=0, hub_wave=0)),
                     ("wave_tier", mm.Tuning(whole_graph_vertices=0, hub_wave=1)),
                     ("no_tier", mm.Tuning(whole_graph_vertices=0, hub_degree=0))):
         b = mm.Batch.from_list(list_of(parts), symmetric=True, tuning=t)

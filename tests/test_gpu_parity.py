@@ -57,8 +57,8 @@ TUNINGS = {
     "relabel_u32_bytehint": mm.Tuning(relabel=1, hint=2),
     "u8_two_bytehint": mm.Tuning(layout=U8, protocol=TWO, hint=2, lazy_init=1),
     "u32_cas_bytehint_w2": mm.Tuning(hint=2, scan_width=2, wave_vertices=128),
-    "hub_every_entry": mm.Tuning(hub_degree=1, hub_chunk=1),
-    "hub_small_u8_lazy": mm.Tuning(layout=U8, lazy_init=1, hub_degree=8, hub_chunk=3),
+    "hub_every_entry": mm.Tuning(hub_degree=1, hub_chunk=1, hub_wave=0),
+    "hub_small_u8_lazy": mm.Tuning(layout=U8, lazy_init=1, hub_degree=8, hub_chunk=3, hub_wave=0),
     "hub_relabel_two": mm.Tuning(relabel=1, protocol=TWO, hub_degree=5, hub_chunk=2, hint=2),
     "no_hub_tier": mm.Tuning(hub_degree=0),
     # small graphs are swept whole with their states in LDS by default; these
@@ -89,6 +89,13 @@ TUNINGS = {
                                        upper_only=1, wait_release=1, whole_graph_vertices=0),
     "hub_wave_bit_hint_u2": mm.Tuning(hub_wave=1, hub_degree=4, hub_chunk=64, hint=1, layout=U2,
                                       protocol=TWO, whole_graph_vertices=0),
+    # the workgroup tier: wavefronts of a workgroup share the sources they found matched
+    "hub_group_every_list": mm.Tuning(hub_wave=2, hub_degree=1, hub_chunk=3, whole_graph_vertices=0,
+                                      wg_size=256),
+    "hub_group_u8_upper_two_waves": mm.Tuning(hub_wave=2, hub_degree=4, hub_chunk=9, layout=U8,
+                                              upper_only=1, wg_size=128, whole_graph_vertices=0),
+    "hub_group_two_hint_relabel": mm.Tuning(hub_wave=2, hub_degree=6, hub_chunk=2, protocol=TWO,
+                                            hint=2, relabel=1, wg_size=192),
     # relabelled with the vertices of more than hot_degree entries last
     "relabel_hot_u32_cas": mm.Tuning(relabel=2, hot_degree=4),
     "relabel_hot_upper_multi_wave": mm.Tuning(relabel=2, hot_degree=8, upper_only=1,
@@ -506,8 +513,8 @@ def test_hub_tier_spreads_a_long_dead_list():
     g = hub_trap(1_000_000)
     off, nbr = to_dev(g)
     times = {}
-    for name, t in (("tier", mm.Tuning()), ("wave_tier", mm.Tuning(hub_wave=1)),
-                    ("no_tier", mm.Tuning(hub_degree=0))):
+    for name, t in (("tier", mm.Tuning(hub_wave=0)), ("wave_tier", mm.Tuning(hub_wave=1)),
+                    ("group_tier", mm.Tuning(hub_wave=2)), ("no_tier", mm.Tuning(hub_degree=0))):
         h = mm.Graph(off, nbr, symmetric=True, tuning=t, timing=True)
         out = h.run()
         h.sync()
@@ -520,3 +527,4 @@ def test_hub_tier_spreads_a_long_dead_list():
     print("hub trap sweep ms:", times)
     assert times["tier"] * 5 < times["no_tier"]
     assert times["wave_tier"] * 5 < times["no_tier"]
+    assert times["group_tier"] * 5 < times["no_tier"]
