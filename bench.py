@@ -326,6 +326,7 @@ def bench_single(args, name, tun, dev, *, natural=False, conflicts=False, ceilin
         "config": dict(config, n=n, m=m, tuning=tun.as_dict()),
         "create_ms": round(create_ms, 2),
         "relabel_copy_bytes": (8 * (n + 1) + 4 * n + 4 * m + 4 * n) if tun.relabel else 0,
+        "ordered_copy_bytes": 4 * m if tun.order_lists else 0,
         "ms_per_step": round(ms_per_step, 5),
         "us_per_step": round(ms_per_step * 1e3, 2),
         "sweep_ms": round(sweep["mean_ms"], 5),
@@ -361,6 +362,7 @@ VARIANTS = {
     "tuned": {},
     "natural_order": {"relabel": 0},
     "relabelled": {"relabel": 1},
+    "order_lists": {"order_lists": 1},
     "relabel_hot": {"relabel": 2},
     "relabel_hot_512": {"relabel": 2, "hot_degree": 512},
     "relabel_hot_1024": {"relabel": 2, "hot_degree": 1024},

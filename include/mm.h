@@ -213,6 +213,16 @@ typedef struct {
                             0 keeps wave_vertices whatever the size */
   int32_t hot_degree;    /* relabel = 2: vertices with more entries than this go to
                             the top of the new ids; >= 1 */
+  int32_t order_lists;   /* 1 (single graphs only; not with relabel): mm_create
+                            copies the neighbour ids into the workspace with every
+                            list of at most 256 entries reordered by ascending
+                            log2 degree of the neighbour (stable), and the sweep
+                            reads the copy: low-degree neighbours, which are more
+                            often still free, are examined first, so scans stop
+                            sooner. Ids, offsets, states and output are the
+                            given ones. Workspace from mm_workspace_bytes_graph
+                            (4m bytes more); create allocates n bytes of
+                            temporary device memory and waits for the copy */
   int64_t iter_cap;      /* loop-trip budget per wavefront; 0 = default of
                             65536 + 8 x (neighbour entries of its block);
                             exceeding it raises MM_ERR_NO_PROGRESS */

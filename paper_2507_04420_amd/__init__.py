@@ -53,6 +53,7 @@ class Tuning:
     hub_wave: int = 1
     min_waves: int = 32
     hot_degree: int = 2048
+    order_lists: int = 0
     iter_cap: int = 0
 
     @classmethod

@@ -57,6 +57,7 @@ class mm_tuning(ctypes.Structure):
         ("hub_wave", ctypes.c_int32),
         ("min_waves", ctypes.c_int32),
         ("hot_degree", ctypes.c_int32),
+        ("order_lists", ctypes.c_int32),
         ("iter_cap", ctypes.c_int64),
     ]
 

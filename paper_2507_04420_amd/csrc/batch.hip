@@ -431,6 +431,8 @@ mm_status common_args(void* workspace, uint32_t flags, const mm_tuning* tuning, 
   const mm_status st = mmi::check_tuning(*t);
   if (st != MM_OK) return st;
   if (t->relabel) return fail(MM_ERR_UNSUPPORTED, "tuning.relabel applies to single graphs only");
+  if (t->order_lists)
+    return fail(MM_ERR_UNSUPPORTED, "tuning.order_lists applies to single graphs only");
   return MM_OK;
 }
 
@@ -683,7 +685,7 @@ size_t mm_batch_workspace_bytes(int32_t num_graphs, const int64_t* vtx_off, cons
   if (num_graphs < 0 || !vtx_off) return 0;
   mm_tuning t;
   if (tp) t = *tp; else mm_default_tuning(&t);
-  if (mmi::check_tuning(t) != MM_OK || t.relabel) return 0;
+  if (mmi::check_tuning(t) != MM_OK || t.relabel || t.order_lists) return 0;
   BatchLayout L;
   if (!plan_layout(num_graphs, vtx_off, t, &L)) return 0;
   return L.total;
@@ -694,7 +696,7 @@ size_t mm_batch_create_device_bytes(int32_t num_graphs, const int64_t* vtx_off, 
   if (num_graphs < 0 || !vtx_off || M < 0) return 0;
   mm_tuning t;
   if (tp) t = *tp; else mm_default_tuning(&t);
-  if (mmi::check_tuning(t) != MM_OK || t.relabel) return 0;
+  if (mmi::check_tuning(t) != MM_OK || t.relabel || t.order_lists) return 0;
   BatchLayout L;
   if (!plan_layout(num_graphs, vtx_off, t, &L)) return 0;
   bool blocked = false;  // a graph not swept whole: the only kind with pieces

@@ -67,6 +67,11 @@ mm_status check_tuning(const mm_tuning& t) {
     return fail(MM_ERR_INVALID_ARG, "tuning.relabel must be 0, 1 or 2");
   if (t.relabel == 2 && t.hot_degree < 1)
     return fail(MM_ERR_INVALID_ARG, "tuning.hot_degree must be >= 1 with relabel = 2");
+  if (t.order_lists != 0 && t.order_lists != 1)
+    return fail(MM_ERR_INVALID_ARG, "tuning.order_lists must be 0 or 1");
+  if (t.order_lists && t.relabel)
+    return fail(MM_ERR_INVALID_ARG, "tuning.order_lists does not apply with relabel (the "
+                "relabelled copy orders its short lists itself)");
   if (t.hub_degree < 0) return fail(MM_ERR_INVALID_ARG, "tuning.hub_degree must be >= 0");
   if (t.hub_degree > 0 && t.hub_chunk < 1)
     return fail(MM_ERR_INVALID_ARG, "tuning.hub_chunk must be >= 1 when hub_degree > 0");
@@ -620,6 +625,7 @@ void mm_default_tuning(mm_tuning* t) {
   t->hub_wave = 1;
   t->min_waves = 32;
   t->hot_degree = 2048;
+  t->order_lists = 0;
   t->iter_cap = 0;
 }
 
@@ -629,13 +635,14 @@ size_t mm_workspace_bytes_graph(int64_t n, int64_t m, const mm_tuning* tp) {
   if (n < 0 || m < 0 || check_tuning(t) != MM_OK || n > mmi::max_vertices(t)) return 0;
   size_t b = kCtrlBytes + mmi::state_bytes(n, t) + mmi::hint_bytes(n, t);
   if (t.relabel) b += mmi::round_up(sizeof(int32_t) * (size_t)n, 256) + mmi::relabel_bytes(n, m);
+  if (t.order_lists) b += mmi::round_up(sizeof(int32_t) * (size_t)m, 256);
   return b;
 }
 
 size_t mm_workspace_bytes(int64_t n, const mm_tuning* tp) {
   mm_tuning t;
   if (tp) t = *tp; else mm_default_tuning(&t);
-  if (t.relabel) return 0;  // the relabelled copy depends on m
+  if (t.relabel || t.order_lists) return 0;  // the copy depends on m
   return mm_workspace_bytes_graph(n, 0, &t);
 }
 
@@ -651,6 +658,8 @@ size_t mm_create_device_bytes(int64_t n, int64_t m, const mm_tuning* tp) {
   }
   // the relabelling's temporaries (freed before create returns)
   if (t.relabel) b += mmi::relabel_temp_bytes(n);
+  // the list reordering's degree buckets (freed before create returns)
+  if (t.order_lists) b += mmi::order_temp_bytes(n);
   return b;
 }
 
@@ -723,6 +732,14 @@ mm_status mm_create(const void* offsets, mm_offset_type off_type, const int32_t*
                                       t.hot_degree, region, &rl, s);
     if (e != hipSuccess) return fail(MM_ERR_HIP, "relabelling failed: %s", hipGetErrorString(e));
   }
+  const int32_t* sweep_nbr = neighbors;
+  if (t.order_lists && m > 0) {
+    int32_t* copy = reinterpret_cast<int32_t*>(ws + kCtrlBytes + mmi::state_bytes(n, t) +
+                                               mmi::hint_bytes(n, t));
+    hipError_t e = mmi::build_ordered_lists(offsets, off_type == MM_OFF_I64, neighbors, n, copy, s);
+    if (e != hipSuccess) return fail(MM_ERR_HIP, "ordering the lists failed: %s", hipGetErrorString(e));
+    sweep_nbr = copy;
+  }
   mm_graph* g = new (std::nothrow) mm_graph();
   if (!g) return fail(MM_ERR_OUT_OF_MEMORY, "host allocation of the handle failed");
   g->relabel = t.relabel != 0;
@@ -730,7 +747,7 @@ mm_status mm_create(const void* offsets, mm_offset_type off_type, const int32_t*
   g->rl_state = rl_state;
   g->off = offsets;
   g->off64 = off_type == MM_OFF_I64;
-  g->nbr = neighbors;
+  g->nbr = sweep_nbr;  // the reordered copy with order_lists
   g->n = n;
   g->m = m;
   g->ws = ws;
@@ -829,6 +846,8 @@ mm_status mm_run_static(const void* offsets, mm_offset_type off_type, const int3
                 "takes at most 2^31-2 vertices", (long long)n);
   if (t.relabel)
     return fail(MM_ERR_UNSUPPORTED, "mm_run_static: tuning.relabel needs a workspace (mm_create)");
+  if (t.order_lists)
+    return fail(MM_ERR_UNSUPPORTED, "mm_run_static: tuning.order_lists needs a workspace (mm_create)");
   // what the pass needs of the scratch, as mm_create's workspace would hold it
   const size_t base = kCtrlBytes + mmi::state_bytes(n, t) + mmi::hint_bytes(n, t);
   const int64_t pieces =

@@ -112,7 +112,7 @@ def test_create_bad_tuning():
                        ("relabel", -1),
                        ("hub_degree", -1), ("whole_graph_lds", 2), ("wait_release", 2),
                        ("mesh_wave_vertices", 100), ("hub_wave", 3), ("hub_wave", -1),
-                       ("upper_only", 2), ("min_waves", -1),
+                       ("upper_only", 2), ("min_waves", -1), ("order_lists", 2),
                        ("iter_cap", -1)):
         lib.mm_default_tuning(ctypes.byref(t))
         setattr(t, field, bad)
@@ -203,6 +203,15 @@ def test_workspace_bytes_graph():
     assert lib.mm_workspace_bytes_graph(1000, 5000, ctypes.byref(t)) == big
     t.hot_degree = 0
     assert lib.mm_workspace_bytes_graph(1000, 5000, ctypes.byref(t)) == 0
+    # reordered lists: a copy of the ids only, and not with a relabelled copy
+    t.hot_degree = 2048
+    t.order_lists = 1
+    assert lib.mm_workspace_bytes_graph(1000, 5000, ctypes.byref(t)) == 0
+    t.relabel = 0
+    assert lib.mm_workspace_bytes(1000, ctypes.byref(t)) == 0
+    assert lib.mm_workspace_bytes_graph(1000, 5000, ctypes.byref(t)) == base + 20224  # 4m to 256 B
+    assert lib.mm_create_device_bytes(1000, 5000, ctypes.byref(t)) >= 1000
+    assert lib.mm_batch_workspace_bytes(1, vtx, ctypes.byref(t)) == 0
 
 
 def _batch_bytes(lib, ns, **kw):

@@ -96,6 +96,12 @@ TUNINGS = {
                                               upper_only=1, wg_size=128, whole_graph_vertices=0),
     "hub_group_two_hint_relabel": mm.Tuning(hub_wave=2, hub_degree=6, hub_chunk=2, protocol=TWO,
                                             hint=2, relabel=1, wg_size=192),
+    # short lists reordered by the degree of the neighbour
+    "order_lists": mm.Tuning(order_lists=1),
+    "order_lists_upper_multi_wave_u8": mm.Tuning(order_lists=1, upper_only=1, layout=U8,
+                                                 whole_graph_vertices=0, wave_vertices=64),
+    "order_lists_two_hubs_hint": mm.Tuning(order_lists=1, protocol=TWO, hint=2, hub_degree=5,
+                                           hub_chunk=3, whole_graph_vertices=0),
     # relabelled with the vertices of more than hot_degree entries last
     "relabel_hot_u32_cas": mm.Tuning(relabel=2, hot_degree=4),
     "relabel_hot_upper_multi_wave": mm.Tuning(relabel=2, hot_degree=8, upper_only=1,
