@@ -112,21 +112,27 @@ def _value(t: Tuning, dim: str):
 SPREAD_LIMIT = 0.0008
 
 
+# Choices that build a copy of the graph at create time: they pay off only for
+# a handle that runs many passes, not for a serving request, which creates its
+# handle and runs one.
+COPIES = {"relabel": 0, "order_lists": 0}
+
+
 class SingleTarget:
     """One resident graph; objective = GEdges/s of a whole pass. With
-    relabel=False the tuning keeps the given order (relabelling pays off only
-    for a handle that runs many passes; a serving request runs one). With
+    copies=False the tuning keeps the given graph (no relabelled or reordered
+    copy, see COPIES). With
     spread_reps > 0 every candidate also runs that many checked passes, and
     one whose matching sizes vary by more than SPREAD_LIMIT (standard
     deviation over mean) is rejected."""
 
     unit = "GEdges/s"
 
-    def __init__(self, csr, reps: int = 5, relabel: bool = True, spread_reps: int = 0):
+    def __init__(self, csr, reps: int = 5, copies: bool = True, spread_reps: int = 0):
         # single graphs here are large: no whole-graph sweeps
         self.dims = [d for d in SPACE if d not in ("whole_graph_vertices", "mesh_wave_vertices") and
-                     (relabel or d != "relabel")]
-        self.fixed = {} if relabel else {"relabel": 0}  # held for the whole search
+                     (copies or (d not in COPIES and d != "hot_degree"))]
+        self.fixed = {} if copies else dict(COPIES)  # held for the whole search
         import torch
         self.off = torch.from_numpy(csr.off).cuda()
         self.nbr = torch.from_numpy(csr.nbr).cuda()
@@ -179,8 +185,8 @@ class MultiTarget:
 
     unit = "GEdges/s"
 
-    def __init__(self, csrs, reps: int = 5, relabel: bool = False, spread_reps: int = 0):
-        self.parts = [SingleTarget(c, reps=reps, relabel=relabel, spread_reps=spread_reps)
+    def __init__(self, csrs, reps: int = 5, copies: bool = False, spread_reps: int = 0):
+        self.parts = [SingleTarget(c, reps=reps, copies=copies, spread_reps=spread_reps)
                       for c in csrs]
         self.dims = self.parts[0].dims
         self.fixed = self.parts[0].fixed
@@ -201,9 +207,9 @@ class BatchTarget:
     """A many-graph batch; objective = graphs/s of a captured pass."""
 
     unit = "graphs/s"
-    # relabelling is for single graphs; whole-graph items trade batch throughput
+    # the copies are for single graphs; whole-graph items trade batch throughput
     # for results independent of the rest of the batch (kept by the serving loop)
-    dims = [d for d in SPACE if d != "relabel"]
+    dims = [d for d in SPACE if d not in COPIES and d != "hot_degree"]
 
     def __init__(self, mix, reps: int = 5):
         import torch

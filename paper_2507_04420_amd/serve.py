@@ -55,14 +55,16 @@ class ResidentGraph:
 
 def solo_tuning(off_host):
     """The tuning a large job runs alone with: the stored entry of its graph
-    class (autotune.classify), without relabelling. A request creates its own
-    handle and runs one pass, and relabelling pays off only for a handle that
-    runs many. The classes a request can fall in below 2^25 vertices are
-    tuned under the autotuner's spread limit, so that a job's result alone and
-    in the mix stay within the serving tolerance."""
+    class (autotune.classify), without a relabelled or reordered copy of the
+    graph. A request creates its own handle and runs one pass, and a copy
+    built at create time pays off only for a handle that runs many. The
+    classes a request can fall in below 2^25 vertices are tuned under the
+    autotuner's spread limit (and without copies), so that a job's result
+    alone and in the mix stay within the serving tolerance."""
     from . import autotune
     t = autotune.tuned(autotune.classify(np.asarray(off_host)))
-    t.relabel = 0
+    for field, value in autotune.COPIES.items():
+        setattr(t, field, value)
     return t
 
 

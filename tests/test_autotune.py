@@ -139,6 +139,19 @@ def test_search_holds_fixed_fields():
     assert r["tuning"]["relabel"] == 0
 
 
+def test_serving_classes_search_without_copies():
+    # the classes a serving request can fall in are searched with the graph
+    # as given: no relabelled or reordered copy, neither as a start nor as a
+    # candidate
+    class Target(FakeTarget):
+        fixed = dict(autotune.COPIES)
+        dims = ["wave_vertices", "scan_width"]
+    r = autotune.search(Target(), start=Tuning(relabel=1, order_lists=1), passes=1,
+                        log=lambda s: None)
+    assert r["tuning"]["relabel"] == 0 and r["tuning"]["order_lists"] == 0
+    assert set(autotune.COPIES) == {"relabel", "order_lists"}
+
+
 def test_multi_target_objective():
     class Part:
         def __init__(self, m, rate):

@@ -174,6 +174,30 @@ def test_footprint_covers_a_relabelled_copy():
     assert lib.mm_workspace_bytes(n, ctypes.byref(ct)) == 0
 
 
+def test_footprint_covers_a_reordered_copy():
+    # a request tuned with reordered lists holds a copy of the ids, and the
+    # create call allocates the neighbours' degree buckets
+    import ctypes
+    from paper_2507_04420_amd import Tuning
+    from paper_2507_04420_amd.serve import request_footprint
+    lib = _lib_or_skip()
+    n, m = 100_000, 1_600_000
+    t = Tuning(order_lists=1)
+    fp = request_footprint(lib, n, m, t, "solo")
+    base = lib.mm_workspace_bytes_graph(n, m, ctypes.byref(Tuning().to_c()))
+    assert fp >= base + 4 * m + n + 4 * n
+
+
+def test_solo_requests_build_no_copy(monkeypatch):
+    # a serving request creates its handle and runs one pass: whatever its
+    # class's stored entry says, it runs without a relabelled or reordered copy
+    from paper_2507_04420_amd import Tuning, autotune, serve
+    monkeypatch.setattr(autotune, "tuned", lambda cls, key=None: Tuning(relabel=1, order_lists=1))
+    off = np.arange(0, 2 * 400_001, 2, dtype=np.int64)  # 400000 vertices of degree 2
+    t = serve.solo_tuning(off)
+    assert t.relabel == 0 and t.order_lists == 0
+
+
 def test_footprint_covers_the_hub_table():
     # every list longer than hub_degree gives ceil(d / hub_chunk) pieces of
     # 24 bytes each, kept by the handle; the bound covers any degree sequence

@@ -53,22 +53,25 @@ def run_handle(csr, tuning=None, passes=5):
     return outs
 
 
-def compare(csr, a, runs, exact):
-    """a: the static pass's output; runs: mm_run's. Both checker-clean; equal
-    where the result cannot depend on the schedule; otherwise the static
-    pass's size lies within the spread of mm_run's sizes widened by the
-    alone-vs-mix tolerance (results vary from pass to pass, Section V-C, so
-    one pass against one pass would test the schedule, not the entry point)."""
-    ca = oracle.check(csr, a)
+def compare(csr, statics, runs, exact):
+    """statics: outputs of successive static passes; runs: mm_run's. All
+    checker-clean; equal where the result cannot depend on the schedule.
+    Otherwise the size varies from pass to pass (Section V-C), in both entry
+    points, so the two are compared as samples: their mean sizes differ by at
+    most the alone-vs-mix tolerance max(2, 1% of SGMM's size). One pass
+    against a few would test the tail of the schedule's spread, not the entry
+    point (on a 3000-vertex ER graph single passes of either range over 2%)."""
+    cas = [oracle.check(csr, a) for a in statics]
     cbs = [oracle.check(csr, b) for b in runs]
-    assert ca.ok and all(cb.ok for cb in cbs), (csr.name, ca, cbs)
+    assert all(c.ok for c in cas + cbs), (csr.name, cas, cbs)
     if exact:
-        for b in runs:
-            np.testing.assert_array_equal(a, b)
+        for a in statics:
+            for b in runs:
+                np.testing.assert_array_equal(a, b)
     else:
         bound = max(2, 0.01 * oracle.sgmm(csr).pairs)
-        sizes = [cb.size for cb in cbs]
-        assert min(sizes) - bound <= ca.size <= max(sizes) + bound, (csr.name, ca.size, sizes, bound)
+        sa, sb = [c.size for c in cas], [c.size for c in cbs]
+        assert abs(np.mean(sa) - np.mean(sb)) <= bound, (csr.name, sa, sb, bound)
 
 
 HUBS = mm.Tuning(hub_degree=256, hub_chunk=64, whole_graph_vertices=0)
@@ -88,13 +91,18 @@ CASES = [
 
 @pytest.mark.parametrize("case", range(len(CASES)))
 def test_static_equals_mm_run_on_two_calls(case):
+    # the static calls of the larger graph, then those of the smaller one,
+    # on the same scratch
     big, small, tuning, exact = CASES[case]
     for csr in (big(), small()):
-        a, status = run_static(csr, tuning)
-        assert status == 0
+        statics = []
+        for _ in range(5):
+            a, status = run_static(csr, tuning)
+            assert status == 0
+            statics.append(a)
         b = run_handle(csr, tuning)
         whole = csr.n <= (tuning or mm.Tuning()).whole_graph_vertices
-        compare(csr, a, b, exact or whole)
+        compare(csr, statics, b, exact or whole)
 
 
 def test_static_unique_result_and_int32_offsets():
