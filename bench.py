@@ -16,8 +16,9 @@ roofline: the sweep kernel's algorithmic bytes per launch (per source its
 cpu_baseline: the oracle's single-thread SGMM, pinned to one host core, on
           the same graph (it also gives T_seq).
 legs: every single-graph configuration (ER n=65536 with int32 offsets,
-      R-MAT-24, R-MAT-27, the 16384^2 grid) with create time, the natural-order
-      sweep beside a relabelled one, B_alg, frac, T_gpu/m and its SGMM
+      R-MAT-24, R-MAT-27, the 16384^2 grid) with create time, the sweep of the
+      graph as given beside one on a create-time copy (relabelled or with
+      reordered lists), B_alg, frac, T_gpu/m and its SGMM
       baseline; batch: the 4096-graph mixture in one captured persistent
       launch against one launch per graph, with its algorithmic bytes from
       every member's T_seq; serve: Poisson request streams over resident
@@ -45,7 +46,7 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_kernel_traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2507_04420_amd", "csrc", f)
                   for f in ("protocol.h", "sweep.h", "pieces.h", "internal.h", "mm.hip", "relabel.hip",
-                            "hubs.hip")]
+                            "hubs.hip", "order.hip")]
 VIOLATION_KEYS = ("out_of_range", "self_mate", "asymmetric", "not_edge", "uncovered")
 LEGS = ("headline", "er65536", "rmat24", "grid16384", "batch", "serve")
 
@@ -247,8 +248,9 @@ def timed_passes(g, out, steps, warmup):
 def bench_single(args, name, tun, dev, *, natural=False, conflicts=False, ceilings=None):
     """One single-graph configuration: the oracle baseline (T_seq), the
     handle's create time, `steps` timed passes, the device check, an
-    instrumented pass (T_gpu, atomics, conflicts), and, for a relabelled
-    tuning, the same passes in the given order on a second handle."""
+    instrumented pass (T_gpu, atomics, conflicts), and, for a tuning that
+    builds a copy of the graph (relabelled or with reordered lists), the same
+    passes on the graph as given on a second handle."""
     import torch
     import paper_2507_04420_amd as mm
 
@@ -298,8 +300,10 @@ def bench_single(args, name, tun, dev, *, natural=False, conflicts=False, ceilin
             log("conflicts (Table II): %s" % conflict_row)
 
     natural_leg = None
-    if natural and tun.relabel:
-        tn = mm.Tuning(**dict(tun.as_dict(), relabel=0))
+    change = {k: v for k, v in COPIES.items() if getattr(tun, k) != v}
+    if natural and change:
+        # the same passes on the graph as given: no relabelled or reordered copy
+        tn = mm.Tuning(**dict(tun.as_dict(), **change))
         tc = time.perf_counter()
         gn = mm.Graph(off, nbr, symmetric=True, timing=True, tuning=tn)
         torch.cuda.synchronize()
@@ -307,14 +311,14 @@ def bench_single(args, name, tun, dev, *, natural=False, conflicts=False, ceilin
         ms_n, sweep_n = timed_passes(gn, out, args.steps, args.warmup)
         chk_n = gn.check(out)
         gn.close()
-        natural_leg = {"tuning_change": {"relabel": 0}, "create_ms": round(create_n, 2),
+        natural_leg = {"tuning_change": change, "create_ms": round(create_n, 2),
                        "ms_per_step": round(ms_n, 5), "sweep_ms": round(sweep_n["mean_ms"], 5),
                        "gedges_per_s": round(m / ms_n / 1e6, 2),
                        "frac": round(sweep_bytes(w, n, t_seq) / (sweep_n["mean_ms"] / 1e3) / 1e9
                                      / HBM_PEAK_GBS, 5),
                        "violations": int(sum(chk_n[k] for k in VIOLATION_KEYS)),
                        "size": chk_n["matched"] // 2}
-        log("%s natural order: create %.1f ms; %.4f ms/pass, sweep %.4f ms; %.1f GEdges/s" % (
+        log("%s without the copy: create %.1f ms; %.4f ms/pass, sweep %.4f ms; %.1f GEdges/s" % (
             name, create_n, ms_n, sweep_n["mean_ms"], m / ms_n / 1e6))
     del off, nbr, out
     torch.cuda.empty_cache()
@@ -352,24 +356,30 @@ def bench_single(args, name, tun, dev, *, natural=False, conflicts=False, ceilin
         if ceilings:
             leg["atomic_frac"] = round(atomics / sweep_s / ceilings["random_atomics_per_s"], 4)
     if natural_leg:
-        leg["natural_order"] = natural_leg
+        leg["without_copy"] = natural_leg
     return leg, counters, conflict_row, sweep
 
+
+# Tuning fields that build a copy of the graph at create time, and their
+# values without it (the headline also times the graph as given).
+COPIES = {"relabel": 0, "order_lists": 0}
 
 # Design-choice variants (--variants): overrides of the tuned tuning, one
 # choice at a time, each timed and counted on the same resident graph.
 VARIANTS = {
     "tuned": {},
     "natural_order": {"relabel": 0},
-    "relabelled": {"relabel": 1},
+    # the relabelled copies replace a reordered one (the two do not combine)
+    "relabelled": {"relabel": 1, "order_lists": 0},
     "order_lists": {"order_lists": 1},
-    "relabel_hot": {"relabel": 2},
-    "relabel_hot_512": {"relabel": 2, "hot_degree": 512},
-    "relabel_hot_1024": {"relabel": 2, "hot_degree": 1024},
-    "relabel_hot_4096": {"relabel": 2, "hot_degree": 4096},
-    "relabel_hot_8192": {"relabel": 2, "hot_degree": 8192},
+    "given_lists": {"order_lists": 0},
+    "relabel_hot": {"relabel": 2, "order_lists": 0},
+    "relabel_hot_512": {"relabel": 2, "hot_degree": 512, "order_lists": 0},
+    "relabel_hot_1024": {"relabel": 2, "hot_degree": 1024, "order_lists": 0},
+    "relabel_hot_4096": {"relabel": 2, "hot_degree": 4096, "order_lists": 0},
+    "relabel_hot_8192": {"relabel": 2, "hot_degree": 8192, "order_lists": 0},
     "all_entries": {"upper_only": 0},
-    "all_entries_relabelled": {"upper_only": 0, "relabel": 1},
+    "all_entries_relabelled": {"upper_only": 0, "relabel": 1, "order_lists": 0},
     "u8_byte_cas": {"layout": 0, "protocol": 0, "lazy_init": 0},
     "u8_byte_cas_lazy": {"layout": 0, "protocol": 0, "lazy_init": 1},
     "u2_two_phase": {"layout": 2, "protocol": 1, "lazy_init": 0},
@@ -379,6 +389,8 @@ VARIANTS = {
     "no_hint": {"hint": 0},
     "assist_16": {"assist_after": 16},
     "assist_256": {"assist_after": 256},
+    "assist_64": {"assist_after": 64},
+    "wg_128": {"wg_size": 128},
     "no_assist": {"assist_after": 0},
     "contiguous_lanes": {"disperse": 0},
     "dispersed_lanes": {"disperse": 1},
@@ -386,14 +398,15 @@ VARIANTS = {
     "upper_only": {"upper_only": 1},
     "upper_only_hint_bytes": {"upper_only": 1, "hint": 2},
     "upper_only_u8": {"upper_only": 1, "layout": 0, "protocol": 0, "lazy_init": 0},
-    "upper_only_natural": {"upper_only": 1, "relabel": 0},
+    "upper_only_natural": {"upper_only": 1, "relabel": 0, "order_lists": 0},
     "upper_wait": {"upper_only": 1, "wait_release": 1},
     "hub_wave": {"hub_wave": 1},
     "hub_wave_1024": {"hub_wave": 1, "hub_chunk": 1024},
     "hub_group": {"hub_wave": 2},
     "hub_group_1024": {"hub_wave": 2, "hub_chunk": 1024},
     "hub_group_wg256": {"hub_wave": 2, "wg_size": 256},
-    "hub_lane_64": {"hub_chunk": 64},
+    "hub_lane_64": {"hub_chunk": 64, "hub_wave": 0},
+    "hub_lane": {"hub_wave": 0},
     "no_hub_tier": {"hub_degree": 0},
     "stream_loads": {"stream_loads": 1},
     "scan_2": {"scan_width": 2},
@@ -889,7 +902,8 @@ def main():
                     "size": head["size"], "size_sgmm": head["size_sgmm"], "t_seq": head["t_seq"]},
         "create_ms": head["create_ms"],
         "relabel_copy_bytes": head["relabel_copy_bytes"],
-        "natural_order": head.get("natural_order"),
+        "ordered_copy_bytes": head["ordered_copy_bytes"],
+        "without_copy": head.get("without_copy"),
         "counters": counters,
         "conflicts": conflicts,
         "legs": others,
