@@ -414,7 +414,12 @@ VARIANTS = {
     "hub_2048": {"hub_degree": 2048},
     "hub_16384": {"hub_degree": 16384},
     "wg_256": {"wg_size": 256},
+    "wv_64": {"wave_vertices": 64},
+    "wv_256": {"wave_vertices": 256},
     "wv_1024": {"wave_vertices": 1024},
+    "wg_64": {"wg_size": 64},
+    "mw_2048": {"min_waves": 2048},
+    "scan_1": {"scan_width": 1},
     "wv_4096": {"wave_vertices": 4096},
     "u32": {"layout": 1, "protocol": 0, "lazy_init": 0},
     "u8": {"layout": 0, "protocol": 0, "lazy_init": 0},

@@ -23,6 +23,8 @@ adversary picks. Pins:
   near lockstep, one wavefront starved), the sweep ends within its trip
   bound with an output in the brute-force set; the same on random 8-vertex
   graphs with four lanes in two wavefronts;
+* the order of a list is free: with every list shuffled, the adversarial
+  schedules still end in the brute-force set;
 * the model is sharp: three mistakes planted in it (no id order, no release
   of u, v taken by a plain store) are each caught on a small graph.
 """
@@ -172,6 +174,44 @@ def test_adversarial_schedules_on_larger_graphs(name):
         graphs.append(graphgen.from_edges(8, E))
     _adversarial(graphs, [(2, 2, "round"), (2, 2, "blocks"), (4, 1, "round"), (1, 4, "round")],
                  name, seed0=3)
+
+
+class _Permuted:
+    """A CSR with the entries of each list in another order (same edges)."""
+
+    def __init__(self, csr, rng):
+        self.n, self.m, self.off = csr.n, csr.m, csr.off
+        nbr = csr.nbr.copy()
+        for v in range(csr.n):
+            b, e = int(csr.off[v]), int(csr.off[v + 1])
+            nbr[b:e] = rng.permutation(nbr[b:e])
+        self.nbr = nbr
+
+
+@pytest.mark.parametrize("name", ["word_cas", "word_two_phase", "word_cas_upper", "u8_cas_word_retries",
+                                  "u2_cas_upper_wait_release"])
+def test_any_list_order(name):
+    # the order in which a lane walks a list is free (the library may reorder
+    # short lists by neighbour degree): every graph of up to 5 vertices and
+    # random 7-vertex graphs with each list shuffled, under the four
+    # adversarial strategies, still end in a maximal matching
+    rng = np.random.default_rng(17)
+    var = variant(**VARIANTS[name])
+    graphs = [g for n in range(2, 6) for g in all_graphs(n)]
+    for _ in range(120):
+        p = rng.uniform(0.2, 0.8)
+        graphs.append(graphgen.from_edges(7, [(a, b) for a, b in itertools.combinations(range(7), 2)
+                                              if rng.random() < p]))
+    cfgs = [(2, 1, "round"), (1, 2, "blocks"), (2, 2, "round")]
+    for idx, g in enumerate(graphs):
+        ok = maximal_set(g)
+        G = graph(_Permuted(g, rng))
+        w, p_, mode = cfgs[idx % len(cfgs)]
+        wave_of, src = lanes(g.n, w, p_, mode)
+        for st in STRATEGIES:
+            trips, mate = run(G, var, wave_of, src, strategy=st, seed=idx * 13 + st, max_trips=20000)
+            assert trips >= 0, (name, idx, st, trips)
+            assert tuple(mate.tolist()) in ok, (name, idx, st, mate)
 
 
 @pytest.mark.parametrize("mutant", [1, 2, 3])
