@@ -495,6 +495,44 @@ def test_unaligned_output(name, shift):
     assert_parity(g, b[shift:shift + g.n])
 
 
+# ---------------------------------------------------------------- reordered lists
+
+def expected_order(csr):
+    """The copy order_lists builds, computed here: each list of at most 256
+    entries stably sorted by 1 + floor(log2 degree) of the neighbour, longer
+    lists as given."""
+    deg = np.diff(csr.off.astype(np.int64))
+    bucket = np.zeros(csr.n, dtype=np.int64)
+    nz = deg > 0
+    bucket[nz] = np.floor(np.log2(deg[nz])).astype(np.int64) + 1
+    out = csr.nbr.copy()
+    for v in range(csr.n):
+        b, e = int(csr.off[v]), int(csr.off[v + 1])
+        if 1 < e - b <= 256:
+            seg = csr.nbr[b:e]
+            out[b:e] = seg[np.argsort(bucket[seg], kind="stable")]
+    return out
+
+
+@pytest.mark.parametrize("make", [lambda: graphgen.rmat(14, seed=3), lambda: graphgen.er(3000, 20, seed=1),
+                                  lambda: hub_trap(300)])
+def test_order_lists_copy_is_the_stable_degree_order(make):
+    # white box, bit for bit: with the word layout and no hint the workspace
+    # holds the 4 KiB control block, then the reordered copy of the ids
+    csr = make()
+    assert np.diff(csr.off).max() > 256 or csr.name.startswith("er")  # long lists stay as given
+    off, nbr = to_dev(csr)
+    h = mm.Graph(off, nbr, symmetric=True, tuning=mm.Tuning(order_lists=1))
+    base = h.workspace.data_ptr()
+    start = (base + 255) // 256 * 256 - base + 4096
+    copy = h.workspace[start:start + 4 * csr.m].view(torch.int32).cpu().numpy()
+    np.testing.assert_array_equal(copy, expected_order(csr))
+    out = h.run()
+    h.sync()
+    assert_parity(csr, out.cpu().numpy())
+    h.close()
+
+
 # ---------------------------------------------------------------- hub tier
 
 def hub_trap(k):
