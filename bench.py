@@ -218,10 +218,26 @@ def live_ceilings(dev) -> dict:
     torch.cuda.synchronize()
     atomics = 5 * aidx.numel() / (ev[0].elapsed_time(ev[1]) / 1e3)
     del acc, aidx, ones, idx
+    # device-to-device copy bandwidth (bytes read + written), a measured
+    # counterpart of the nominal 8 TB/s
+    src = torch.ones(1 << 28, dtype=torch.int32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    ev[0].record()
+    for _ in range(5):
+        dst.copy_(src)
+    ev[1].record()
+    torch.cuda.synchronize()
+    copy_gbs = 5 * 2 * src.numel() * 4 / (ev[0].elapsed_time(ev[1]) / 1e3) / 1e9
+    del src, dst
     torch.cuda.empty_cache()
     return {"random_reads_per_s": round(reads, -6), "random_atomics_per_s": round(atomics, -6),
+            "copy_gbs": round(copy_gbs, 1),
             "how": "torch index_select of 2^26 random int32 over 1 GiB; torch index_add_ of 2^26 "
-                   "random int32 slots over 512 MiB (atomic add); 5 timed repeats each"}
+                   "random int32 slots over 512 MiB (atomic add); copy_ of 1 GiB (read + write "
+                   "bytes); 5 timed repeats each"}
 
 
 def timed_passes(g, out, steps, warmup):
@@ -569,6 +585,28 @@ def bench_serve(args, dev):
             "(%.2f jobs each), %d solo" % (
                 rate, count, r["p50_ms"], r["p99_ms"], r["gedges_per_s"], r["batch_launches"],
                 r["mean_jobs_per_batch"], r["solo_launches"]))
+
+    # admission by HBM footprint under a budget that binds: four times the
+    # largest request's footprint, at the highest rate up to 2000 req/s
+    probe = scheduler()
+    fps = [probe.executor.footprint(serve.Request(0, g, 0.0), probe.route(serve.Request(0, g, 0.0)))
+           for g in graphs]
+    budget = 4 * max(fps)
+    rate = max([r for r in args.serve_rates if r <= 2000.0] or [min(args.serve_rates)])
+    count = max(args.serve_requests, int(rate * args.serve_seconds))
+    gid = rng.integers(0, len(graphs), size=count)
+    arr = serve.poisson_arrivals(count, rate, seed=args.seed + 7 * int(rate))
+    reqs = [serve.Request(i, graphs[g], float(arr[i])) for i, g in enumerate(gid)]
+    ex = serve.GpuExecutor.for_serving(batch_slots=2, solo_slots=2)
+    s = serve.Scheduler(ex, hbm_budget=budget, small_edges=2_000_000, max_batch=1024, batch_slots=2,
+                        solo_slots=2, keep_results=False)
+    comps, wall = serve.run_trace(s, reqs, timeout=120)
+    r = serve.summarize(comps, wall, int(sum(graphs[g].m for g in gid)))
+    r.update(rate_req_per_s=rate, hbm_budget_bytes=int(budget), peak_in_use_bytes=int(s.peak_in_use),
+             largest_footprint_bytes=int(max(fps)))
+    out["budget_bound"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
+    log("serve %5d req/s under a %.1f MB budget: p50 %.3f ms p99 %.3f ms, peak in use %.1f MB" % (
+        rate, budget / 1e6, r["p50_ms"], r["p99_ms"], s.peak_in_use / 1e6))
     return out
 
 
@@ -731,9 +769,9 @@ def main():
     ap.add_argument("--serve-rates", type=float, nargs="+",
                     default=[200.0, 500.0, 1000.0, 2000.0, 20000.0])
     ap.add_argument("--serve-seconds", type=float, default=1.5)
-    ap.add_argument("--serve-requests", type=int, default=2000,
-                    help="requests per rate at least (10000 gives the p99 more samples)")
-    ap.add_argument("--serve-pool", type=int, default=96)
+    ap.add_argument("--serve-requests", type=int, default=10000,
+                    help="requests per rate at least (the default 10000 puts 100 samples above the p99)")
+    ap.add_argument("--serve-pool", type=int, default=256)
     ap.add_argument("--variants", default=None,
                     help="comma-separated design-choice variants (%s): time and count each on the "
                          "workload and print one JSON line of rows instead of the benchmark line"
@@ -870,6 +908,23 @@ def main():
         secondary["l2_miss_read_requests_per_launch_stored"] = req
         if ceilings:
             secondary["request_frac"] = round(req / sweep_s / ceilings["random_reads_per_s"], 4)
+    # the same roof with other byte counts (states once per vertex, as in
+    # frac_d1): every entry's id read once (B_full, 4m for 4 T_seq), the ids
+    # this pass read (T_gpu for T_seq); the measured copy bandwidth instead
+    # of the nominal peak; the stored traffic over B_sweep
+    n_, w_ = cfg["n"], (8 if cfg.get("offsets") == "int64" else 4)
+    b_full = sweep_bytes_d1(w_, n_, m)
+    secondary["alg_bytes_full_d1"] = int(b_full)
+    secondary["frac_full_d1"] = round(b_full / sweep_s / 1e9 / HBM_PEAK_GBS, 5)
+    if counters:
+        t_gpu = counters["touched"] + counters["assist_reads"]
+        secondary["alg_bytes_t_gpu_d1"] = int(sweep_bytes_d1(w_, n_, t_gpu))
+        secondary["frac_t_gpu_d1"] = round(secondary["alg_bytes_t_gpu_d1"] / sweep_s / 1e9
+                                           / HBM_PEAK_GBS, 5)
+    if ceilings and ceilings.get("copy_gbs"):
+        secondary["frac_of_copy_bw"] = round(achieved / ceilings["copy_gbs"], 5)
+    if traffic:
+        secondary["traffic_over_alg_bytes"] = round(traffic / b_sweep, 3)
     result = {
         "metric": METRIC,
         "value": round(value, 3),
