@@ -580,18 +580,20 @@ def bench_serve(args, dev):
         r = serve.summarize(comps, wall, edges)
         r["rate_req_per_s"] = rate
         r["peak_in_use_bytes"] = int(s.peak_in_use)
+        r["memory_waits"] = int(s.memory_waits)
         out["rates"].append({k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()})
         log("serve %5d req/s: %d requests, p50 %.3f ms p99 %.3f ms, %.1f GEdges/s, %d batches "
             "(%.2f jobs each), %d solo" % (
                 rate, count, r["p50_ms"], r["p99_ms"], r["gedges_per_s"], r["batch_launches"],
                 r["mean_jobs_per_batch"], r["solo_launches"]))
 
-    # admission by HBM footprint under a budget that binds: four times the
-    # largest request's footprint, at the highest rate up to 2000 req/s
+    # admission by HBM footprint under a budget that binds: 1.25 times the
+    # largest request's footprint (two of the largest jobs never run at
+    # once), at the highest rate up to 2000 req/s
     probe = scheduler()
     fps = [probe.executor.footprint(serve.Request(0, g, 0.0), probe.route(serve.Request(0, g, 0.0)))
            for g in graphs]
-    budget = 4 * max(fps)
+    budget = int(1.25 * max(fps))
     rate = max([r for r in args.serve_rates if r <= 2000.0] or [min(args.serve_rates)])
     count = max(args.serve_requests, int(rate * args.serve_seconds))
     gid = rng.integers(0, len(graphs), size=count)
@@ -603,10 +605,11 @@ def bench_serve(args, dev):
     comps, wall = serve.run_trace(s, reqs, timeout=120)
     r = serve.summarize(comps, wall, int(sum(graphs[g].m for g in gid)))
     r.update(rate_req_per_s=rate, hbm_budget_bytes=int(budget), peak_in_use_bytes=int(s.peak_in_use),
-             largest_footprint_bytes=int(max(fps)))
+             largest_footprint_bytes=int(max(fps)), memory_waits=int(s.memory_waits))
     out["budget_bound"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
-    log("serve %5d req/s under a %.1f MB budget: p50 %.3f ms p99 %.3f ms, peak in use %.1f MB" % (
-        rate, budget / 1e6, r["p50_ms"], r["p99_ms"], s.peak_in_use / 1e6))
+    log("serve %5d req/s under a %.1f MB budget: p50 %.3f ms p99 %.3f ms, peak in use %.1f MB, "
+        "%d requests waited for memory" % (rate, budget / 1e6, r["p50_ms"], r["p99_ms"],
+                                           s.peak_in_use / 1e6, s.memory_waits))
     return out
 
 

@@ -157,7 +157,9 @@ class Scheduler:
     completions: list = field(default_factory=list)
     in_use: int = 0
     peak_in_use: int = 0
+    memory_waits: int = 0   # requests that waited at the head for memory to free up
     _admit_time: dict = field(default_factory=dict)
+    _blocked: int = -1      # the request last counted in memory_waits
     _fp: dict = field(default_factory=dict)
     _free_batch: list = None
     _free_solo: list = None
@@ -213,6 +215,9 @@ class Scheduler:
             fp = self._fp[r.rid]
             route = self.route(r)
             if self.in_use + fp > self.hbm_budget:
+                if r.rid != self._blocked:
+                    self.memory_waits += 1
+                    self._blocked = r.rid
                 break
             if route == "solo" and not self._free_solo:
                 break

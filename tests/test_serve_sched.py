@@ -124,6 +124,8 @@ def test_head_of_line_blocks_on_memory():
     assert order == [0, 1, 2]
     c = {x.rid: x for x in s.completions}
     assert c[1].admitted >= c[0].done and c[2].admitted >= c[1].admitted
+    # request 1 waited for memory (counted once, however many rounds it waited)
+    assert s.memory_waits == 1
 
 
 def test_oversized_request_is_rejected():
