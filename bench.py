@@ -18,8 +18,9 @@ cpu_baseline: the oracle's single-thread SGMM, pinned to one host core, on
 legs: every single-graph configuration (ER n=65536 with int32 offsets,
       R-MAT-24, R-MAT-27, the 16384^2 grid) with create time, the sweep of the
       graph as given beside one on a create-time copy (relabelled or with
-      reordered lists), B_alg, frac, T_gpu/m and its SGMM
-      baseline; batch: the 4096-graph mixture in one captured persistent
+      reordered lists), B_alg, frac, T_gpu/m and its SGMM baseline, and for
+      ER and R-MAT-24 the multi-pass mutual-selection baseline (time, passes,
+      ids read); batch: the 4096-graph mixture in one captured persistent
       launch against one launch per graph, with its algorithmic bytes from
       every member's T_seq; serve: Poisson request streams over resident
       graphs (p50/p99 arrival-to-result latency, GEdges/s).
@@ -261,7 +262,8 @@ def timed_passes(g, out, steps, warmup):
     return ev0.elapsed_time(ev1) / steps, g.timing()
 
 
-def bench_single(args, name, tun, dev, *, natural=False, conflicts=False, ceilings=None):
+def bench_single(args, name, tun, dev, *, natural=False, conflicts=False, ceilings=None,
+                 ems=False):
     """One single-graph configuration: the oracle baseline (T_seq), the
     handle's create time, `steps` timed passes, the device check, an
     instrumented pass (T_gpu, atomics, conflicts), and, for a tuning that
@@ -299,6 +301,29 @@ def bench_single(args, name, tun, dev, *, natural=False, conflicts=False, ceilin
         "violations %d, size %d (SGMM %d)" % (
             name, create_ms, ms_per_step, sweep["mean_ms"], sweep["min_ms"], sweep["max_ms"],
             m / ms_per_step / 1e6, viol, size, ref.pairs))
+
+    ems_leg = None
+    if ems:
+        # the multi-pass baseline the paper compares with (Section II-C), on
+        # the same resident graph: time, passes and ids read against the sweep
+        ge = mm.Graph(off, nbr, symmetric=True, tuning=tun)
+        o_e, st_e = ge.ems(seed=args.seed)
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(3):
+            t_e = time.perf_counter()
+            o_e, st_e = ge.ems(seed=args.seed, out=o_e)
+            torch.cuda.synchronize()
+            times.append((time.perf_counter() - t_e) * 1e3)
+        chk_e = ge.check(o_e)
+        ge.close()
+        ems_leg = {"ms": round(float(np.median(times)), 3), "iterations": int(st_e["iterations"]),
+                   "touched_over_m": round(st_e["touched"] / m, 4), "pairs": int(st_e["pairs"]),
+                   "violations": int(sum(chk_e[k] for k in VIOLATION_KEYS)),
+                   "sweep_speedup": round(float(np.median(times)) / ms_per_step, 1)}
+        log("%s mutual selection: %.3f ms, %d passes, ids read %.3f m, %d pairs (sweep %.4f ms)" % (
+            name, ems_leg["ms"], ems_leg["iterations"], ems_leg["touched_over_m"], ems_leg["pairs"],
+            ms_per_step))
 
     counters = conflict_row = None
     if not args.no_stats:
@@ -373,6 +398,8 @@ def bench_single(args, name, tun, dev, *, natural=False, conflicts=False, ceilin
             leg["atomic_frac"] = round(atomics / sweep_s / ceilings["random_atomics_per_s"], 4)
     if natural_leg:
         leg["without_copy"] = natural_leg
+    if ems_leg:
+        leg["mutual_selection"] = ems_leg
     return leg, counters, conflict_row, sweep
 
 
@@ -868,7 +895,8 @@ def main():
         for name in ("er65536", "rmat24", "grid16384"):
             if name in legs:
                 out[name] = bench_single(args, name, tuning_for(workload_class(name)), dev,
-                                         natural=True, ceilings=ceilings)[0]
+                                         natural=True, ceilings=ceilings,
+                                         ems=name in ("er65536", "rmat24"))[0]
         if "batch" in legs:
             tb = mm.Tuning.default() if args.untuned else autotune.tuned("batch")
             out["batch"] = dict(bench_batch(args, tb, dev), tuning=tb.as_dict())
@@ -885,7 +913,8 @@ def main():
     for name in ("er65536", "rmat24", "grid16384"):
         if name in legs and name != args.workload:
             others[name] = bench_single(args, name, tuning_for(workload_class(name)), dev,
-                                        natural=True, ceilings=ceilings)[0]
+                                        natural=True, ceilings=ceilings,
+                                        ems=name in ("er65536", "rmat24"))[0]
     batch = None
     if "batch" in legs:
         tb = mm.Tuning.default() if args.untuned else autotune.tuned("batch")

@@ -48,35 +48,85 @@ __global__ void ems_fill_kernel(int32_t* __restrict__ mate, int64_t n) {
 }
 
 // Selection: sel[x] = the unmatched neighbour y of unmatched x whose edge is
-// heaviest (weight descending, then key ascending), or -1.
+// heaviest (weight descending, then key ascending), or -1. A wavefront takes
+// 64 vertices, one per lane; a list of more than 64 entries is then scanned
+// by the whole wavefront (lanes 64 entries apart, a shuffle reduction), so
+// that a hub's list does not hold one lane for its whole length.
+__device__ __forceinline__ bool heavier(uint64_t w, uint64_t key, uint64_t bw, uint64_t bkey) {
+  return w > bw || (w == bw && key < bkey);
+}
+
 template <typename OffT>
 __global__ void ems_select_kernel(const OffT* __restrict__ off, const int32_t* __restrict__ nbr,
                                   int64_t n, const int32_t* __restrict__ mate,
                                   int32_t* __restrict__ sel, uint64_t seed_mix,
                                   unsigned long long* counters) {
   unsigned long long touched = 0, selecting = 0;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += stride) {
+  const int lane = (int)(threadIdx.x & 63);
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t base = wave * 64; base < n; base += waves * 64) {
+    const int64_t x = base + lane;
     int32_t best = -1;
-    if (mate[x] == -1) {
-      uint64_t bw = 0, bkey = 0;
-      const int64_t b = (int64_t)off[x], e = (int64_t)off[x + 1];
+    int64_t b = 0, e = 0;
+    bool longl = false;
+    if (x < n && mate[x] == -1) {
+      b = (int64_t)off[x];
+      e = (int64_t)off[x + 1];
       touched += (unsigned long long)(e - b);
-      for (int64_t i = b; i < e; ++i) {
+      longl = e - b > 64;
+      uint64_t bw = 0, bkey = 0;
+      for (int64_t i = b; i < e && !longl; ++i) {
         const int64_t y = nbr[i];
         if (y == x || mate[y] != -1) continue;
         const uint64_t key = x < y ? ((uint64_t)x << 32) | (uint64_t)y
                                    : ((uint64_t)y << 32) | (uint64_t)x;
         const uint64_t w = splitmix64(seed_mix ^ key);
-        if (best < 0 || w > bw || (w == bw && key < bkey)) {
+        if (best < 0 || heavier(w, key, bw, bkey)) {
           best = (int32_t)y;
           bw = w;
           bkey = key;
         }
       }
     }
-    sel[x] = best;
-    selecting += best >= 0;
+    if (x < n && !longl) {
+      sel[x] = best;
+      selecting += best >= 0;
+    }
+    uint64_t lm = __ballot(longl);
+    while (lm) {
+      const int l = __builtin_ctzll(lm);
+      lm &= lm - 1;
+      const int64_t xl = __shfl(x, l, 64), lb = __shfl(b, l, 64), le = __shfl(e, l, 64);
+      int32_t by = -1;
+      uint64_t bw = 0, bkey = ~0ull;
+      for (int64_t i = lb + lane; i < le; i += 64) {
+        const int64_t y = nbr[i];
+        if (y == xl || mate[y] != -1) continue;
+        const uint64_t key = xl < y ? ((uint64_t)xl << 32) | (uint64_t)y
+                                    : ((uint64_t)y << 32) | (uint64_t)xl;
+        const uint64_t w = splitmix64(seed_mix ^ key);
+        if (by < 0 || heavier(w, key, bw, bkey)) {
+          by = (int32_t)y;
+          bw = w;
+          bkey = key;
+        }
+      }
+#pragma unroll
+      for (int d = 32; d >= 1; d >>= 1) {
+        const int32_t oy = __shfl_xor(by, d, 64);
+        const uint64_t ow = __shfl_xor(bw, d, 64), okey = __shfl_xor(bkey, d, 64);
+        if (oy >= 0 && (by < 0 || heavier(ow, okey, bw, bkey))) {
+          by = oy;
+          bw = ow;
+          bkey = okey;
+        }
+      }
+      if (lane == l) {
+        sel[xl] = by;
+        selecting += by >= 0;
+      }
+    }
   }
   wave_add(touched, counters + 0);
   wave_add(selecting, counters + 1);
