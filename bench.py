@@ -425,6 +425,8 @@ VARIANTS = {
     "all_entries_relabelled": {"upper_only": 0, "relabel": 1, "order_lists": 0},
     "u8_byte_cas": {"layout": 0, "protocol": 0, "lazy_init": 0},
     "u8_byte_cas_lazy": {"layout": 0, "protocol": 0, "lazy_init": 1},
+    "lazy": {"lazy_init": 1},
+    "eager": {"lazy_init": 0},
     "u2_two_phase": {"layout": 2, "protocol": 1, "lazy_init": 0},
     "u32_two_phase": {"layout": 1, "protocol": 1, "lazy_init": 0},
     "hint_bits": {"hint": 1},
