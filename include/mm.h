@@ -126,7 +126,11 @@ typedef struct {
                             long scan 64 entries at a time; <= 0 disables */
   int32_t lazy_init;     /* 1: unmatched outputs written by the sweep itself instead
                             of a separate fill (needs MM_SYMMETRIC; not with
-                            MM_LAYOUT_U32 + MM_PROTOCOL_CAS, where it is implicit) */
+                            MM_LAYOUT_U32 + MM_PROTOCOL_CAS, where it is implicit,
+                            nor with upper_only or relabel). Applies only where the
+                            hub tier cannot cut a list: hub_degree = 0, m <=
+                            hub_degree, or a graph swept whole by one wavefront;
+                            elsewhere the output is written eagerly */
   int32_t scan_width;    /* neighbour ids a lane reads per scan step: 1..4 */
   int32_t stream_loads;  /* 1: read offsets and neighbour ids with non-temporal loads,
                             so that their lines are evicted first and the state (or

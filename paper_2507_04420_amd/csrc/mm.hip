@@ -755,9 +755,15 @@ mm_status mm_create(const void* offsets, mm_offset_type off_type, const int32_t*
   g->flags = flags;
   g->tun = t;
   // Lazy output is only sound when every edge is in both endpoints' lists
-  // and both endpoints examine it.
+  // and both endpoints examine it, and when no hub piece can hold part of a
+  // source's list (a piece cannot finalise its source). The last condition
+  // is decided from the tuning and the sizes, as mm_run_static decides it
+  // without counting the pieces, so that both entry points run the same
+  // kernels for the same graph and tuning.
+  const bool may_have_pieces = n > t.whole_graph_vertices &&
+                               mmi::hub_pieces_bound(m, t.hub_degree, t.hub_chunk) > 0;
   g->lazy = t.lazy_init && (flags & MM_SYMMETRIC) && !t.relabel && !t.upper_only &&
-            !(t.layout == MM_LAYOUT_U32 && t.protocol == MM_PROTOCOL_CAS);
+            !may_have_pieces && !(t.layout == MM_LAYOUT_U32 && t.protocol == MM_PROTOCOL_CAS);
   // a graph swept whole by one wavefront gets no hub pieces (as in batches)
   if (t.hub_degree > 0 && m > t.hub_degree && n > t.whole_graph_vertices) {
     // the table is built on the lists the sweep reads (relabelled or given)
@@ -890,6 +896,7 @@ mm_status mm_run_static(const void* offsets, mm_offset_type off_type, const int3
   g.rl = mmi::RelabelView{};
   g.rl_state = nullptr;
   g.err_out = status_out;
+  // the same rule as mm_create's
   g.lazy = t.lazy_init && (flags & MM_SYMMETRIC) && pieces == 0 && !t.upper_only &&
            !(t.layout == MM_LAYOUT_U32 && t.protocol == MM_PROTOCOL_CAS);
   if (pieces > 0) {

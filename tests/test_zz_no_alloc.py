@@ -71,6 +71,8 @@ def compare(csr, statics, runs, exact):
     else:
         bound = max(2, 0.01 * oracle.sgmm(csr).pairs)
         sa, sb = [c.size for c in cas], [c.size for c in cbs]
+        print("%s: static %s, mm_run %s, mean difference %.2f of the bound" % (
+            csr.name, sa, sb, abs(np.mean(sa) - np.mean(sb)) / bound))
         assert abs(np.mean(sa) - np.mean(sb)) <= bound, (csr.name, sa, sb, bound)
 
 
