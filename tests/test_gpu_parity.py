@@ -495,6 +495,61 @@ def test_unaligned_output(name, shift):
     assert_parity(g, b[shift:shift + g.n])
 
 
+def expected_relabel(csr, mode, hot):
+    """The relabelled copy relabel.hip builds, computed here: new -> given map
+    (a stable sort by the mode's key), int64 offsets in the new order, and the
+    lists with ids mapped (mode 1: lists of at most 64 entries sorted by new
+    id; mode 2: given order)."""
+    deg = np.diff(csr.off.astype(np.int64))
+    if mode == 1:
+        key = np.zeros(csr.n, dtype=np.int64)
+        nz = deg > 0
+        key[nz] = np.floor(np.log2(deg[nz])).astype(np.int64) + 1
+    else:
+        key = np.where(deg == 0, 0, np.where(deg > hot, 2, 1))
+    orig = np.argsort(key, kind="stable").astype(np.int32)
+    inv = np.empty(csr.n, dtype=np.int64)
+    inv[orig] = np.arange(csr.n)
+    roff = np.zeros(csr.n + 1, dtype=np.int64)
+    roff[1:] = np.cumsum(deg[orig])
+    rnbr = np.empty(csr.m, dtype=np.int32)
+    for v in range(csr.n):
+        x = orig[v]
+        lst = inv[csr.nbr[csr.off[x]:csr.off[x + 1]]]
+        if mode == 1 and len(lst) <= 64:
+            lst = np.sort(lst)
+        rnbr[roff[v]:roff[v + 1]] = lst
+    return orig, roff, rnbr
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_relabelled_copy_is_the_stated_order(mode):
+    # white box, bit for bit: with the word layout and no hint the workspace
+    # holds the 4 KiB control block, the states in new ids (4n), then the
+    # relabelled offsets, the new -> given map and the lists
+    csr = graphgen.rmat(13, seed=4)
+    hot = 40
+    off, nbr = to_dev(csr)
+    h = mm.Graph(off, nbr, symmetric=True, tuning=mm.Tuning(relabel=mode, hot_degree=hot))
+    r256 = lambda b: (b + 255) // 256 * 256
+    base = h.workspace.data_ptr()
+    region = (base + 255) // 256 * 256 - base + 4096 + r256(4 * csr.n)
+    ws = h.workspace
+    roff = ws[region:region + 8 * (csr.n + 1)].view(torch.int64).cpu().numpy()
+    o0 = region + r256(8 * (csr.n + 1))
+    orig = ws[o0:o0 + 4 * csr.n].view(torch.int32).cpu().numpy()
+    n0 = o0 + r256(4 * csr.n)
+    rnbr = ws[n0:n0 + 4 * csr.m].view(torch.int32).cpu().numpy()
+    e_orig, e_roff, e_rnbr = expected_relabel(csr, mode, hot)
+    np.testing.assert_array_equal(orig, e_orig)
+    np.testing.assert_array_equal(roff, e_roff)
+    np.testing.assert_array_equal(rnbr, e_rnbr)
+    out = h.run()
+    h.sync()
+    assert_parity(csr, out.cpu().numpy())
+    h.close()
+
+
 # ---------------------------------------------------------------- reordered lists
 
 def expected_order(csr):
