@@ -186,41 +186,20 @@ def sweep_bytes_d1(w: int, n: int, t_seq: int) -> int:
 
 
 def live_ceilings(dev) -> dict:
-    """The two ceilings of a pass of random accesses, measured on this GPU
-    with plain torch operations (not this library's kernels): independent
-    random 4-byte reads over a 1 GiB array (each one line request past L2),
-    and independent atomic adds at random 4-byte slots of a 512 MiB array."""
+    """The ceilings of a pass of random accesses, measured on this GPU: the
+    library's probe (mm_probe_ceilings: plain kernels of independent random
+    4-byte reads, and of random 4-byte atomic adds, over 1 GiB, 2^26 of each,
+    no other memory traffic), and a device-to-device copy of 1 GiB with torch
+    (bytes read + written) as a measured counterpart of the nominal 8 TB/s."""
+    import ctypes
     import torch
-    g = torch.Generator(device=dev)
-    g.manual_seed(12345)
-    data = torch.ones(1 << 28, dtype=torch.int32, device=dev)
-    idx = torch.randint(0, 1 << 28, (1 << 26,), device=dev, generator=g)
+    from paper_2507_04420_amd import _lib
+    lib = _lib.load()
+    reads, atomics = ctypes.c_double(), ctypes.c_double()
+    stream = torch.cuda.current_stream(dev)
+    _lib.check(lib.mm_probe_ceilings(1 << 30, 1 << 26, ctypes.c_void_p(stream.cuda_stream),
+                                     ctypes.byref(reads), ctypes.byref(atomics)))
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-    for _ in range(2):
-        data.index_select(0, idx)
-    torch.cuda.synchronize()
-    ev[0].record()
-    for _ in range(5):
-        data.index_select(0, idx)
-    ev[1].record()
-    torch.cuda.synchronize()
-    reads = 5 * idx.numel() / (ev[0].elapsed_time(ev[1]) / 1e3)
-    del data
-    acc = torch.zeros(1 << 27, dtype=torch.int32, device=dev)
-    aidx = idx % (1 << 27)
-    ones = torch.ones(aidx.numel(), dtype=torch.int32, device=dev)
-    for _ in range(2):
-        acc.index_add_(0, aidx, ones)
-    torch.cuda.synchronize()
-    ev[0].record()
-    for _ in range(5):
-        acc.index_add_(0, aidx, ones)
-    ev[1].record()
-    torch.cuda.synchronize()
-    atomics = 5 * aidx.numel() / (ev[0].elapsed_time(ev[1]) / 1e3)
-    del acc, aidx, ones, idx
-    # device-to-device copy bandwidth (bytes read + written), a measured
-    # counterpart of the nominal 8 TB/s
     src = torch.ones(1 << 28, dtype=torch.int32, device=dev)
     dst = torch.empty_like(src)
     for _ in range(2):
@@ -234,11 +213,11 @@ def live_ceilings(dev) -> dict:
     copy_gbs = 5 * 2 * src.numel() * 4 / (ev[0].elapsed_time(ev[1]) / 1e3) / 1e9
     del src, dst
     torch.cuda.empty_cache()
-    return {"random_reads_per_s": round(reads, -6), "random_atomics_per_s": round(atomics, -6),
+    return {"random_reads_per_s": round(reads.value, -6), "random_atomics_per_s": round(atomics.value, -6),
             "copy_gbs": round(copy_gbs, 1),
-            "how": "torch index_select of 2^26 random int32 over 1 GiB; torch index_add_ of 2^26 "
-                   "random int32 slots over 512 MiB (atomic add); copy_ of 1 GiB (read + write "
-                   "bytes); 5 timed repeats each"}
+            "how": "mm_probe_ceilings: 2^26 independent random 4-byte reads, then 2^26 random "
+                   "4-byte atomic adds, over 1 GiB (plain kernels, two timed launches each); "
+                   "torch copy_ of 1 GiB (read + write bytes), 5 timed repeats"}
 
 
 def timed_passes(g, out, steps, warmup):

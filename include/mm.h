@@ -482,6 +482,18 @@ size_t mm_ems_scratch_bytes(int64_t n);
 mm_status mm_ems_run(mm_handle h, void* stream, uint64_t seed, void* scratch,
                      size_t scratch_bytes, int32_t* match_out, mm_ems_stats* stats);
 
+/* ------------------------------------------------------------------ measurement
+ * The two ceilings that bind a pass of random state accesses on this GPU
+ * (the secondary roofs beside HBM bandwidth): the rate of independent random
+ * 4-byte reads and of random 4-byte atomic adds (agent scope) over an array
+ * of array_bytes bytes (>= 4096), ops of each, by plain kernels whose only
+ * memory traffic is those accesses. Allocates and frees its own device array
+ * (array_bytes + 256 bytes, stream-ordered on `stream`) and waits for
+ * `stream`. Outputs: operations per second.
+ */
+mm_status mm_probe_ceilings(int64_t array_bytes, int64_t ops, void* stream, double* reads_per_s,
+                            double* atomics_per_s);
+
 /* Thread-local description of the last non-OK status returned on this thread. */
 const char* mm_last_error(void);
 

@@ -116,6 +116,8 @@ SIGNATURES = {
     "mm_pairs": (_I32, [_P, _P, _P, _P, _I64, ctypes.POINTER(_I64)]),
     "mm_ems_scratch_bytes": (_SZ, [_I64]),
     "mm_ems_run": (_I32, [_P, _P, ctypes.c_uint64, _P, _SZ, _P, ctypes.POINTER(mm_ems_stats)]),
+    "mm_probe_ceilings": (_I32, [_I64, _I64, _P, ctypes.POINTER(ctypes.c_double),
+                                 ctypes.POINTER(ctypes.c_double)]),
     "mm_last_error": (ctypes.c_char_p, []),
     "mm_version": (ctypes.c_char_p, []),
 }

@@ -12,7 +12,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libmm_hip.so")
 SOURCES = [os.path.join(CSRC, f) for f in ("mm.hip", "batch.hip", "check.hip", "pairs.hip", "ems.hip",
-                                           "relabel.hip", "hubs.hip", "order.hip")]
+                                           "relabel.hip", "hubs.hip", "order.hip", "probe.hip")]
 HEADERS = [os.path.join(CSRC, f) for f in ("protocol.h", "sweep.h", "batch.h", "internal.h",
                                            "pieces.h", "whole.h")] + [
     os.path.join(ROOT, "include", "mm.h")]

@@ -253,3 +253,11 @@ def test_batch_workspace_short_blocks_and_mesh_room():
     f = _batch_bytes(lib, [1000] * 8, wave_vertices=64)
     g = _batch_bytes(lib, [1000] * 8, wave_vertices=4096)
     assert f == g
+
+
+def test_probe_rejects_bad_arguments_without_a_device():
+    lib = _lib.load()
+    r, a = ctypes.c_double(), ctypes.c_double()
+    assert lib.mm_probe_ceilings(100, 10, None, ctypes.byref(r), ctypes.byref(a)) == _lib.MM_ERR_INVALID_ARG
+    assert lib.mm_probe_ceilings(1 << 20, 0, None, ctypes.byref(r), ctypes.byref(a)) == _lib.MM_ERR_INVALID_ARG
+    assert lib.mm_probe_ceilings(1 << 20, 10, None, None, ctypes.byref(a)) == _lib.MM_ERR_INVALID_ARG

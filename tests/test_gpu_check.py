@@ -124,3 +124,14 @@ def test_check_rejects_bad_tensor():
         g.check(torch.zeros(15, dtype=torch.int32, device="cuda"))
     with pytest.raises(ValueError):
         g.check(torch.zeros(16, dtype=torch.int64, device="cuda"))
+
+
+def test_probe_ceilings_are_plausible():
+    # the measurement probe behind the bench's secondary roofs: positive rates
+    # of a plausible size for random 4-byte accesses to 256 MiB
+    import ctypes
+    from paper_2507_04420_amd import _lib
+    lib = _lib.load()
+    r, a = ctypes.c_double(), ctypes.c_double()
+    assert lib.mm_probe_ceilings(1 << 28, 1 << 24, None, ctypes.byref(r), ctypes.byref(a)) == 0
+    assert 1e9 < r.value < 1e12 and 1e8 < a.value < 1e12, (r.value, a.value)
