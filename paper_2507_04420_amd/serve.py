@@ -153,6 +153,7 @@ class Scheduler:
     keep_results: bool = True
     pending: deque = field(default_factory=deque)   # arrived, not admitted
     ready: deque = field(default_factory=deque)     # admitted small jobs awaiting a batch
+    solo_ready: deque = field(default_factory=deque)  # admitted large jobs awaiting a solo slot
     inflight: list = field(default_factory=list)
     completions: list = field(default_factory=list)
     in_use: int = 0
@@ -180,12 +181,13 @@ class Scheduler:
         self.pending.append(req)
 
     def idle(self) -> bool:
-        return not (self.pending or self.ready or self.inflight)
+        return not (self.pending or self.ready or self.solo_ready or self.inflight)
 
     def step(self, now: float) -> int:
         """One scheduling round; returns the number of requests completed."""
         done = self._retire(now)
         self._admit(now)
+        self._launch_solos(now)
         self._launch_batches(now)
         return done
 
@@ -208,28 +210,33 @@ class Scheduler:
         return count
 
     def _admit(self, now):
-        # strict arrival order: a request that does not fit blocks those behind
-        # it, so a large job is never starved by a stream of small ones
+        # memory is granted in strict arrival order: a request that does not
+        # fit blocks those behind it, so a large job is never starved by a
+        # stream of small ones. A large job that fits waits for a solo slot
+        # with its memory held, and the small jobs behind it, which need no
+        # solo slot, go on into batches
         while self.pending:
             r = self.pending[0]
             fp = self._fp[r.rid]
-            route = self.route(r)
             if self.in_use + fp > self.hbm_budget:
                 if r.rid != self._blocked:
                     self.memory_waits += 1
                     self._blocked = r.rid
                 break
-            if route == "solo" and not self._free_solo:
-                break
             self.pending.popleft()
             self.in_use += fp
             self.peak_in_use = max(self.peak_in_use, self.in_use)
             self._admit_time[r.rid] = now
-            if route == "solo":
-                slot = self._free_solo.pop(0)
-                self._start("solo", [r], slot, now, fp)
+            if self.route(r) == "solo":
+                self.solo_ready.append(r)
             else:
                 self.ready.append(r)
+
+    def _launch_solos(self, now):
+        while self.solo_ready and self._free_solo:
+            r = self.solo_ready.popleft()
+            slot = self._free_solo.pop(0)
+            self._start("solo", [r], slot, now, self._fp[r.rid])
 
     def _launch_batches(self, now):
         while self.ready and self._free_batch:

@@ -108,8 +108,29 @@ def test_large_jobs_use_solo_slots_and_overlap():
     drive(s, ex, reqs)
     solo = [L for L in ex.launches if L["route"] == "solo"]
     assert len(solo) == 3 and {L["slot"] for L in solo} == {0, 1}
-    # the third solo job waited for a slot; the small job behind it waited too (arrival order)
     assert ex.launches[0]["reqs"] == [0] and ex.launches[1]["reqs"] == [1]
+    # the third solo job waits for a slot with its memory held; the small job
+    # behind it needs no solo slot and is batched at once, ahead of it
+    order = [L["reqs"] for L in ex.launches]
+    assert order.index([3]) < order.index([2])
+    c = {x.rid: x for x in s.completions}
+    assert c[3].launched < c[2].launched
+
+
+def test_waiting_solo_job_keeps_its_place_for_memory():
+    # a large job waiting for a solo slot holds its memory: later small jobs
+    # are admitted only into what is left, so they cannot starve it
+    ex = FakeExecutor()
+    fp_big = 8 * 100_000 + 4096
+    budget = 3 * fp_big
+    s = Scheduler(ex, hbm_budget=budget, small_edges=1000, solo_slots=1, batch_slots=4)
+    reqs = [Request(0, graph(100_000, 10**6), 0.0), Request(1, graph(100_000, 10**6), 0.0)]
+    reqs += [Request(2 + k, graph(50_000, 500), 1e-5) for k in range(10)]
+    seen = drive(s, ex, reqs)
+    assert max(seen) <= budget
+    c = {x.rid: x for x in s.completions}
+    # job 1 was admitted (memory granted) before any of the later small jobs
+    assert all(c[1].admitted <= c[k].admitted for k in range(2, 12))
 
 
 def test_head_of_line_blocks_on_memory():
