@@ -394,6 +394,16 @@ VARIANTS = {
     # the relabelled copies replace a reordered one (the two do not combine)
     "relabelled": {"relabel": 1, "order_lists": 0},
     "order_lists": {"order_lists": 1},
+    "upper_first": {"order_lists": 2, "upper_only": 1},
+    "probe_first": {"probe_first": 1},
+    "probe_each": {"probe_first": 2},
+    "probe_first_upper_first": {"probe_first": 1, "order_lists": 2, "upper_only": 1},
+    "probe_first_given_lists": {"probe_first": 1, "order_lists": 0},
+    "probe_none": {"probe_first": 0},
+    "chunk_256": {"hub_chunk": 256},
+    "assist_chunk_256": {"assist_after": 256, "hub_chunk": 256},
+    "probe_first_w2": {"probe_first": 1, "scan_width": 2},
+    "probe_first_w3": {"probe_first": 1, "scan_width": 3},
     "given_lists": {"order_lists": 0},
     "relabel_hot": {"relabel": 2, "order_lists": 0},
     "relabel_hot_512": {"relabel": 2, "hot_degree": 512, "order_lists": 0},

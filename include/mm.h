@@ -226,7 +226,21 @@ typedef struct {
                             sooner. Ids, offsets, states and output are the
                             given ones. Workspace from mm_workspace_bytes_graph
                             (4m bytes more); create allocates n bytes of
-                            temporary device memory and waits for the copy */
+                            temporary device memory and waits for the copy.
+                            2 (needs upper_only = 1): the same copy with each
+                            such list's neighbours above its vertex first (each
+                            part in that degree order), so that on symmetric
+                            input a scan, which skips the neighbours below its
+                            source, ends at the first of them. 0: the given
+                            lists */
+  int32_t probe_first;   /* 1: the first state read of each source's scan reads only
+                            its first candidate (on lists in degree order that
+                            one is usually free, and reading the next candidates'
+                            states with it would be wasted requests); later reads
+                            take the rest of a step's scan_width ids together.
+                            2: every state read takes one candidate (ids are
+                            still read scan_width at a time). 0: every read
+                            takes a whole step's candidates */
   int64_t iter_cap;      /* loop-trip budget per wavefront; 0 = default of
                             65536 + 8 x (neighbour entries of its block);
                             exceeding it raises MM_ERR_NO_PROGRESS */

@@ -54,6 +54,7 @@ class Tuning:
     min_waves: int = 32
     hot_degree: int = 2048
     order_lists: int = 0
+    probe_first: int = 0
     iter_cap: int = 0
 
     @classmethod

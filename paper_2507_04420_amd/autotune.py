@@ -37,7 +37,8 @@ SPACE = {
                         (_lib.MM_LAYOUT_U2, _lib.MM_PROTOCOL_TWO_PHASE),
                         (_lib.MM_LAYOUT_U32, _lib.MM_PROTOCOL_TWO_PHASE)],
     "relabel": [0, 1, 2],
-    "order_lists": [0, 1],
+    "order_lists": [0, 1, 2],
+    "probe_first": [0, 1, 2],
     "hot_degree": [512, 1024, 2048, 4096, 8192],
     "hint": [0, 1, 2],
     "disperse": [0, 1],

@@ -630,6 +630,8 @@ mm_status finish_create(std::vector<mmb::GraphDesc>& descs, const std::vector<in
   p.params.wait_release = t.wait_release;
   p.params.upper_only = (t.upper_only && (flags & MM_SYMMETRIC)) ? 1 : 0;
   p.params.hub_wave = t.hub_wave;
+  p.params.lower_stop = 0;  // no reordered copy of a batch's lists
+  p.params.probe_first = t.probe_first;
   p.params.iter_cap = t.iter_cap;
   p.params.hub_degree = n_chunks > 0 ? t.hub_degree : 0;
   p.params.hub_chunk = t.hub_chunk;

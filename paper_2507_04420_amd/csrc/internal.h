@@ -62,11 +62,13 @@ inline int64_t hub_pieces_bound(int64_t m, int64_t hub_degree, int64_t chunk) {
 hipError_t build_relabel(const void* off, int off64, const int32_t* nbr, int64_t n, int64_t m,
                          int mode, int64_t hot, uint8_t* region, RelabelView* view, hipStream_t s);
 // The neighbour lists with each list of at most 256 entries reordered by
-// ascending log2 degree of the neighbour (order.hip), written to out (m ids);
-// waits for the copy before it returns. Temporary device memory: at most
-// order_temp_bytes(n), freed before it returns.
+// ascending log2 degree of the neighbour (order.hip), with upper_first the
+// neighbours above the list's vertex before those below it, written to out
+// (m ids); waits for the copy before it returns. Temporary device memory: at
+// most order_temp_bytes(n), freed before it returns.
+constexpr int64_t kOrderedMax = 256;  // the longest list the copy reorders
 hipError_t build_ordered_lists(const void* off, int off64, const int32_t* nbr, int64_t n,
-                               int32_t* out, hipStream_t s);
+                               int upper_first, int32_t* out, hipStream_t s);
 size_t order_temp_bytes(int64_t n);
 
 // The hub tier's table (see hubs.hip), allocated stream-ordered on s and

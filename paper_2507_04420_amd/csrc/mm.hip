@@ -67,14 +67,19 @@ mm_status check_tuning(const mm_tuning& t) {
     return fail(MM_ERR_INVALID_ARG, "tuning.relabel must be 0, 1 or 2");
   if (t.relabel == 2 && t.hot_degree < 1)
     return fail(MM_ERR_INVALID_ARG, "tuning.hot_degree must be >= 1 with relabel = 2");
-  if (t.order_lists != 0 && t.order_lists != 1)
-    return fail(MM_ERR_INVALID_ARG, "tuning.order_lists must be 0 or 1");
+  if (t.order_lists < 0 || t.order_lists > 2)
+    return fail(MM_ERR_INVALID_ARG, "tuning.order_lists must be 0, 1 or 2");
+  if (t.order_lists == 2 && !t.upper_only)
+    return fail(MM_ERR_INVALID_ARG, "tuning.order_lists = 2 (upper neighbours first) needs "
+                "upper_only = 1");
   if (t.order_lists && t.relabel)
     return fail(MM_ERR_INVALID_ARG, "tuning.order_lists does not apply with relabel (the "
                 "relabelled copy orders its short lists itself)");
   if (t.hub_degree < 0) return fail(MM_ERR_INVALID_ARG, "tuning.hub_degree must be >= 0");
   if (t.hub_degree > 0 && t.hub_chunk < 1)
     return fail(MM_ERR_INVALID_ARG, "tuning.hub_chunk must be >= 1 when hub_degree > 0");
+  if (t.probe_first < 0 || t.probe_first > 2)
+    return fail(MM_ERR_INVALID_ARG, "tuning.probe_first must be 0, 1 or 2");
   if (t.iter_cap < 0) return fail(MM_ERR_INVALID_ARG, "tuning.iter_cap must be >= 0");
   if (t.whole_graph_lds != 0 && t.whole_graph_lds != 1)
     return fail(MM_ERR_INVALID_ARG, "tuning.whole_graph_lds must be 0 or 1");
@@ -368,6 +373,9 @@ SweepParams make_params(const mm_graph* g) {
   p.wait_release = g->tun.wait_release;
   p.upper_only = (g->tun.upper_only && (g->flags & MM_SYMMETRIC)) ? 1 : 0;
   p.hub_wave = g->tun.hub_wave;
+  // the copy holds each short list's neighbours above its vertex first
+  p.lower_stop = (g->tun.order_lists == 2 && p.upper_only) ? (int32_t)mmi::kOrderedMax : 0;
+  p.probe_first = g->tun.probe_first;
   p.iter_cap = g->tun.iter_cap;
   p.err = g->err_out ? g->err_out : reinterpret_cast<uint32_t*>(g->ws);
   p.hub_degree = g->n_chunks > 0 ? g->tun.hub_degree : 0;
@@ -626,6 +634,7 @@ void mm_default_tuning(mm_tuning* t) {
   t->min_waves = 32;
   t->hot_degree = 2048;
   t->order_lists = 0;
+  t->probe_first = 0;
   t->iter_cap = 0;
 }
 
@@ -736,7 +745,8 @@ mm_status mm_create(const void* offsets, mm_offset_type off_type, const int32_t*
   if (t.order_lists && m > 0) {
     int32_t* copy = reinterpret_cast<int32_t*>(ws + kCtrlBytes + mmi::state_bytes(n, t) +
                                                mmi::hint_bytes(n, t));
-    hipError_t e = mmi::build_ordered_lists(offsets, off_type == MM_OFF_I64, neighbors, n, copy, s);
+    hipError_t e = mmi::build_ordered_lists(offsets, off_type == MM_OFF_I64, neighbors, n,
+                                            t.order_lists == 2, copy, s);
     if (e != hipSuccess) return fail(MM_ERR_HIP, "ordering the lists failed: %s", hipGetErrorString(e));
     sweep_nbr = copy;
   }

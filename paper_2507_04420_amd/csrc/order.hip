@@ -11,11 +11,19 @@
 // pieces anyway, are copied as they are. The sweep then reads the copy with
 // the caller's offsets; nothing else changes (same ids, same states, same
 // output).
+//
+// Upper neighbours first (order_lists = 2): a sweep that examines each edge
+// from its lower end skips every neighbour below the source. This order puts
+// the neighbours above the source first, in the same degree order, and those
+// below it after them, so a scan can stop at the first neighbour below its
+// source instead of reading the rest of the list only to skip it.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
 
 #include "internal.h"
+
+static_assert(mmi::kOrderedMax == 256, "the wavefront sort takes 4 keys per lane");
 
 namespace {
 
@@ -60,11 +68,14 @@ __device__ __forceinline__ void bitonic256(uint32_t (&k)[4], int lane) {
 // different banks; then it writes the ids in key order. Lists of 65 to 256
 // entries are then reordered by the whole wavefront, one after the other:
 // keys bucket * 256 + position, four per lane, sorted by a bitonic network in
-// registers. Longer lists are copied as they are, coalesced.
+// registers. Longer lists are copied as they are, coalesced. With
+// upper_first, a neighbour below the list's vertex has a key above every
+// other (a bit above the bucket's: a degree below 2^63 has a bucket below 64).
 template <typename OffT>
 __global__ __launch_bounds__(256) void order_lists_kernel(const OffT* __restrict__ off,
                                                           const int32_t* __restrict__ nbr,
                                                           const uint8_t* __restrict__ bk, int64_t n,
+                                                          int upper_first,
                                                           int32_t* __restrict__ out) {
   __shared__ uint16_t keys_s[4][64 * 64];
   uint16_t* srt = keys_s[threadIdx.x >> 6];
@@ -78,12 +89,14 @@ __global__ __launch_bounds__(256) void order_lists_kernel(const OffT* __restrict
       b = (int64_t)off[v];
       e = (int64_t)off[v + 1];
     }
-    const bool midl = e - b > 64 && e - b <= 256;
-    const bool longl = e - b > 256;
+    const bool midl = e - b > 64 && e - b <= mmi::kOrderedMax;
+    const bool longl = e - b > mmi::kOrderedMax;
     if (!midl && !longl) {
       const int len = (int)(e - b);
       for (int k = 0; k < len; ++k) {
-        const uint16_t key = (uint16_t)((bk[nbr[b + k]] << 6) | k);
+        const int32_t y = nbr[b + k];
+        const uint32_t low = (upper_first && (int64_t)y < v) ? 1u : 0u;
+        const uint16_t key = (uint16_t)((low << 12) | ((uint32_t)bk[y] << 6) | (uint32_t)k);
         int j = k - 1;
         while (j >= 0 && srt[j * 64 + lane] > key) {
           srt[(j + 1) * 64 + lane] = srt[j * 64 + lane];
@@ -99,10 +112,17 @@ __global__ __launch_bounds__(256) void order_lists_kernel(const OffT* __restrict
       mm &= mm - 1;
       const int64_t lb = __shfl(b, l, 64);
       const int len = (int)(__shfl(e, l, 64) - lb);
+      const int64_t lv = base + l;
       uint32_t k[4];
       for (int q = 0; q < 4; ++q) {
         const int i = lane * 4 + q;
-        k[q] = i < len ? ((uint32_t)bk[nbr[lb + i]] << 8) | (uint32_t)i : 0xffffffffu;
+        if (i < len) {
+          const int32_t y = nbr[lb + i];
+          const uint32_t low = (upper_first && (int64_t)y < lv) ? 1u : 0u;
+          k[q] = (low << 14) | ((uint32_t)bk[y] << 8) | (uint32_t)i;
+        } else {
+          k[q] = 0xffffffffu;
+        }
       }
       bitonic256(k, lane);
       for (int q = 0; q < 4; ++q) {
@@ -128,7 +148,8 @@ int blocks_for(int64_t n) {
 }
 
 template <typename OffT>
-hipError_t build_typed(const OffT* off, const int32_t* nbr, int64_t n, int32_t* out, hipStream_t s) {
+hipError_t build_typed(const OffT* off, const int32_t* nbr, int64_t n, int upper_first, int32_t* out,
+                       hipStream_t s) {
   uint8_t* bk = nullptr;
   hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&bk), (size_t)n, s);
   if (e == hipSuccess) {
@@ -137,7 +158,7 @@ hipError_t build_typed(const OffT* off, const int32_t* nbr, int64_t n, int32_t* 
   }
   if (e == hipSuccess) {
     hipLaunchKernelGGL((order_lists_kernel<OffT>), dim3(blocks_for(n)), dim3(256), 0, s, off, nbr, bk,
-                       n, out);
+                       n, upper_first, out);
     e = hipGetLastError();
   }
   if (bk) hipFreeAsync(bk, s);
@@ -153,10 +174,10 @@ namespace mmi {
 size_t order_temp_bytes(int64_t n) { return n > 0 ? round_up((size_t)n, 256) : 0; }
 
 hipError_t build_ordered_lists(const void* off, int off64, const int32_t* nbr, int64_t n,
-                               int32_t* out, hipStream_t s) {
+                               int upper_first, int32_t* out, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  if (off64) return build_typed(static_cast<const int64_t*>(off), nbr, n, out, s);
-  return build_typed(static_cast<const int32_t*>(off), nbr, n, out, s);
+  if (off64) return build_typed(static_cast<const int64_t*>(off), nbr, n, upper_first, out, s);
+  return build_typed(static_cast<const int32_t*>(off), nbr, n, upper_first, out, s);
 }
 
 }  // namespace mmi

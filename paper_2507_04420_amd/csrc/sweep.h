@@ -84,6 +84,11 @@ struct SweepParams {
   int32_t wait_release;    // 1: release u while waiting for a reserved v
   int32_t upper_only;      // 1 (symmetric input): examine only neighbours above the source
   int32_t hub_wave;        // 1, 2: hub pieces swept by a wavefront each (pieces.h), else a lane each
+  int32_t lower_stop;      // > 0 (with upper_only): every list of at most this many entries
+                           // holds its neighbours above the source first, so its scan ends at
+                           // the first neighbour below the source; 0: no such order
+  int32_t probe_first;     // 1: a source's first state read takes only its first candidate;
+                           // 2: every state read takes one candidate
   int64_t iter_cap;        // 0: per-block default budget
   uint32_t* err;           // bit 0: loop-trip budget exceeded
   // Hub tier. Main pass: sources with more than hub_degree entries are left
@@ -235,6 +240,9 @@ __device__ __forceinline__ void sweep_block(const SweepParams& a, OffP __restric
   uint32_t cb_w = 0, cb_o = 0;  // its filter word and (relabelled graphs) given id
   int64_t trips = 0;
   int phase = P_IDLE;
+  bool cut = false;  // the current list is ordered upper neighbours first
+  bool probe1 = false;  // the next state read is the source's first: one candidate only
+  int kr = 0;           // the buffered ids [k, kr) have their states read
   // vertex ids (local to the graph, < 2^31) in 32 bits, list positions in 64
   int32_t x = 0, u = 0, v = 0;
   int64_t i = 0, e = 0;
@@ -267,7 +275,7 @@ __device__ __forceinline__ void sweep_block(const SweepParams& a, OffP __restric
     uint32_t fw = 0;
 #pragma unroll
     for (int j = kMaxW - 1; j >= 0; --j) {
-      if (j >= k && j < nids && (int64_t)ids[j] != x && (!upper || ids[j] > x) &&
+      if (j >= k && j < kr && (int64_t)ids[j] != x && (!upper || ids[j] > x) &&
           !filter_matched(rw[j], ids[j])) {
         found = j;
         fy = ids[j];
@@ -281,6 +289,9 @@ __device__ __forceinline__ void sweep_block(const SweepParams& a, OffP __restric
       v = x < y ? y : x;
       vguess = HINT ? 0u : ((x < y) ? fw : xword);
       phase = P_RES;
+    } else if (kr < nids) {  // the rest of the step's ids: their states next
+      k = kr;
+      phase = P_STS;
     } else {
       k = nids;
       phase = (i < e) ? P_IDS : (LAZY ? P_FIN : P_IDLE);
@@ -305,6 +316,13 @@ __device__ __forceinline__ void sweep_block(const SweepParams& a, OffP __restric
         steps += nids;
         k = 0;
         if (STATS) cnt.add(S_TOUCHED, (uint32_t)nids);
+        if (cut) {
+          // past the neighbours above x: the rest of the list is below it
+          bool low = false;
+#pragma unroll
+          for (int j = 0; j < kMaxW; ++j) low = low || (j < nids && ids[j] < x);
+          if (low) e = i;
+        }
         bool any = !upper;
 #pragma unroll
         for (int j = 0; j < kMaxW; ++j) any = any || (j < nids && ids[j] > x);
@@ -443,11 +461,20 @@ __device__ __forceinline__ void sweep_block(const SweepParams& a, OffP __restric
         for (int j = 0; j < kMaxW; ++j)
           if (j < W) ids[j] = (i + j < e) ? ld_stream(nbr + i + j, nt) : (int32_t)x;
         break;
-      case P_STS:
+      case P_STS: {
+        // the candidates among [k, nids); with probe1 the first one only
+        int lim = nids;
 #pragma unroll
-        for (int j = 0; j < kMaxW; ++j)
-          if (j < nids && (int64_t)ids[j] != x && (!upper || ids[j] > x)) rw[j] = filter_word(ids[j]);
+        for (int j = 0; j < kMaxW; ++j) {
+          if (j >= k && j < lim && (int64_t)ids[j] != x && (!upper || ids[j] > x)) {
+            rw[j] = filter_word(ids[j]);
+            if (probe1 || a.probe_first == 2) lim = j + 1;
+          }
+        }
+        kr = lim;
+        probe1 = false;
         break;
+      }
       case P_RES:
         if (STATS) cnt.add(S_RES_ATT, 1);
         res_w = L.reserve(u);
@@ -486,10 +513,14 @@ __device__ __forceinline__ void sweep_block(const SweepParams& a, OffP __restric
       const bool cand = aid >= 0 && (int64_t)aid != ax && (!upper || aid > ax) &&
                         !filter_matched(aw, aid);
       const uint64_t cm = __ballot(cand);
+      const uint64_t lowm = a.lower_stop > 0 ? __ballot(aid >= 0 && aid < ax) : 0;
       if (lane == al) {
         if (filter_matched(axw, x)) {
           phase = P_IDLE;  // the source was matched by another lane meanwhile
         } else {
+          // an ordered list ends at its first neighbour below x; every
+          // candidate comes before it
+          if (cut && lowm) e = ai + __builtin_ctzll(lowm);
           i = cm ? ai + __builtin_ctzll(cm) : (ae - ai > 64 ? ai + 64 : ae);
           steps = 0;
           nids = 0;
@@ -543,6 +574,8 @@ __device__ __forceinline__ void sweep_block(const SweepParams& a, OffP __restric
           x = slot.x;
           i = slot.b;
           e = slot.e;
+          cut = upper && a.lower_stop > 0 && !a.chunks && e - i <= a.lower_stop;
+          probe1 = a.probe_first != 0;
           xword = HINT ? 0u : slot.word;
           xorig = slot.orig;
           steps = 0;

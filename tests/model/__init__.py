@@ -61,11 +61,15 @@ def graph(csr) -> Graph:
 
 
 def variant(layout="word", two_phase=0, wait_release=0, lazy=0, scan_width=2, stale=1, upper=0,
-            mutant=0):
-    """mutant: a planted mistake (1 no id order, 2 no release of u, 3 v taken
-    by a plain store after a read); 0 for the protocol itself."""
+            mutant=0, probe=0):
+    """upper: 1 each edge from its lower end, 2 the same with a scan ending at
+    the first neighbour below its source (lists ordered upper neighbours
+    first). probe: 1 a source's first state read takes its first candidate
+    only, 2 every state read takes one. mutant: a planted mistake (1 no id
+    order, 2 no release of u, 3 v taken by a plain store after a read); 0 for
+    the protocol itself."""
     return np.array([LAYOUTS[layout], two_phase, wait_release, lazy, scan_width, stale, upper,
-                     mutant], dtype=np.int32)
+                     mutant, probe], dtype=np.int32)
 
 
 def lanes(n, waves, per_wave, mode="blocks"):

@@ -32,7 +32,10 @@
  *   lazy         symmetric input only: a source whose list ends with every
  *                neighbour matched writes its own "unmatched" output;
  *   upper        symmetric input only: a lane examines only the neighbours
- *                above its source (each undirected edge from its lower end).
+ *                above its source (each undirected edge from its lower end);
+ *                upper = 2 also ends a scan at the first neighbour below the
+ *                source, which is sound when every list holds the neighbours
+ *                above its vertex first.
  *
  * Two drivers: pm_run follows one schedule drawn by a seeded generator under
  * a strategy; pm_explore visits every state reachable under every schedule
@@ -57,6 +60,7 @@ enum { D_NONE = 0, D_RW0, D_RW1, D_RW2, D_RW3, D_XW, D_RES, D_CHKU, D_CHKV, D_MA
 
 typedef struct {
   int layout, two_phase, wait_release, lazy, scan_width, stale, upper;
+  int probe;  /* 1: a source's first state read takes one candidate; 2: every one does */
   int mutant; /* planted mistakes, to show the model notices them: 1 no id
                  order (u is always the source), 2 u is never given back,
                  3 v is taken by a plain store after a read saw it free */
@@ -76,7 +80,9 @@ typedef struct {
 } Op;
 
 typedef struct {
-  uint8_t phase, nsrc, si, k, nids, nops, pad0, pad1;
+  uint8_t phase, nsrc, si, k, nids, nops;
+  uint8_t kr;     /* the buffered ids [k, kr) have their states read */
+  uint8_t probe1; /* the next state read is the source's first */
   int8_t x, u, v, pad2;
   int16_t i, e;
   int8_t ids[4];
@@ -170,7 +176,7 @@ static void issue_unmatched(const Ctx *c, Lane *L, int x) {
 
 static void advance(const Ctx *c, Lane *L) {
   int found = -1;
-  for (int j = L->k; j < L->nids; ++j)
+  for (int j = L->k; j < L->kr; ++j)
     if (L->ids[j] != L->x && (!c->var.upper || L->ids[j] > L->x) &&
         decode(c, L->rw[j], L->ids[j]) != S_MCHD) {
       found = j;
@@ -187,6 +193,9 @@ static void advance(const Ctx *c, Lane *L) {
     }
     L->vguess = (L->x < y) ? L->rw[found] : L->xword;
     L->phase = P_RES;
+  } else if (L->kr < L->nids) { /* the rest of the step's ids: their states next */
+    L->k = L->kr;
+    L->phase = P_STS;
   } else {
     L->k = L->nids;
     L->phase = L->i < L->e ? P_IDS : (c->var.lazy ? P_FIN : P_IDLE);
@@ -209,6 +218,7 @@ static void consume(const Ctx *c, Lane *L) {
       } else {
         L->i = (int16_t)g->off[x];
         L->e = (int16_t)g->off[x + 1];
+        L->probe1 = (uint8_t)(c->var.probe != 0);
         L->phase = P_IDS;
       }
       break;
@@ -224,8 +234,12 @@ static void consume(const Ctx *c, Lane *L) {
       L->k = 0;
       L->phase = P_STS;
       if (c->var.upper) {
-        int any = 0;
-        for (int j = 0; j < L->nids; ++j) any |= L->ids[j] > L->x;
+        int any = 0, low = 0;
+        for (int j = 0; j < L->nids; ++j) {
+          any |= L->ids[j] > L->x;
+          low |= L->ids[j] < L->x;
+        }
+        if (c->var.upper == 2 && low) L->e = L->i; /* the rest is below the source */
         if (!any) { /* nothing above the source here: read on without states */
           L->k = L->nids;
           L->phase = L->i < L->e ? P_IDS : (c->var.lazy ? P_FIN : P_IDLE);
@@ -353,11 +367,17 @@ static void issue(const Ctx *c, Lane *L) {
     case P_SRC:
       push(L, K_LD_CACHED, D_XW, word_of(c, L->x), 0, 0);
       break;
-    case P_STS:
-      for (int j = 0; j < L->nids; ++j)
-        if (L->ids[j] != L->x && (!c->var.upper || L->ids[j] > L->x))
+    case P_STS: {
+      int lim = L->nids;
+      for (int j = L->k; j < lim; ++j)
+        if (L->ids[j] != L->x && (!c->var.upper || L->ids[j] > L->x)) {
           push(L, K_LD_CACHED, (uint8_t)(D_RW0 + j), word_of(c, L->ids[j]), 0, 0);
+          if (L->probe1 || c->var.probe == 2) lim = j + 1;
+        }
+      L->kr = (uint8_t)lim;
+      L->probe1 = 0;
       break;
+    }
     case P_RES:
       issue_reserve(c, L, L->u, D_RES);
       break;
@@ -479,6 +499,7 @@ static int setup(Ctx *c, State *s, const Graph *g, const int *var6, int lanes, c
   c->var.stale = var6[5];
   c->var.upper = var6[6];
   c->var.mutant = var6[7];
+  c->var.probe = var6[8];
   if (g->n > PM_MAXN || lanes < 1 || lanes > PM_MAXL || max_src > PM_MAXS) return -1;
   c->lanes = lanes;
   c->waves = 0;
@@ -549,7 +570,7 @@ static uint64_t rng_next(uint64_t *x) {
 
 /*
  * Runs one schedule. var6 = {layout, two_phase, wait_release, lazy,
- * scan_width, stale, upper, mutant}; lanes in wavefronts wave_of[l]; src: lanes x max_src
+ * scan_width, stale, upper, mutant, probe}; lanes in wavefronts wave_of[l]; src: lanes x max_src
  * source ids (-1 ends a lane's list). strategy: 0 every choice equally
  * likely; 1 wavefronts advance before pending operations are applied where
  * possible (operations stay in flight long, reads are stale); 2 operations

@@ -42,8 +42,8 @@ def test_version_and_defaults():
     assert t.wg_size % 64 == 0 and t.wave_vertices % 64 == 0
     # the ctypes mirror has the C layout: the last fields read back as written
     assert t.whole_graph_vertices == 16384 and t.iter_cap == 0 and t.whole_graph_lds == 1
-    assert t.hot_degree == 2048
-    assert ctypes.sizeof(_lib.mm_tuning) == 96
+    assert t.hot_degree == 2048 and t.probe_first == 0
+    assert ctypes.sizeof(_lib.mm_tuning) == 104
     from paper_2507_04420_amd import Tuning
     assert Tuning.default() == Tuning()  # the Python defaults mirror the library's
 
@@ -112,7 +112,10 @@ def test_create_bad_tuning():
                        ("relabel", -1),
                        ("hub_degree", -1), ("whole_graph_lds", 2), ("wait_release", 2),
                        ("mesh_wave_vertices", 100), ("hub_wave", 3), ("hub_wave", -1),
-                       ("upper_only", 2), ("min_waves", -1), ("order_lists", 2),
+                       ("upper_only", 2), ("min_waves", -1), ("order_lists", 3),
+                       ("order_lists", -1),
+                       ("order_lists", 2),  # upper neighbours first needs upper_only = 1
+                       ("probe_first", 3), ("probe_first", -1),
                        ("iter_cap", -1)):
         lib.mm_default_tuning(ctypes.byref(t))
         setattr(t, field, bad)
@@ -212,6 +215,14 @@ def test_workspace_bytes_graph():
     assert lib.mm_workspace_bytes_graph(1000, 5000, ctypes.byref(t)) == base + 20224  # 4m to 256 B
     assert lib.mm_create_device_bytes(1000, 5000, ctypes.byref(t)) >= 1000
     assert lib.mm_batch_workspace_bytes(1, vtx, ctypes.byref(t)) == 0
+    # upper neighbours first: the same copy in another order, with upper_only only
+    t.order_lists = 2
+    assert lib.mm_workspace_bytes_graph(1000, 5000, ctypes.byref(t)) == 0
+    t.upper_only = 1
+    with_upper = lib.mm_workspace_bytes_graph(1000, 5000, ctypes.byref(t))
+    t.order_lists = 1
+    assert with_upper == lib.mm_workspace_bytes_graph(1000, 5000, ctypes.byref(t)) > 0
+    t.upper_only = 0
 
 
 def _batch_bytes(lib, ns, **kw):

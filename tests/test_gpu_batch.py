@@ -30,6 +30,7 @@ TUNINGS = {
     "u32_whole_in_device_memory": mm.Tuning(whole_graph_lds=0),
     "u32_mesh128": mm.Tuning(whole_graph_vertices=0, mesh_wave_vertices=128),
     "u32_upper_only": mm.Tuning(upper_only=1, whole_graph_vertices=0, hint=2),
+    "u32_probe_first_upper": mm.Tuning(probe_first=1, upper_only=1, whole_graph_vertices=0),
     "u32_hub_wave": mm.Tuning(hub_wave=1, hub_degree=6, hub_chunk=65, whole_graph_vertices=0),
     # the workgroup tier is taken as the wavefront tier in batches
     "u32_hub_group": mm.Tuning(hub_wave=2, hub_degree=5, hub_chunk=7, whole_graph_vertices=0,

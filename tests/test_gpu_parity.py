@@ -102,6 +102,20 @@ TUNINGS = {
                                                  whole_graph_vertices=0, wave_vertices=64),
     "order_lists_two_hubs_hint": mm.Tuning(order_lists=1, protocol=TWO, hint=2, hub_degree=5,
                                            hub_chunk=3, whole_graph_vertices=0),
+    # the same with the neighbours above each vertex first, where a scan of a
+    # short list ends at its first neighbour below the source: in the lane's
+    # reads, in the wavefront assist's, and never in a hub piece
+    "upper_first": mm.Tuning(order_lists=2, upper_only=1, whole_graph_vertices=0),
+    "upper_first_assist_u8": mm.Tuning(order_lists=2, upper_only=1, layout=U8, assist_after=16,
+                                       scan_width=2, whole_graph_vertices=0, wave_vertices=64),
+    # a source's first state read takes its first candidate only
+    "probe_first_ordered": mm.Tuning(probe_first=1, order_lists=1, upper_only=1, whole_graph_vertices=0),
+    "probe_each_upper_first_assist": mm.Tuning(probe_first=2, order_lists=2, upper_only=1, assist_after=8,
+                                               whole_graph_vertices=0),
+    "probe_first_u8_two_hint_w3": mm.Tuning(probe_first=1, layout=U8, protocol=TWO, hint=1, scan_width=3,
+                                            whole_graph_vertices=0, wave_vertices=64),
+    "upper_first_two_lane_pieces": mm.Tuning(order_lists=2, upper_only=1, protocol=TWO, hub_degree=5,
+                                             hub_chunk=3, hub_wave=0, whole_graph_vertices=0),
     # relabelled with the vertices of more than hot_degree entries last
     "relabel_hot_u32_cas": mm.Tuning(relabel=2, hot_degree=4),
     "relabel_hot_upper_multi_wave": mm.Tuning(relabel=2, hot_degree=8, upper_only=1,
@@ -552,10 +566,11 @@ def test_relabelled_copy_is_the_stated_order(mode):
 
 # ---------------------------------------------------------------- reordered lists
 
-def expected_order(csr):
+def expected_order(csr, upper_first=False):
     """The copy order_lists builds, computed here: each list of at most 256
     entries stably sorted by 1 + floor(log2 degree) of the neighbour, longer
-    lists as given."""
+    lists as given; with upper_first, stably sorted first by whether the
+    neighbour is below the list's vertex."""
     deg = np.diff(csr.off.astype(np.int64))
     bucket = np.zeros(csr.n, dtype=np.int64)
     nz = deg > 0
@@ -565,23 +580,27 @@ def expected_order(csr):
         b, e = int(csr.off[v]), int(csr.off[v + 1])
         if 1 < e - b <= 256:
             seg = csr.nbr[b:e]
-            out[b:e] = seg[np.argsort(bucket[seg], kind="stable")]
+            seg = seg[np.argsort(bucket[seg], kind="stable")]
+            if upper_first:
+                seg = seg[np.argsort(seg < v, kind="stable")]
+            out[b:e] = seg
     return out
 
 
+@pytest.mark.parametrize("upper_first", [False, True])
 @pytest.mark.parametrize("make", [lambda: graphgen.rmat(14, seed=3), lambda: graphgen.er(3000, 20, seed=1),
-                                  lambda: hub_trap(300)])
-def test_order_lists_copy_is_the_stable_degree_order(make):
+                                  lambda: hub_trap(300), lambda: hub_trap(100)])
+def test_order_lists_copy_is_the_stable_degree_order(make, upper_first):
     # white box, bit for bit: with the word layout and no hint the workspace
     # holds the 4 KiB control block, then the reordered copy of the ids
     csr = make()
-    assert np.diff(csr.off).max() > 256 or csr.name.startswith("er")  # long lists stay as given
     off, nbr = to_dev(csr)
-    h = mm.Graph(off, nbr, symmetric=True, tuning=mm.Tuning(order_lists=1))
+    t = mm.Tuning(order_lists=2, upper_only=1) if upper_first else mm.Tuning(order_lists=1)
+    h = mm.Graph(off, nbr, symmetric=True, tuning=t)
     base = h.workspace.data_ptr()
     start = (base + 255) // 256 * 256 - base + 4096
     copy = h.workspace[start:start + 4 * csr.m].view(torch.int32).cpu().numpy()
-    np.testing.assert_array_equal(copy, expected_order(csr))
+    np.testing.assert_array_equal(copy, expected_order(csr, upper_first))
     out = h.run()
     h.sync()
     assert_parity(csr, out.cpu().numpy())

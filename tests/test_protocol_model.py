@@ -9,7 +9,8 @@ operation of a trip is in flight until the wavefront's next trip, cached
 reads may be stale, and the options take v in two phases, give u back while
 waiting for v (wait_release), keep states in packed words whose CAS must be
 retried when another field changes, write unmatched outputs lazily, or
-examine each edge only from its lower endpoint (upper_only). The model runs
+examine each edge only from its lower endpoint (upper_only), or read the
+states of a step's candidates one at a time (probe_first). The model runs
 the lanes' state machine with the memory operations applied in an order an
 adversary picks. Pins:
 
@@ -25,6 +26,9 @@ adversary picks. Pins:
   graphs with four lanes in two wavefronts;
 * the order of a list is free: with every list shuffled, the adversarial
   schedules still end in the brute-force set;
+* a scan may end at the first neighbour below its source when every list
+  holds the neighbours above its vertex first (each part in any order); the
+  same cut on lists in another order is caught;
 * the model is sharp: three mistakes planted in it (no id order, no release
   of u, v taken by a plain store) are each caught on a small graph.
 """
@@ -49,6 +53,9 @@ VARIANTS = {
     "u8_two_phase": dict(layout="u8", two_phase=1),
     "u2_cas_upper_wait_release": dict(layout="u2", upper=1, wait_release=1),
     "u2_two_phase_lazy": dict(layout="u2", two_phase=1, lazy=1),
+    # state reads of one candidate: a source's first, or every one
+    "word_cas_upper_probe_first": dict(layout="word", upper=1, probe=1, scan_width=3),
+    "u8_two_phase_probe_each": dict(layout="u8", two_phase=1, probe=2),
 }
 STRATEGIES = (0, 1, 2, 3)
 
@@ -212,6 +219,63 @@ def test_any_list_order(name):
             trips, mate = run(G, var, wave_of, src, strategy=st, seed=idx * 13 + st, max_trips=20000)
             assert trips >= 0, (name, idx, st, trips)
             assert tuple(mate.tolist()) in ok, (name, idx, st, mate)
+
+
+class _UpperFirst:
+    """A CSR with each list's neighbours above its vertex first, each part
+    shuffled (lower_first: those below first instead)."""
+
+    def __init__(self, csr, rng, lower_first=False):
+        self.n, self.m, self.off = csr.n, csr.m, csr.off
+        nbr = csr.nbr.copy()
+        for v in range(csr.n):
+            b, e = int(csr.off[v]), int(csr.off[v + 1])
+            seg = rng.permutation(nbr[b:e])
+            below = seg < v
+            nbr[b:e] = np.concatenate([seg[below], seg[~below]] if lower_first else
+                                      [seg[~below], seg[below]])
+        self.nbr = nbr
+
+
+@pytest.mark.parametrize("name", ["word_cas_upper", "u2_cas_upper_wait_release", "u8_two_phase"])
+def test_upper_first_scan_cut(name):
+    # the reordered copy with the neighbours above each vertex first lets a
+    # scan end at its first neighbour below the source: every graph of up to
+    # 5 vertices and random 7-vertex graphs, under the four adversarial
+    # strategies, still end in a maximal matching
+    rng = np.random.default_rng(23)
+    var = variant(**dict(VARIANTS[name], upper=2))
+    graphs = [g for n in range(2, 6) for g in all_graphs(n)]
+    for _ in range(120):
+        p = rng.uniform(0.2, 0.8)
+        graphs.append(graphgen.from_edges(7, [(a, b) for a, b in itertools.combinations(range(7), 2)
+                                              if rng.random() < p]))
+    cfgs = [(2, 1, "round"), (1, 2, "blocks"), (2, 2, "round")]
+    for idx, g in enumerate(graphs):
+        ok = maximal_set(g)
+        G = graph(_UpperFirst(g, rng))
+        w, p_, mode = cfgs[idx % len(cfgs)]
+        wave_of, src = lanes(g.n, w, p_, mode)
+        for st in STRATEGIES:
+            trips, mate = run(G, var, wave_of, src, strategy=st, seed=idx * 11 + st, max_trips=20000)
+            assert trips >= 0, (name, idx, st, trips)
+            assert tuple(mate.tolist()) in ok, (name, idx, st, mate)
+
+
+def test_scan_cut_needs_the_order():
+    # the cut is sharp: on lists with the neighbours below each vertex first
+    # it skips edges, and some small graph ends with an edge whose endpoints
+    # are both unmatched
+    var = variant(layout="word", upper=2)
+    caught = 0
+    for n in (3, 4):
+        for g in all_graphs(n):
+            ok = maximal_set(g)
+            G = graph(_UpperFirst(g, np.random.default_rng(n), lower_first=True))
+            wave_of, src = lanes(g.n, 1, 1, "blocks")
+            trips, mate = run(G, var, wave_of, src, strategy=0, seed=1, max_trips=20000)
+            caught += trips >= 0 and tuple(mate.tolist()) not in ok
+    assert caught > 0
 
 
 @pytest.mark.parametrize("mutant", [1, 2, 3])
