@@ -410,7 +410,8 @@ VARIANTS = {
     "relabel_hot_1024": {"relabel": 2, "hot_degree": 1024, "order_lists": 0},
     "relabel_hot_4096": {"relabel": 2, "hot_degree": 4096, "order_lists": 0},
     "relabel_hot_8192": {"relabel": 2, "hot_degree": 8192, "order_lists": 0},
-    "all_entries": {"upper_only": 0},
+    # (the upper-first copy needs upper_only: the degree-ordered one instead)
+    "all_entries": {"upper_only": 0, "order_lists": 1},
     "all_entries_relabelled": {"upper_only": 0, "relabel": 1, "order_lists": 0},
     "u8_byte_cas": {"layout": 0, "protocol": 0, "lazy_init": 0},
     "u8_byte_cas_lazy": {"layout": 0, "protocol": 0, "lazy_init": 1},

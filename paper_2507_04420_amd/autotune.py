@@ -341,7 +341,10 @@ def _targets(classes, seed, rmat_scale=27, grid_side=16384):
             out[c] = lambda: MultiTarget([graphgen.er(40000, 12, seed=seed), graphgen.er(150000, 8, seed=seed)],
                                          spread_reps=SPREAD_REPS)
         elif c == "er":
-            out[c] = lambda: SingleTarget(graphgen.er(1 << 22, 16, seed=seed))
+            # both sizes: the 65536-vertex graph is in flight whole, and the
+            # best scan there is not the best on 4M vertices
+            out[c] = lambda: MultiTarget([graphgen.er(1 << 16, 16, seed=seed),
+                                          graphgen.er(1 << 22, 16, seed=seed)], copies=True)
         elif c == "batch":
             out[c] = lambda: BatchTarget(graphgen.mixture(4096, seed=seed))
         else:

@@ -69,7 +69,12 @@ def test_variants_are_valid_tunings():
     import ctypes
     import paper_2507_04420_amd as mm
     from paper_2507_04420_amd import _lib
+    from paper_2507_04420_amd import autotune
     lib = _lib.load()
-    for name, over in bench.VARIANTS.items():
-        t = mm.Tuning(**dict(mm.Tuning().as_dict(), **over)).to_c()
-        assert lib.mm_workspace_bytes_graph(1000, 5000, ctypes.byref(t)) > 0, name
+    # over the defaults and over each single-graph workload's tuned entry,
+    # which the bench's variants override
+    bases = [mm.Tuning()] + [autotune.tuned(c, key="gfx950_256cu") for c in ("rmat", "er", "grid")]
+    for base in bases:
+        for name, over in bench.VARIANTS.items():
+            t = mm.Tuning(**dict(base.as_dict(), **over)).to_c()
+            assert lib.mm_workspace_bytes_graph(1000, 5000, ctypes.byref(t)) > 0, (name, base)
