@@ -171,6 +171,40 @@ def test_run_trace_with_simulated_clock():
     assert wall > 0.019
 
 
+def test_run_trace_freezes_the_collector_only_while_it_runs():
+    # the objects alive at the start are out of the collector's view during
+    # the trace (a full collection cannot stall the loop), and back after it,
+    # also when the trace fails
+    import gc
+    ex = FakeExecutor()
+    seen = []
+
+    class Probe(Scheduler):
+        def step(self, now):
+            seen.append(gc.get_freeze_count())
+            ex.now = now + 1.0
+            return super().step(now)
+
+    assert gc.get_freeze_count() == 0
+    comps, _ = run_trace(Probe(ex, hbm_budget=1 << 40, small_edges=10**6),
+                         [Request(k, graph(100, 1000), 0.0) for k in range(3)])
+    assert len(comps) == 3 and min(seen) > 0 and gc.get_freeze_count() == 0
+    seen.clear()
+    run_trace(Probe(ex, hbm_budget=1 << 40, small_edges=10**6), [Request(0, graph(100, 1000), 0.0)],
+              freeze_gc=False)
+    assert max(seen) == 0
+
+    class Stuck(Scheduler):
+        def step(self, now):
+            return 0
+
+    clock = iter(range(10**6))
+    with pytest.raises(TimeoutError):
+        run_trace(Stuck(ex, hbm_budget=1 << 40, small_edges=10**6), [Request(0, graph(100, 1000), 0.0)],
+                  clock=lambda: float(next(clock)), timeout=5.0)
+    assert gc.get_freeze_count() == 0
+
+
 def _lib_or_skip():
     from paper_2507_04420_amd import _lib
     return _lib.load()
