@@ -400,6 +400,8 @@ VARIANTS = {
     "probe_first_upper_first": {"probe_first": 1, "order_lists": 2, "upper_only": 1},
     "probe_first_given_lists": {"probe_first": 1, "order_lists": 0},
     "probe_none": {"probe_first": 0},
+    "occ6": {"occupancy": 6},
+    "occ0": {"occupancy": 0},
     "chunk_256": {"hub_chunk": 256},
     "assist_chunk_256": {"assist_after": 256, "hub_chunk": 256},
     "probe_first_w2": {"probe_first": 1, "scan_width": 2},

@@ -241,6 +241,12 @@ typedef struct {
                             2: every state read takes one candidate (ids are
                             still read scan_width at a time). 0: every read
                             takes a whole step's candidates */
+  int32_t occupancy;     /* 6: single-graph sweeps (not relabelled, not
+                            instrumented) run a build of the sweep kernel limited
+                            to 80 VGPRs, so that six wavefronts share each SIMD
+                            instead of five: more latency hidden, and more of the
+                            graph in flight at once. 0: the compiler's register
+                            budget. Batches ignore it */
   int64_t iter_cap;      /* loop-trip budget per wavefront; 0 = default of
                             65536 + 8 x (neighbour entries of its block);
                             exceeding it raises MM_ERR_NO_PROGRESS */

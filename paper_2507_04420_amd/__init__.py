@@ -55,6 +55,7 @@ class Tuning:
     hot_degree: int = 2048
     order_lists: int = 0
     probe_first: int = 0
+    occupancy: int = 0
     iter_cap: int = 0
 
     @classmethod

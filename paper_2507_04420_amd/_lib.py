@@ -59,6 +59,7 @@ class mm_tuning(ctypes.Structure):
         ("hot_degree", ctypes.c_int32),
         ("order_lists", ctypes.c_int32),
         ("probe_first", ctypes.c_int32),
+        ("occupancy", ctypes.c_int32),
         ("iter_cap", ctypes.c_int64),
     ]
 

@@ -39,6 +39,7 @@ SPACE = {
     "relabel": [0, 1, 2],
     "order_lists": [0, 1, 2],
     "probe_first": [0, 1, 2],
+    "occupancy": [0, 6],
     "hot_degree": [512, 1024, 2048, 4096, 8192],
     "hint": [0, 1, 2],
     "disperse": [0, 1],

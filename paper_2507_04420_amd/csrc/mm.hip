@@ -80,6 +80,8 @@ mm_status check_tuning(const mm_tuning& t) {
     return fail(MM_ERR_INVALID_ARG, "tuning.hub_chunk must be >= 1 when hub_degree > 0");
   if (t.probe_first < 0 || t.probe_first > 2)
     return fail(MM_ERR_INVALID_ARG, "tuning.probe_first must be 0, 1 or 2");
+  if (t.occupancy != 0 && t.occupancy != 6)
+    return fail(MM_ERR_INVALID_ARG, "tuning.occupancy must be 0 or 6");
   if (t.iter_cap < 0) return fail(MM_ERR_INVALID_ARG, "tuning.iter_cap must be >= 0");
   if (t.whole_graph_lds != 0 && t.whole_graph_lds != 1)
     return fail(MM_ERR_INVALID_ARG, "tuning.whole_graph_lds must be 0 or 1");
@@ -222,12 +224,11 @@ __global__ void validate_kernel(const OffT* __restrict__ off, const int32_t* __r
 // knows it (the table was filled by this pass's own stream); n_chunks is then
 // the table's capacity, which sizes the grid.
 template <typename OffT, class Layout, bool HINT, bool LAZY, bool STATS>
-__global__ __launch_bounds__(256) void sweep_kernel(SweepParams p, const OffT* __restrict__ off,
-                                                   const int32_t* __restrict__ nbr, int64_t n,
-                                                   int64_t v_begin, int64_t main_waves,
-                                                   int64_t n_chunks,
-                                                   const unsigned long long* chunk_count, Layout L,
-                                                   unsigned long long* stats) {
+__device__ __forceinline__ void sweep_graph(SweepParams p, const OffT* __restrict__ off,
+                                            const int32_t* __restrict__ nbr, int64_t n,
+                                            int64_t v_begin, int64_t main_waves, int64_t n_chunks,
+                                            const unsigned long long* chunk_count, Layout L,
+                                            unsigned long long* stats) {
   // the workgroup tier's slots (pieces.h), cleared before any wavefront of
   // the workgroup reads them
   __shared__ int32_t seen[4];
@@ -269,6 +270,32 @@ __global__ __launch_bounds__(256) void sweep_kernel(SweepParams p, const OffT* _
   sweep_block<OffT, Layout, HINT, LAZY, STATS>(p, off, nbr, L, vb, nv, queues[threadIdx.x >> 6],
                                                cnt);
   if (STATS) cnt.flush(stats);
+}
+
+template <typename OffT, class Layout, bool HINT, bool LAZY, bool STATS>
+__global__ __launch_bounds__(256) void sweep_kernel(SweepParams p, const OffT* __restrict__ off,
+                                                   const int32_t* __restrict__ nbr, int64_t n,
+                                                   int64_t v_begin, int64_t main_waves,
+                                                   int64_t n_chunks,
+                                                   const unsigned long long* chunk_count, Layout L,
+                                                   unsigned long long* stats) {
+  sweep_graph<OffT, Layout, HINT, LAZY, STATS>(p, off, nbr, n, v_begin, main_waves, n_chunks,
+                                               chunk_count, L, stats);
+}
+
+// The same sweep compiled for at least six wavefronts per SIMD (tuning
+// occupancy = 6): at most 80 VGPRs, where the compiler alone takes 81 and
+// gets five. The lanes' chains of dependent memory operations are the
+// bound, so more wavefronts hide more of their latency; the graph's share in
+// flight grows too. Instantiated only for the sweeps that fit without spills
+// (not relabelled, not instrumented).
+template <typename OffT, class Layout, bool HINT, bool LAZY, bool STATS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void sweep_kernel_w6(
+    SweepParams p, const OffT* __restrict__ off, const int32_t* __restrict__ nbr, int64_t n,
+    int64_t v_begin, int64_t main_waves, int64_t n_chunks, const unsigned long long* chunk_count,
+    Layout L, unsigned long long* stats) {
+  sweep_graph<OffT, Layout, HINT, LAZY, STATS>(p, off, nbr, n, v_begin, main_waves, n_chunks,
+                                               chunk_count, L, stats);
 }
 
 // A graph swept whole by one wavefront, its states in that wavefront's LDS
@@ -446,9 +473,14 @@ hipError_t launch_sweep(const mm_graph* g, const Layout& L, hipStream_t s) {
     hipError_t e = hipEventRecord(g->timing->before(), s);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((sweep_kernel<OffT, Layout, HINT, LAZY, STATS>), dim3((unsigned)blocks),
-                     dim3(g->tun.wg_size), 0, s, pl, off, nbr, g->n, v_begin, waves, g->n_chunks,
-                     g->chunk_count, L, stats);
+  void (*kernel)(SweepParams, const OffT*, const int32_t*, int64_t, int64_t, int64_t, int64_t,
+                 const unsigned long long*, Layout, unsigned long long*) =
+      sweep_kernel<OffT, Layout, HINT, LAZY, STATS>;
+  if constexpr (!Layout::kRelabelled && !STATS) {
+    if (g->tun.occupancy == 6) kernel = sweep_kernel_w6<OffT, Layout, HINT, LAZY, STATS>;
+  }
+  hipLaunchKernelGGL(kernel, dim3((unsigned)blocks), dim3(g->tun.wg_size), 0, s, pl, off, nbr, g->n,
+                     v_begin, waves, g->n_chunks, g->chunk_count, L, stats);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (g->timing) {
@@ -635,6 +667,7 @@ void mm_default_tuning(mm_tuning* t) {
   t->hot_degree = 2048;
   t->order_lists = 0;
   t->probe_first = 0;
+  t->occupancy = 0;
   t->iter_cap = 0;
 }
 

@@ -42,7 +42,7 @@ def test_version_and_defaults():
     assert t.wg_size % 64 == 0 and t.wave_vertices % 64 == 0
     # the ctypes mirror has the C layout: the last fields read back as written
     assert t.whole_graph_vertices == 16384 and t.iter_cap == 0 and t.whole_graph_lds == 1
-    assert t.hot_degree == 2048 and t.probe_first == 0
+    assert t.hot_degree == 2048 and t.probe_first == 0 and t.occupancy == 0
     assert ctypes.sizeof(_lib.mm_tuning) == 104
     from paper_2507_04420_amd import Tuning
     assert Tuning.default() == Tuning()  # the Python defaults mirror the library's
@@ -115,7 +115,7 @@ def test_create_bad_tuning():
                        ("upper_only", 2), ("min_waves", -1), ("order_lists", 3),
                        ("order_lists", -1),
                        ("order_lists", 2),  # upper neighbours first needs upper_only = 1
-                       ("probe_first", 3), ("probe_first", -1),
+                       ("probe_first", 3), ("probe_first", -1), ("occupancy", 5), ("occupancy", 8),
                        ("iter_cap", -1)):
         lib.mm_default_tuning(ctypes.byref(t))
         setattr(t, field, bad)

@@ -108,6 +108,14 @@ TUNINGS = {
     "upper_first": mm.Tuning(order_lists=2, upper_only=1, whole_graph_vertices=0),
     "upper_first_assist_u8": mm.Tuning(order_lists=2, upper_only=1, layout=U8, assist_after=16,
                                        scan_width=2, whole_graph_vertices=0, wave_vertices=64),
+    # the sweep kernel built for six wavefronts per SIMD
+    "occupancy6_tuned_shape": mm.Tuning(occupancy=6, order_lists=2, upper_only=1, probe_first=1,
+                                        assist_after=16, whole_graph_vertices=0),
+    "occupancy6_u2_two_lazy_hubs": mm.Tuning(occupancy=6, layout=U2, protocol=TWO, lazy_init=1,
+                                             hub_degree=5, hub_chunk=3, hub_wave=0,
+                                             whole_graph_vertices=0),
+    "occupancy6_u8_bytehint_release": mm.Tuning(occupancy=6, layout=U8, hint=2, wait_release=1,
+                                                whole_graph_vertices=0, wave_vertices=64),
     # a source's first state read takes its first candidate only
     "probe_first_ordered": mm.Tuning(probe_first=1, order_lists=1, upper_only=1, whole_graph_vertices=0),
     "probe_each_upper_first_assist": mm.Tuning(probe_first=2, order_lists=2, upper_only=1, assist_after=8,
