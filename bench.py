@@ -425,6 +425,7 @@ VARIANTS = {
     "hint_bytes": {"hint": 2},
     "no_hint": {"hint": 0},
     "assist_16": {"assist_after": 16},
+    "assist_32": {"assist_after": 32},
     "assist_256": {"assist_after": 256},
     "assist_64": {"assist_after": 64},
     "wg_128": {"wg_size": 128},
