@@ -968,7 +968,8 @@ def main():
         "config": cfg,
         "roofline": {
             "bound": "hbm",
-            "kernel": "sweep_kernel",
+            # the six-wave build with occupancy = 6 (the same code)
+            "kernel": "sweep_kernel_w6" if cfg["tuning"].get("occupancy") == 6 else "sweep_kernel",
             "achieved": round(achieved, 2),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
