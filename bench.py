@@ -457,6 +457,7 @@ VARIANTS = {
     "wv_1024": {"wave_vertices": 1024},
     "wg_64": {"wg_size": 64},
     "mw_2048": {"min_waves": 2048},
+    "mw_32": {"min_waves": 32},
     "scan_1": {"scan_width": 1},
     "wv_4096": {"wave_vertices": 4096},
     "u32": {"layout": 1, "protocol": 0, "lazy_init": 0},

@@ -55,7 +55,7 @@ SPACE = {
     # source while waiting for the next vertex of its row), so they move
     # together
     "upper_wait": [(0, 0), (0, 1), (1, 0), (1, 1)],
-    "min_waves": [4, 8, 16, 32, 64, 2048],
+    "min_waves": [4, 8, 16, 32, 64, 2048, 16384],
     "hub_wave": [0, 1, 2],
     "hub_chunk": [64, 256, 1024, 4096],
 }
