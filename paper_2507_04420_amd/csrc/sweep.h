@@ -268,7 +268,8 @@ __device__ __forceinline__ void sweep_block(const SweepParams& a, OffP __restric
   int32_t aid = -1;
   uint32_t aw = 0, axw = 0;
 
-  // Next candidate among the buffered ids [k, nids), else read on.
+  // Next candidate among the buffered ids whose states were read, [k, kr);
+  // else the states of the rest of the step's ids; else read on.
   auto advance = [&]() {
     int found = -1;
     int32_t fy = 0;
